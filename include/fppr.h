@@ -1,0 +1,249 @@
+/*
+ * fppr — fully edge-weighted personalized PageRank by Monte Carlo walks on
+ * one MI355X (gfx950).
+ *
+ * Problem (Lin, WWW'19, Definition 1 and Sec. 2.1): for a directed graph
+ * G = (V, E, w) with integer weights w(e) >= 1, a termination probability
+ * alpha in (0,1) and R walks per source, estimate pi(s,t), the probability
+ * that a walk from s ends at t, as count(s,t) / R. A walk moves to an
+ * out-neighbour t of its tail u with probability w(u,t) / sum_v w(u,v), then
+ * stops there with probability alpha (so it takes at least one step); at a
+ * node without out-neighbours it restarts from its head (Sec. 2.1).
+ * Algorithm 2 generates the walks; its last phase counts them per
+ * (head, tail). The library returns the integer counts; pi_hat = count / R.
+ *
+ * Exactness: every random number is Philox4x32-10 (Salmon et al., SC'11)
+ * keyed by the 64-bit seed (key word 0 = low half) on the counter
+ * (walk index i, move index m, source id s, 0); the coin is "stop iff
+ * x2 < T(alpha)" with T(alpha) = floor(alpha * 2^32 + 1/2) clamped to
+ * [1, 2^32-1]; the weighted pick takes X = floor((x1 * 2^32 + x0) * W / 2^64)
+ * and the first out-edge whose inclusive weight prefix exceeds X. Results are
+ * therefore a pure function of (graph, alpha, R, seed, source) and do not
+ * depend on launch shapes, the hub threshold or which other sources run.
+ *
+ * Conventions for every call:
+ *  - every function returns an fppr_status (0 = FPPR_OK) unless stated;
+ *  - pointers documented as "device" are HIP device pointers on the device
+ *    that was current when the graph was created; "host" pointers are
+ *    ordinary host memory;
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *    device work is enqueued on it and is asynchronous unless stated;
+ *  - argument errors are reported synchronously and leave nothing enqueued;
+ *    a failed HIP call returns FPPR_DEVICE_ERROR; fppr_last_error() gives a
+ *    thread-local description of the last failure;
+ *  - no call throws; all handles are opaque; destroy calls accept NULL.
+ */
+#ifndef FPPR_H
+#define FPPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPPR_API __attribute__((visibility("default")))
+
+typedef enum {
+  FPPR_OK = 0,
+  FPPR_INVALID_ARGUMENT = 1,
+  FPPR_OUT_OF_MEMORY = 2,
+  FPPR_DEVICE_ERROR = 3,
+  FPPR_NOT_READY = 4,  /* poll: request still running */
+  FPPR_CAPACITY = 5,   /* submit: admitted later (queued), not an error */
+  FPPR_CANCELLED = 6,
+  FPPR_INTERNAL = 7
+} fppr_status;
+
+enum { FPPR_MEM_HOST = 0, FPPR_MEM_DEVICE = 1 };
+
+/* Walks stop after this many moves even without a terminating coin (never
+ * reached in practice for alpha >= 0.01); both the library and any checker
+ * apply the same cap. */
+#define FPPR_MOVE_CAP 65536u
+
+/* Padding entry of top-k lists shorter than k: (FPPR_NO_NODE, 0). */
+#define FPPR_NO_NODE 0xFFFFFFFFu
+
+typedef struct fppr_graph fppr_graph;
+
+/* Graph in CSR form (Sec. 2.1: G = (V, E, w), w(e) > 0; the paper keeps each
+ * node's out-neighbour set, Sec. 2.3). Multi-edges and self-loops are
+ * allowed; edge order within a row decides which edge a given draw hits, so
+ * callers that compare runs keep the same order (canonical: sorted by
+ * (dst, w)). */
+typedef struct {
+  uint32_t n;                  /* nodes, 1 <= n <= 2^32 - 2 */
+  uint64_t m;                  /* edges, m < 2^40 */
+  const uint64_t* row_offsets; /* [n+1]: 0 = off[0] <= off[1] <= ... <= off[n] = m */
+  const uint32_t* col;         /* [m]: destination of each edge, < n */
+  const uint32_t* w;           /* [m]: weight of each edge, >= 1 */
+  int mem;                     /* FPPR_MEM_HOST: copied at create;
+                                  FPPR_MEM_DEVICE: borrowed, the caller keeps the
+                                  arrays alive and unchanged in shape until
+                                  fppr_graph_destroy */
+} fppr_csr;
+
+typedef struct {
+  /* Rows with more than hub_threshold out-edges ("hubs", the large nodes of
+   * Sec. 4.1) are searched in two levels: a top-level table of every
+   * chunk-th prefix, then one chunk. This is the integer counterpart of the
+   * alias tree (Algorithm 3, Lemma 1): it picks exactly the same edge as a
+   * flat search, so it never changes results. 0 selects 4096; UINT32_MAX
+   * disables splitting (rows of 2^23 or more edges are split regardless). */
+  uint32_t hub_threshold;
+  /* Chunk size of hub rows: a power of two in [64, 2^20]; 0 selects 4096. */
+  uint32_t chunk;
+} fppr_graph_opts;
+
+/* Creates the device graph: validates the CSR (device-side; INVALID_ARGUMENT
+ * on n == 0, n > 2^32-2, m >= 2^40, a non-monotone offset array, off[0] != 0,
+ * off[n] != m, col >= n, w == 0, more than 2^23-1 hubs), computes the
+ * per-row inclusive uint64 weight prefixes, the 16-byte node records and the
+ * hub tables. Synchronous: returns after the graph is ready. The library
+ * allocates its own device arrays (freed by fppr_graph_destroy).
+ * opts may be NULL (defaults). */
+FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opts* opts,
+                                       void* stream, fppr_graph** out);
+FPPR_API fppr_status fppr_graph_destroy(fppr_graph* g);
+
+/* Recomputes every derived array (prefixes, records, hub tables; the pool if
+ * one was built) from the CSR the graph was created from, asynchronously on
+ * `stream`, without allocating. For a borrowed CSR whose col/w contents were
+ * rewritten in place; row_offsets must be unchanged. Validation failures are
+ * recorded on the device and reported by fppr_graph_check. */
+FPPR_API fppr_status fppr_graph_rebuild(fppr_graph* g, void* stream);
+
+/* Synchronises `stream` and reports a validation failure recorded by
+ * fppr_graph_rebuild (INVALID_ARGUMENT) or FPPR_OK. */
+FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream);
+
+/* Basic facts of a created graph (host outputs; any pointer may be NULL). */
+FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t* m,
+                                     uint32_t* n_hubs, uint64_t* n_small, uint64_t* device_bytes);
+
+typedef struct {
+  uint32_t S;     /* small nodes: 1 <= out-degree <= S (S >= 1) */
+  uint32_t L;     /* at most L plain steps per short walk, 1 <= L <= 255 */
+  uint32_t K;     /* short walks per small node: power of two in [1, 2^16] */
+  double alpha;   /* termination probability; runs that stitch must use the same */
+  uint64_t seed;  /* Philox key of the short walks, counter (slot j, step t, node v, 1) */
+} fppr_pool_opts;
+
+/* Short-walk pool (Sec. 4.2, "big moves" for small nodes): for every small
+ * node v, K walks of at most L plain steps from v, each stopping on its coin
+ * (marked terminated), after L steps, or on reaching a node without
+ * out-neighbours (both marked active). A stitched run takes, at a small
+ * node, slot j = floor(x0 * K / 2^32) of that node's pool: it jumps to the
+ * entry's end node, adds its steps, and stops iff the entry is terminated.
+ * Owned by the graph; building again replaces it. Asynchronous on `stream`
+ * (allocates on first build or when the size grows). */
+FPPR_API fppr_status fppr_graph_build_pool(fppr_graph* g, const fppr_pool_opts* opts, void* stream);
+
+/* Copies the pool to host memory in canonical order: small nodes by
+ * increasing id, then slot; entry = end | steps << 32 | mark << 48 (mark 1 =
+ * terminated). `entries` holds n_small * K values. Synchronous. */
+FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entries, uint64_t count,
+                                            void* stream);
+
+/* T(alpha) = floor(alpha * 2^32 + 1/2) clamped to [1, 2^32-1]: a walk stops
+ * after a move iff that move's x2 < T (Algorithm 2's coin "q <= alpha").
+ * Returns 0 when alpha is not in (0, 1). */
+FPPR_API uint32_t fppr_alpha_threshold(double alpha);
+
+/* Walks per source for the guarantee of Definition 1 (relative error eps for
+ * pi >= delta with probability 1 - pf): ceil((2 + 2 eps / 3) ln(2 / pf) /
+ * (eps^2 delta)), a Bernstein-bound constant for the Omega(log(1/pf) /
+ * (eps^2 delta)) of Sec. 2.1. Returns 0 on invalid input. */
+FPPR_API uint64_t fppr_walks_for_guarantee(double eps, double delta, double pf);
+
+enum {
+  FPPR_STITCH = 1u,    /* take pool entries at small nodes (needs a pool built
+                          with the same alpha) */
+  FPPR_COUNTS = 2u,    /* write per-source sparse counts */
+  FPPR_DIGESTS = 4u,   /* write per-source digests */
+  FPPR_STATS = 8u      /* accumulate walk statistics */
+};
+
+typedef struct {
+  double alpha;    /* termination probability in (0, 1) */
+  uint32_t R;      /* walks per source (omega of Algorithm 2), 1 <= R <= 2^20 */
+  uint64_t seed;   /* Philox key */
+  uint32_t topk;   /* k largest counts per source, 0 <= k <= R and k <= 1024 */
+  uint32_t flags;  /* FPPR_* bits */
+} fppr_params;
+
+/* Counters accumulated over a run (device memory, 8 x uint64, added to; the
+ * caller zeroes them). steps counts edges traversed: restarts and every
+ * step of a stitched move included. */
+typedef struct {
+  uint64_t walks;
+  uint64_t moves;          /* Philox-keyed iterations */
+  uint64_t steps;
+  uint64_t capped;         /* walks stopped by FPPR_MOVE_CAP */
+  uint64_t dangling_moves; /* restarts to the head */
+  uint64_t plain_moves;    /* weighted picks */
+  uint64_t stitched_moves; /* pool entries taken */
+  uint64_t probe_log_sum;  /* sum over plain moves of ceil(log2(out-degree)) */
+} fppr_stats;
+
+/* Stage timer: HIP events the library records on the run's stream around
+ * its walk kernel and its aggregation kernel. Created and owned by the
+ * caller through these calls. */
+typedef struct fppr_profile fppr_profile;
+FPPR_API fppr_status fppr_profile_create(fppr_profile** out);
+FPPR_API fppr_status fppr_profile_destroy(fppr_profile* p);
+/* Waits for the events of the last run that used `p` and returns the walk
+ * and aggregation kernel durations in milliseconds (host outputs). */
+FPPR_API fppr_status fppr_profile_read(fppr_profile* p, double* walk_ms, double* aggregate_ms);
+
+/* Outputs (all device pointers, caller-owned; NULL = not wanted):
+ *  topk       [n_src][k][2] uint32: (t, count) by count descending then t
+ *             ascending; rows shorter than k padded with (FPPR_NO_NODE, 0)
+ *  counts     [n_src][R][2] uint32: (t, count) sorted by t; entries beyond
+ *             n_distinct[s] are zero (needs FPPR_COUNTS)
+ *  n_distinct [n_src] uint32: number of distinct endpoints (with counts)
+ *  digest     [n_src] uint64: sum mod 2^64 over (t, count) of
+ *             fmix64(fmix64(s << 32 | t) ^ (count * 0x9E3779B97F4A7C15)),
+ *             fmix64 = MurmurHash3's 64-bit finalizer (needs FPPR_DIGESTS)
+ *  endpoints  [n_src][R] uint32: raw endpoint of walk i of source row j at
+ *             j * R + i; when given it replaces the workspace's endpoint
+ *             buffer
+ *  stats      one fppr_stats (needs FPPR_STATS)
+ *  profile    host handle of a stage timer, or NULL */
+typedef struct {
+  uint32_t* topk;
+  uint32_t* counts;
+  uint32_t* n_distinct;
+  uint64_t* digest;
+  uint32_t* endpoints;
+  fppr_stats* stats;
+  fppr_profile* profile;
+} fppr_out;
+
+/* Workspace size (bytes, 256-byte aligned device memory) for a run of
+ * n_sources sources. Pure host computation. */
+FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,
+                               uint64_t* workspace_bytes);
+
+/* Runs R walks from each source and aggregates them (Algorithm 2).
+ * sources: device uint32 [n_sources] (each < n; duplicates allowed), or NULL
+ * for all nodes 0..n-1 (then n_sources must equal n). n_sources == 0 is a
+ * no-op. workspace: device, >= fppr_plan bytes. Asynchronous on `stream`. */
+FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_t* sources,
+                              uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
+                              const fppr_out* out, void* stream);
+
+/* Synchronises `stream` and reports whether a run that used `workspace` met
+ * a source id >= n (INVALID_ARGUMENT; such a source gets no walks and its
+ * endpoints read FPPR_NO_NODE) or FPPR_OK. */
+FPPR_API fppr_status fppr_run_check(const void* workspace, void* stream);
+
+/* Thread-local text of the last failure ("" if none). */
+FPPR_API const char* fppr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

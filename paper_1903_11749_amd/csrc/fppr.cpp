@@ -1,0 +1,497 @@
+// C-ABI of the library: graph lifetime, pool, planning and runs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fppr_internal.hpp"
+
+struct fppr_profile {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace fppr {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout: [0, 256) control words, then the endpoint buffer.
+constexpr uint64_t kCtlBytes = 256;
+
+template <typename T>
+hipError_t dmalloc(T** p, uint64_t count, uint64_t* acc) {
+  uint64_t bytes = align_up(count * sizeof(T));
+  if (bytes == 0) bytes = kAlign;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e == hipSuccess) {
+    *p = static_cast<T*>(q);
+    if (acc) *acc += bytes;
+  }
+  return e;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(const_cast<void*>(static_cast<const void*>(p)));
+  p = nullptr;
+}
+
+void free_graph(fppr_graph* g) {
+  if (!g) return;
+  int prev = -1;
+  if (hipGetDevice(&prev) == hipSuccess && prev != g->device) (void)hipSetDevice(g->device);
+  if (g->owns_csr) {
+    dfree(g->off);
+    dfree(g->col);
+    dfree(g->w);
+  }
+  dfree(g->P);
+  dfree(g->rec);
+  dfree(g->hubs);
+  dfree(g->TL);
+  dfree(g->flag);
+  dfree(g->scan);
+  dfree(g->scan2);
+  dfree(g->rows);
+  dfree(g->scan_blocks);
+  dfree(g->d_err);
+  dfree(g->pool);
+  dfree(g->rec_st);
+  dfree(g->small_nodes);
+  if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
+  delete g;
+}
+
+std::string err_bits(uint32_t e) {
+  std::string s;
+  if (e & kErrOffsets) s += " row_offsets not monotone / off[0] != 0 / off[n] != m;";
+  if (e & kErrCol) s += " col >= n;";
+  if (e & kErrWeight) s += " weight == 0;";
+  if (e & kErrHubs) s += " too many hubs or hub table overflow;";
+  if (e & kErrDegree) s += " a row has 2^32 or more edges;";
+  if (e & kErrCapacity) s += " pool table overflow (graph changed shape);";
+  return s;
+}
+
+fppr_status invalid(const std::string& msg) {
+  set_error(msg);
+  return FPPR_INVALID_ARGUMENT;
+}
+
+// Host-visible copy of the control words of d_err.
+struct Ctl {
+  uint32_t err;
+  uint32_t n_rows;
+  uint64_t hubs;
+  uint64_t tl;
+  uint64_t small;
+};
+
+hipError_t read_ctl(const fppr_graph* g, hipStream_t s, Ctl* c) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  uint32_t raw[8];
+  e = hipMemcpy(raw, g->d_err, sizeof raw, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  c->err = raw[0];
+  c->n_rows = raw[1];
+  std::memcpy(&c->hubs, raw + 2, 8);
+  std::memcpy(&c->tl, raw + 4, 8);
+  std::memcpy(&c->small, raw + 6, 8);
+  return hipSuccess;
+}
+
+hipError_t zero_ctl(fppr_graph* g, hipStream_t s) {
+  return launch_zero_u64(reinterpret_cast<uint64_t*>(g->d_err), 8, s);
+}
+
+// prefixes, hub scans, records (no host sync); caps must already be sized
+hipError_t derive(fppr_graph* g, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_row_prefix(g, s)) != hipSuccess) return e;
+  if ((e = launch_hub_flags(g, s)) != hipSuccess) return e;
+  if ((e = launch_hub_chunks(g, s)) != hipSuccess) return e;
+  return launch_records(g, s);
+}
+
+uint32_t log2_exact(uint32_t v) {
+  uint32_t l = 0;
+  while ((1u << l) < v) ++l;
+  return l;
+}
+
+bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+fppr_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? FPPR_OUT_OF_MEMORY : FPPR_DEVICE_ERROR;
+}
+
+}  // namespace fppr
+
+using namespace fppr;
+
+extern "C" {
+
+FPPR_API const char* fppr_last_error(void) { return g_last_error.c_str(); }
+
+FPPR_API uint32_t fppr_alpha_threshold(double alpha) {
+  if (!(alpha > 0.0 && alpha < 1.0)) return 0;
+  double t = std::floor(alpha * 4294967296.0 + 0.5);
+  if (t < 1.0) t = 1.0;
+  if (t > 4294967295.0) t = 4294967295.0;
+  return static_cast<uint32_t>(t);
+}
+
+FPPR_API uint64_t fppr_walks_for_guarantee(double eps, double delta, double pf) {
+  if (!(eps > 0.0) || !(delta > 0.0 && delta <= 1.0) || !(pf > 0.0 && pf < 1.0)) return 0;
+  const double r = std::ceil((2.0 + 2.0 * eps / 3.0) * std::log(2.0 / pf) / (eps * eps * delta));
+  if (!(r < 1.8e19)) return 0;
+  return static_cast<uint64_t>(r);
+}
+
+FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opts* opts,
+                                       void* stream, fppr_graph** out) {
+  if (!out) return invalid("out is NULL");
+  *out = nullptr;
+  if (!csr) return invalid("csr is NULL");
+  if (csr->n == 0 || csr->n > 0xFFFFFFFEu) return invalid("n must be in [1, 2^32-2]");
+  if (csr->m >= (1ull << 40)) return invalid("m must be below 2^40");
+  if (!csr->row_offsets) return invalid("row_offsets is NULL");
+  if (csr->m && (!csr->col || !csr->w)) return invalid("col or w is NULL");
+  if (csr->mem != FPPR_MEM_HOST && csr->mem != FPPR_MEM_DEVICE) return invalid("mem must be HOST or DEVICE");
+  uint32_t H = 4096, C = 4096;
+  if (opts) {
+    if (opts->hub_threshold) H = opts->hub_threshold;
+    if (opts->chunk) C = opts->chunk;
+  }
+  if (!is_pow2(C) || C < 64 || C > (1u << 20)) return invalid("chunk must be a power of two in [64, 2^20]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  fppr_graph* g = new fppr_graph();
+  g->n = csr->n;
+  g->m = csr->m;
+  g->H = H;
+  g->chunk = C;
+  g->chunk_log2 = log2_exact(C);
+  hipError_t e = hipGetDevice(&g->device);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipGetDevice");
+  }
+  const uint64_t n = g->n, m = g->m;
+  uint64_t* acc = &g->device_bytes;
+#define FPPR_TRY(expr, what)        \
+  do {                              \
+    hipError_t e_ = (expr);         \
+    if (e_ != hipSuccess) {         \
+      fppr_status st_ = hip_fail(e_, what); \
+      free_graph(g);                \
+      return st_;                   \
+    }                               \
+  } while (0)
+
+  if (csr->mem == FPPR_MEM_HOST) {
+    uint64_t* off = nullptr;
+    uint32_t *col = nullptr, *w = nullptr;
+    g->owns_csr = true;
+    FPPR_TRY(dmalloc(&off, n + 1, acc), "hipMalloc(row_offsets)");
+    g->off = off;
+    FPPR_TRY(dmalloc(&col, m, acc), "hipMalloc(col)");
+    g->col = col;
+    FPPR_TRY(dmalloc(&w, m, acc), "hipMalloc(w)");
+    g->w = w;
+    FPPR_TRY(hipMemcpyAsync(off, csr->row_offsets, (n + 1) * 8, hipMemcpyHostToDevice, s), "copy offsets");
+    if (m) {
+      FPPR_TRY(hipMemcpyAsync(col, csr->col, m * 4, hipMemcpyHostToDevice, s), "copy col");
+      FPPR_TRY(hipMemcpyAsync(w, csr->w, m * 4, hipMemcpyHostToDevice, s), "copy w");
+    }
+  } else {
+    g->off = csr->row_offsets;
+    g->col = csr->col;
+    g->w = csr->w;
+  }
+  FPPR_TRY(dmalloc(&g->P, m, acc), "hipMalloc(P)");
+  FPPR_TRY(dmalloc(&g->rec, n, acc), "hipMalloc(rec)");
+  FPPR_TRY(dmalloc(&g->flag, n, acc), "hipMalloc(flag)");
+  FPPR_TRY(dmalloc(&g->scan, n, acc), "hipMalloc(scan)");
+  FPPR_TRY(dmalloc(&g->scan2, n, acc), "hipMalloc(scan2)");
+  FPPR_TRY(dmalloc(&g->rows, n, acc), "hipMalloc(rows)");
+  FPPR_TRY(dmalloc(&g->scan_blocks, scan_block_count(n) + 1, acc), "hipMalloc(scan blocks)");
+  FPPR_TRY(dmalloc(&g->d_err, 16, acc), "hipMalloc(ctl)");
+
+  FPPR_TRY(zero_ctl(g, s), "zero control words");
+  FPPR_TRY(launch_validate(g, s), "validate");
+  Ctl c{};
+  FPPR_TRY(read_ctl(g, s, &c), "read validation");
+  if (c.err) {
+    std::string msg = "invalid CSR:" + err_bits(c.err);
+    free_graph(g);
+    return invalid(msg);
+  }
+  FPPR_TRY(launch_row_prefix(g, s), "row prefix");
+  FPPR_TRY(launch_hub_flags(g, s), "hub flags");
+  FPPR_TRY(launch_hub_chunks(g, s), "hub chunks");
+  FPPR_TRY(read_ctl(g, s, &c), "read hub counts");
+  if (c.hubs >= kMaxHubs) {
+    free_graph(g);
+    return invalid("too many hub rows (raise hub_threshold)");
+  }
+  g->n_hub = static_cast<uint32_t>(c.hubs);
+  g->n_tl = c.tl;
+  FPPR_TRY(dmalloc(&g->hubs, g->n_hub, acc), "hipMalloc(hubs)");
+  FPPR_TRY(dmalloc(&g->TL, g->n_tl, acc), "hipMalloc(TL)");
+  FPPR_TRY(launch_records(g, s), "records");
+  FPPR_TRY(read_ctl(g, s, &c), "read records status");
+  if (c.err) {
+    std::string msg = "graph build failed:" + err_bits(c.err);
+    free_graph(g);
+    return invalid(msg);
+  }
+#undef FPPR_TRY
+  *out = g;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_graph_destroy(fppr_graph* g) {
+  if (!g) return FPPR_OK;
+  (void)hipDeviceSynchronize();
+  free_graph(g);
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t* m,
+                                     uint32_t* n_hubs, uint64_t* n_small, uint64_t* device_bytes) {
+  if (!g) return invalid("graph is NULL");
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (n_hubs) *n_hubs = g->n_hub;
+  if (n_small) *n_small = g->has_pool ? g->n_small : 0;
+  if (device_bytes) *device_bytes = g->device_bytes;
+  return FPPR_OK;
+}
+
+static fppr_status pool_kernels(fppr_graph* g, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_small_flags(g, g->pool_opts.S, s)) != hipSuccess) return hip_fail(e, "small flags");
+  if ((e = launch_small_compact(g, g->pool_opts.S, s)) != hipSuccess) return hip_fail(e, "small compact");
+  if ((e = launch_pool(g, s)) != hipSuccess) return hip_fail(e, "pool");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_graph_build_pool(fppr_graph* g, const fppr_pool_opts* o, void* stream) {
+  if (!g || !o) return invalid("graph or opts is NULL");
+  if (o->S < 1) return invalid("S must be >= 1");
+  if (o->L < 1 || o->L > 255) return invalid("L must be in [1, 255]");
+  if (!is_pow2(o->K) || o->K > 65536) return invalid("K must be a power of two in [1, 2^16]");
+  const uint32_t T = fppr_alpha_threshold(o->alpha);
+  if (!T) return invalid("alpha must be in (0, 1)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  uint64_t n_small = g->n_small;
+  if (!g->has_pool || g->pool_opts.S != o->S) {
+    if ((e = launch_small_flags(g, o->S, s)) != hipSuccess) return hip_fail(e, "small flags");
+    Ctl c{};
+    if ((e = read_ctl(g, s, &c)) != hipSuccess) return hip_fail(e, "read small count");
+    n_small = c.small;
+  }
+  const uint64_t need = n_small * o->K;
+  if (!g->rec_st) {
+    if ((e = dmalloc(&g->rec_st, g->n, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(rec_st)");
+    if ((e = dmalloc(&g->small_nodes, g->n, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(small nodes)");
+  }
+  if (need > g->pool_cap || !g->pool) {
+    if (g->pool) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+      g->device_bytes -= align_up(g->pool_cap * 8);
+      dfree(g->pool);
+      g->pool_cap = 0;
+    }
+    if ((e = dmalloc(&g->pool, need, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(pool)");
+    g->pool_cap = need;
+  }
+  g->pool_opts = *o;
+  g->pool_T = T;
+  g->K_log2 = log2_exact(o->K);
+  g->n_small = n_small;
+  g->has_pool = true;
+  return pool_kernels(g, s);
+}
+
+FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entries, uint64_t count,
+                                            void* stream) {
+  if (!g || !entries) return invalid("graph or entries is NULL");
+  if (!g->has_pool) return invalid("no pool built");
+  const uint64_t total = g->n_small * g->pool_opts.K;
+  if (count < total) return invalid("entries too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  if (total) {
+    e = hipMemcpy(entries, g->pool, total * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy pool");
+  }
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_graph_rebuild(fppr_graph* g, void* stream) {
+  if (!g) return invalid("graph is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if ((e = zero_ctl(g, s)) != hipSuccess) return hip_fail(e, "zero control words");
+  if ((e = launch_validate(g, s)) != hipSuccess) return hip_fail(e, "validate");
+  if ((e = derive(g, s)) != hipSuccess) return hip_fail(e, "derive");
+  if (g->has_pool) return pool_kernels(g, s);
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream) {
+  if (!g) return invalid("graph is NULL");
+  Ctl c{};
+  hipError_t e = read_ctl(g, static_cast<hipStream_t>(stream), &c);
+  if (e != hipSuccess) return hip_fail(e, "read control words");
+  if (c.err) return invalid("graph rebuild failed:" + err_bits(c.err));
+  return FPPR_OK;
+}
+
+static fppr_status check_params(const fppr_graph* g, const fppr_params* p) {
+  if (!g || !p) return invalid("graph or params is NULL");
+  if (!fppr_alpha_threshold(p->alpha)) return invalid("alpha must be in (0, 1)");
+  if (p->R < 1 || p->R > kAggMaxR) return invalid("R must be in [1, 4096]");
+  if (p->topk > p->R || p->topk > 1024) return invalid("topk must be <= R and <= 1024");
+  if (p->flags & ~(FPPR_STITCH | FPPR_COUNTS | FPPR_DIGESTS | FPPR_STATS)) return invalid("unknown flag bits");
+  if (p->flags & FPPR_STITCH) {
+    if (!g->has_pool) return invalid("FPPR_STITCH needs a pool (fppr_graph_build_pool)");
+    if (g->pool_T != fppr_alpha_threshold(p->alpha)) return invalid("pool was built for another alpha");
+  }
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,
+                               uint64_t* workspace_bytes) {
+  fppr_status st = check_params(g, p);
+  if (st != FPPR_OK) return st;
+  if (!workspace_bytes) return invalid("workspace_bytes is NULL");
+  *workspace_bytes = kCtlBytes + align_up(n_sources * p->R * 4ull);
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_t* sources,
+                              uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
+                              const fppr_out* out, void* stream) {
+  fppr_status st = check_params(g, p);
+  if (st != FPPR_OK) return st;
+  if (!out) return invalid("out is NULL");
+  if (!sources && n_sources != g->n) return invalid("sources == NULL needs n_sources == n");
+  if (n_sources == 0) return FPPR_OK;
+  if (n_sources > (1ull << 40) / p->R) return invalid("n_sources * R too large");
+  uint64_t need = 0;
+  fppr_plan(g, p, n_sources, &need);
+  if (!workspace || workspace_bytes < need) return invalid("workspace missing or smaller than fppr_plan");
+  if (p->topk && !out->topk) return invalid("topk > 0 needs out->topk");
+  if ((p->flags & FPPR_COUNTS) && (!out->counts || !out->n_distinct)) return invalid("FPPR_COUNTS needs out->counts and out->n_distinct");
+  if ((p->flags & FPPR_DIGESTS) && !out->digest) return invalid("FPPR_DIGESTS needs out->digest");
+  if ((p->flags & FPPR_STATS) && !out->stats) return invalid("FPPR_STATS needs out->stats");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* ctl = static_cast<unsigned long long*>(workspace);
+  uint32_t* endpoints = out->endpoints
+                            ? out->endpoints
+                            : reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + kCtlBytes);
+  hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(ctl), kCtlBytes / 8, s);
+  if (e != hipSuccess) return hip_fail(e, "zero control words");
+
+  WalkLaunch w{};
+  const bool stitch = (p->flags & FPPR_STITCH) != 0;
+  w.rec = stitch ? g->rec_st : g->rec;
+  w.sources = sources;
+  w.n_src = n_sources;
+  w.R = p->R;
+  w.R_magic = ~0ull / p->R;
+  w.key0 = static_cast<uint32_t>(p->seed);
+  w.key1 = static_cast<uint32_t>(p->seed >> 32);
+  w.T = fppr_alpha_threshold(p->alpha);
+  w.pool = stitch ? g->pool : nullptr;
+  w.K_log2 = stitch ? g->K_log2 : 0;
+  w.stitch = stitch;
+  w.endpoints = endpoints;
+  w.work_counter = ctl;
+  w.stats = (p->flags & FPPR_STATS) ? out->stats : nullptr;
+  fppr_profile* prof = out->profile;
+  if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
+  if ((e = launch_walk(g, w, s)) != hipSuccess) return hip_fail(e, "walk kernel");
+  if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
+
+  AggLaunch a{};
+  a.endpoints = endpoints;
+  a.sources = sources;
+  a.n_src = n_sources;
+  a.R = p->R;
+  a.k = p->topk;
+  a.topk = p->topk ? out->topk : nullptr;
+  a.counts = (p->flags & FPPR_COUNTS) ? out->counts : nullptr;
+  a.n_distinct = (p->flags & FPPR_COUNTS) ? out->n_distinct : nullptr;
+  a.digest = (p->flags & FPPR_DIGESTS) ? out->digest : nullptr;
+  if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
+  if (a.topk || a.counts || a.digest) {
+    if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");
+  }
+  if (prof && (e = hipEventRecord(prof->ev[3], s)) != hipSuccess) return hip_fail(e, "event");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_profile_create(fppr_profile** out) {
+  if (!out) return invalid("out is NULL");
+  auto* p = new fppr_profile();
+  for (auto& e : p->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      fppr_profile_destroy(p);
+      return hip_fail(r, "hipEventCreate");
+    }
+  }
+  *out = p;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_profile_destroy(fppr_profile* p) {
+  if (!p) return FPPR_OK;
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete p;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_profile_read(fppr_profile* p, double* walk_ms, double* aggregate_ms) {
+  if (!p) return invalid("profile is NULL");
+  hipError_t e = hipEventSynchronize(p->ev[3]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  float a = 0.f, b = 0.f;
+  if ((e = hipEventElapsedTime(&a, p->ev[0], p->ev[1])) != hipSuccess) return hip_fail(e, "elapsed");
+  if ((e = hipEventElapsedTime(&b, p->ev[2], p->ev[3])) != hipSuccess) return hip_fail(e, "elapsed");
+  if (walk_ms) *walk_ms = a;
+  if (aggregate_ms) *aggregate_ms = b;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_run_check(const void* workspace, void* stream) {
+  if (!workspace) return invalid("workspace is NULL");
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  unsigned long long ctl[2];
+  e = hipMemcpy(ctl, workspace, sizeof ctl, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "read run status");
+  if (ctl[1]) return invalid("a source id was >= n (its walks were skipped)");
+  return FPPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Host-side internals of the library: the graph object and the kernel launch
+// entry points of each stage.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fppr.h"
+#include "fppr_device.hpp"
+
+namespace fppr {
+
+// Error bits written by the validation kernels.
+enum : uint32_t {
+  kErrOffsets = 1u,
+  kErrCol = 2u,
+  kErrWeight = 4u,
+  kErrHubs = 8u,
+  kErrDegree = 16u,
+  kErrCapacity = 32u,
+};
+
+struct DeviceBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace fppr
+
+struct fppr_graph {
+  int device = 0;
+  uint32_t n = 0;
+  uint64_t m = 0;
+  // CSR on the device (borrowed, or owned copies of host input)
+  const uint64_t* off = nullptr;
+  const uint32_t* col = nullptr;
+  const uint32_t* w = nullptr;
+  bool owns_csr = false;
+  // derived arrays
+  uint64_t* P = nullptr;            // [m]
+  uint4* rec = nullptr;             // [n]
+  uint32_t H = 4096, chunk = 4096, chunk_log2 = 12;
+  uint32_t n_hub = 0;
+  uint64_t n_tl = 0;
+  fppr::HubEntry* hubs = nullptr;   // [n_hub]
+  uint64_t* TL = nullptr;           // [n_tl]
+  // scratch (kept for rebuilds)
+  uint32_t* flag = nullptr;         // [n]   per-node u32 input of scans
+  uint64_t* scan = nullptr;         // [n]   exclusive scan output
+  uint64_t* scan2 = nullptr;        // [n]
+  uint32_t* rows = nullptr;         // [n]   list of long rows
+  uint64_t* scan_blocks = nullptr;  // block sums of the scans
+  uint32_t* d_err = nullptr;        // [4]   error bits, counters
+  // pool
+  bool has_pool = false;
+  fppr_pool_opts pool_opts{};
+  uint32_t pool_T = 0;
+  uint32_t K_log2 = 0;
+  uint64_t n_small = 0;
+  uint64_t* pool = nullptr;          // [n_small * K]
+  uint64_t pool_cap = 0;             // entries allocated
+  uint4* rec_st = nullptr;           // [n] stitched records
+  uint32_t* small_nodes = nullptr;   // [n] rank -> node
+  uint64_t device_bytes = 0;
+};
+
+namespace fppr {
+
+void set_error(const std::string& msg);
+fppr_status hip_fail(hipError_t e, const char* what);
+
+// build.hip
+hipError_t launch_validate(const fppr_graph* g, hipStream_t s);
+hipError_t launch_row_prefix(fppr_graph* g, hipStream_t s);
+// flag[u] = 1 for hub rows, scan -> hub ids; flag[u] = nchunks, scan2 -> TL offsets
+hipError_t launch_hub_flags(fppr_graph* g, hipStream_t s);
+hipError_t launch_hub_chunks(fppr_graph* g, hipStream_t s);
+hipError_t launch_records(fppr_graph* g, hipStream_t s);
+// exclusive scan of u32 input to u64 output; writes the total to *total_dev
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* blocks,
+                           uint64_t* total_dev, hipStream_t s);
+uint64_t scan_block_count(uint64_t n);
+
+// pool.hip
+hipError_t launch_small_flags(fppr_graph* g, uint32_t S, hipStream_t s);
+hipError_t launch_small_compact(fppr_graph* g, uint32_t S, hipStream_t s);
+hipError_t launch_pool(fppr_graph* g, hipStream_t s);
+
+// walk.hip
+struct WalkLaunch {
+  const uint4* rec;
+  const uint32_t* sources;
+  uint64_t n_src;
+  uint32_t R;
+  uint64_t R_magic;   // floor((2^64 - 1) / R)
+  uint32_t key0, key1, T;
+  const uint64_t* pool;
+  uint32_t K_log2;
+  bool stitch;
+  uint32_t* endpoints;
+  unsigned long long* work_counter;  // zeroed before launch
+  fppr_stats* stats;                 // may be null
+};
+hipError_t launch_walk(const fppr_graph* g, const WalkLaunch& a, hipStream_t s);
+hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s);
+
+// aggregate.hip
+struct AggLaunch {
+  const uint32_t* endpoints;
+  const uint32_t* sources;
+  uint64_t n_src;
+  uint32_t R;
+  uint32_t k;
+  uint32_t* topk;
+  uint32_t* counts;
+  uint32_t* n_distinct;
+  uint64_t* digest;
+};
+hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s);
+constexpr uint32_t kAggMaxR = 4096;
+
+}  // namespace fppr

@@ -1,0 +1,334 @@
+"""Thin Python binding of the fppr C-ABI (include/fppr.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. PyTorch provides device memory and streams. The functions keep
+the C names; `Graph` and `run` are small conveniences over them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfppr.so")
+
+FPPR_OK = 0
+FPPR_INVALID_ARGUMENT = 1
+FPPR_OUT_OF_MEMORY = 2
+FPPR_DEVICE_ERROR = 3
+FPPR_NOT_READY = 4
+FPPR_CAPACITY = 5
+FPPR_CANCELLED = 6
+FPPR_INTERNAL = 7
+FPPR_MEM_HOST = 0
+FPPR_MEM_DEVICE = 1
+FPPR_STITCH = 1
+FPPR_COUNTS = 2
+FPPR_DIGESTS = 4
+FPPR_STATS = 8
+FPPR_MOVE_CAP = 65536
+FPPR_NO_NODE = 0xFFFFFFFF
+
+STATS_FIELDS = ("walks", "moves", "steps", "capped", "dangling_moves", "plain_moves",
+                "stitched_moves", "probe_log_sum")
+
+
+class FpprError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fppr status {status}: {msg}")
+        self.status = status
+
+
+class fppr_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("row_offsets", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("mem", ctypes.c_int)]
+
+
+class fppr_graph_opts(ctypes.Structure):
+    _fields_ = [("hub_threshold", ctypes.c_uint32), ("chunk", ctypes.c_uint32)]
+
+
+class fppr_pool_opts(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_uint32), ("L", ctypes.c_uint32), ("K", ctypes.c_uint32),
+                ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class fppr_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("R", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("topk", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class fppr_out(ctypes.Structure):
+    _fields_ = [("topk", ctypes.c_void_p), ("counts", ctypes.c_void_p),
+                ("n_distinct", ctypes.c_void_p), ("digest", ctypes.c_void_p),
+                ("endpoints", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("profile", ctypes.c_void_p)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported symbol
+P = ctypes.c_void_p
+_SIGS = [
+    ("fppr_graph_create", ctypes.c_int, [ctypes.POINTER(fppr_csr), ctypes.POINTER(fppr_graph_opts), P,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    ("fppr_graph_destroy", ctypes.c_int, [P]),
+    ("fppr_graph_rebuild", ctypes.c_int, [P, P]),
+    ("fppr_graph_check", ctypes.c_int, [P, P]),
+    ("fppr_graph_info", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
+    ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
+    ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
+    ("fppr_walks_for_guarantee", ctypes.c_uint64, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    ("fppr_plan", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_run", ctypes.c_int, [P, ctypes.POINTER(fppr_params), P, ctypes.c_uint64, P, ctypes.c_uint64,
+                                ctypes.POINTER(fppr_out), P]),
+    ("fppr_run_check", ctypes.c_int, [P, P]),
+    ("fppr_profile_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
+    ("fppr_profile_destroy", ctypes.c_int, [P]),
+    ("fppr_profile_read", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    ("fppr_last_error", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """Loads the in-tree libfppr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FpprError(FPPR_INTERNAL, f"{LIB_PATH} is missing: build it first "
+                            "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [name for name, _, _ in _SIGS]
+
+
+def _check(status):
+    if status != FPPR_OK:
+        raise FpprError(status, lib().fppr_last_error().decode())
+
+
+def fppr_alpha_threshold(alpha: float) -> int:
+    return int(lib().fppr_alpha_threshold(float(alpha)))
+
+
+def fppr_walks_for_guarantee(eps: float, delta: float, pf: float) -> int:
+    return int(lib().fppr_walks_for_guarantee(eps, delta, pf))
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """Device graph. `csr` is a CSR object with n, row_offsets, col, w (numpy
+    arrays: copied) or torch device tensors (borrowed: kept referenced here)."""
+
+    def __init__(self, csr=None, hub_threshold: int = 0, chunk: int = 0, stream=None, *, n=None,
+                 row_offsets=None, col=None, w=None):
+        import torch
+
+        if csr is not None:
+            n, row_offsets, col, w = csr.n, csr.row_offsets, csr.col, csr.w
+        self.n = int(n)
+        self._keep = None
+        c = fppr_csr()
+        c.n = self.n
+        c.m = int(col.shape[0])
+        if isinstance(col, torch.Tensor):
+            assert row_offsets.dtype == torch.int64 and col.dtype == torch.int32 and w.dtype == torch.int32
+            assert row_offsets.is_cuda and col.is_cuda and w.is_cuda
+            self._keep = (row_offsets, col, w)
+            c.row_offsets, c.col, c.w = _dptr(row_offsets), _dptr(col), _dptr(w)
+            c.mem = FPPR_MEM_DEVICE
+        else:
+            ro = np.ascontiguousarray(row_offsets, dtype=np.uint64)
+            cl = np.ascontiguousarray(col, dtype=np.uint32)
+            ww = np.ascontiguousarray(w, dtype=np.uint32)
+            self._host = (ro, cl, ww)
+            c.row_offsets = ro.ctypes.data
+            c.col = cl.ctypes.data if cl.size else None
+            c.w = ww.ctypes.data if ww.size else None
+            c.mem = FPPR_MEM_HOST
+        self.m = int(c.m)
+        o = fppr_graph_opts(hub_threshold, chunk)
+        h = ctypes.c_void_p()
+        _check(lib().fppr_graph_create(ctypes.byref(c), ctypes.byref(o), _stream_ptr(stream),
+                                       ctypes.byref(h)))
+        self._h = h
+        self._host = None
+        self.pool_opts = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n = ctypes.c_uint32()
+        m = ctypes.c_uint64()
+        hubs = ctypes.c_uint32()
+        small = ctypes.c_uint64()
+        by = ctypes.c_uint64()
+        _check(lib().fppr_graph_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(hubs),
+                                     ctypes.byref(small), ctypes.byref(by)))
+        return dict(n=n.value, m=m.value, hubs=hubs.value, small=small.value, device_bytes=by.value)
+
+    def build_pool(self, S: int, L: int, K: int, alpha: float, seed: int, stream=None):
+        o = fppr_pool_opts(S, L, K, alpha, seed)
+        _check(lib().fppr_graph_build_pool(self._h, ctypes.byref(o), _stream_ptr(stream)))
+        self.pool_opts = dict(S=S, L=L, K=K, alpha=alpha, seed=seed)
+
+    def export_pool(self, stream=None) -> np.ndarray:
+        info = self.info()
+        count = info["small"] * self.pool_opts["K"]
+        out = np.zeros(max(count, 1), dtype=np.uint64)
+        _check(lib().fppr_graph_export_pool(self._h, out.ctypes.data, count, _stream_ptr(stream)))
+        return out[:count]
+
+    def rebuild(self, stream=None):
+        _check(lib().fppr_graph_rebuild(self._h, _stream_ptr(stream)))
+
+    def check(self, stream=None):
+        _check(lib().fppr_graph_check(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fppr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(alpha, R, seed, topk=0, stitch=False, counts=True, digests=True, stats=True):
+    flags = (FPPR_STITCH if stitch else 0) | (FPPR_COUNTS if counts else 0) | \
+        (FPPR_DIGESTS if digests else 0) | (FPPR_STATS if stats else 0)
+    return fppr_params(float(alpha), int(R), int(seed), int(topk), flags)
+
+
+def fppr_plan(graph: Graph, params: fppr_params, n_sources: int) -> int:
+    ws = ctypes.c_uint64()
+    _check(lib().fppr_plan(graph.handle, ctypes.byref(params), n_sources, ctypes.byref(ws)))
+    return int(ws.value)
+
+
+@dataclass
+class Outputs:
+    topk: object = None        # torch int32 [n_src, k, 2] (bit pattern of uint32)
+    counts: object = None      # torch int32 [n_src, R, 2]
+    n_distinct: object = None  # torch int32 [n_src]
+    digest: object = None      # torch int64 [n_src]
+    endpoints: object = None   # torch int32 [n_src, R]
+    stats: object = None       # torch int64 [8]
+    profile: object = None     # Profile (stage timer) or None
+
+    def stats_dict(self):
+        if self.stats is None:
+            return None
+        v = self.stats.cpu().numpy().astype(np.uint64)
+        return {k: int(x) for k, x in zip(STATS_FIELDS, v)}
+
+
+def alloc_outputs(n_src, R, topk, counts=True, digests=True, stats=True, endpoints=False,
+                  device="cuda"):
+    import torch
+
+    o = Outputs()
+    if topk:
+        o.topk = torch.empty((n_src, topk, 2), dtype=torch.int32, device=device)
+    if counts:
+        o.counts = torch.empty((n_src, R, 2), dtype=torch.int32, device=device)
+        o.n_distinct = torch.empty((n_src,), dtype=torch.int32, device=device)
+    if digests:
+        o.digest = torch.empty((n_src,), dtype=torch.int64, device=device)
+    if stats:
+        o.stats = torch.zeros((8,), dtype=torch.int64, device=device)
+    if endpoints:
+        o.endpoints = torch.empty((n_src, R), dtype=torch.int32, device=device)
+    return o
+
+
+def fppr_run(graph: Graph, params: fppr_params, sources, n_sources: int, workspace, out: Outputs,
+             stream=None):
+    """sources: torch int32 device tensor or None (all nodes)."""
+    o = fppr_out(_dptr(out.topk), _dptr(out.counts), _dptr(out.n_distinct), _dptr(out.digest),
+                 _dptr(out.endpoints), _dptr(out.stats),
+                 out.profile.handle if out.profile is not None else None)
+    _check(lib().fppr_run(graph.handle, ctypes.byref(params), _dptr(sources), n_sources,
+                          _dptr(workspace), workspace.numel() * workspace.element_size(),
+                          ctypes.byref(o), _stream_ptr(stream)))
+
+
+class Profile:
+    """Stage timer: walk and aggregation kernel durations of the last run."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().fppr_profile_create(ctypes.byref(h)))
+        self.handle = h
+
+    def read(self):
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(lib().fppr_profile_read(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib().fppr_profile_destroy(self.handle)
+            self.handle = None
+
+
+def fppr_run_check(workspace, stream=None):
+    _check(lib().fppr_run_check(_dptr(workspace), _stream_ptr(stream)))
+
+
+def run(graph: Graph, alpha, R, seed, sources=None, topk=0, stitch=False, counts=True,
+        digests=True, stats=True, endpoints=False, stream=None, check=True) -> Outputs:
+    """Allocates workspace and outputs with torch, runs, and returns the outputs
+    (device tensors). sources: None (all nodes) or an int sequence / tensor."""
+    import torch
+
+    if sources is None:
+        src = None
+        n_src = graph.n
+    else:
+        src = torch.as_tensor(np.asarray(sources, dtype=np.uint32).view(np.int32)
+                              if not isinstance(sources, torch.Tensor) else sources)
+        src = src.to(device="cuda", dtype=torch.int32).contiguous()
+        n_src = int(src.numel())
+    p = make_params(alpha, R, seed, topk, stitch, counts, digests, stats)
+    ws_bytes = fppr_plan(graph, p, n_src)
+    ws = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device="cuda")
+    out = alloc_outputs(n_src, R, topk, counts, digests, stats, endpoints)
+    fppr_run(graph, p, src, n_src, ws, out, stream)
+    if check:
+        fppr_run_check(ws, stream)
+    out._workspace = ws
+    return out
