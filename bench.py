@@ -43,15 +43,50 @@ def alg_bytes(st: dict) -> int:
             + 8 * st["stitched_moves"] + 4 * st["walks"])
 
 
+WALK_SOURCES = ["paper_1903_11749_amd/csrc/walk.hip", "paper_1903_11749_amd/csrc/fppr_device.hpp",
+                "paper_1903_11749_amd/csrc/fppr_internal.hpp"]
+PMC_SUMMARY = "profiles/k_walk_rmat24_pmc.md"
+
+
+def walk_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic():
+    """HBM bytes per walk launch from the committed counter summary, or None
+    when the walk kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if ":" in line and line.split(":", 1)[0] in ("walk_kernel_source_sha256",
+                                                     "walk_traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("walk_kernel_source_sha256") != walk_source_hash():
+        return None
+    return int(vals["walk_traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["scale24", "medium"], default="scale24")
-    ap.add_argument("--cpu-sample", type=int, default=8192,
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device-to-device 3 times (scale for byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -68,6 +103,17 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     fppr.lib()
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy // 4 * 4
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nb, "copies": 3}), flush=True)
+        return
 
     if args.workload == "scale24":
         cfg = dict(synth.SCALE24)
@@ -143,8 +189,9 @@ def main():
     walk_avg = float(np.mean(walk_ms))
     ab = alg_bytes(st_last)
     achieved = ab / (walk_avg / 1e3) / 1e9
+    traffic = counted_traffic() if args.workload == "scale24" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
                 "kernel": "k_walk", "kernel_ms": round(walk_avg, 3),
                 "alg_bytes_per_launch": ab,
                 "walk_steps_per_s_kernel": round(st_last["steps"] / (walk_avg / 1e3), 1),
