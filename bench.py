@@ -1,8 +1,9 @@
 """Benchmark: one step = the whole hot path on the R-MAT scale-24 workload.
 
 Step (all on one HIP stream, CSR already resident in HBM):
-  rebuild   validation, per-row uint64 weight prefixes, node records, hub
-            split (hubs: > 4096 out-edges, chunks of 4096)
+  rebuild   validation, per-row uint64 weight prefixes, node records, and
+            the 8-ary prefix trees of every row above 8 out-edges (the
+            split of large nodes; it never changes results)
   pool      short walks of <= 3 steps for every node of out-degree <= 32
             (K = 64 per node)
   run       128 walks from every one of the 2^24 sources, alpha = 0.15,
@@ -85,6 +86,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")
+    ap.add_argument("--hub-threshold", type=int, default=0,
+                    help="rows above this many edges get a prefix tree (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device 3 times (scale for byte counters)")
     args = ap.parse_args()
@@ -121,7 +124,7 @@ def main():
         g = synth.scale24_graph()
         wname = ("rmat-scale24 (n=2^24, m=2^28, a,b,c,d=.57,.19,.19,.05, Zipf(1.2) weights "
                  "in [1,1e4]), alpha=0.15, R=128, all sources, short walks S=32 L=3 K=64, "
-                 "hubs >4096, top-32")
+                 "large rows split, top-32")
     else:
         cfg = dict(synth.MEDIUM)
         cfg["hub_threshold"] = 4096
@@ -138,7 +141,7 @@ def main():
     col = torch.from_numpy(g.col.view(np.int32)).cuda()
     w = torch.from_numpy(g.w.view(np.int32)).cuda()
     torch.cuda.synchronize()
-    G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=cfg["hub_threshold"])
+    G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=args.hub_threshold)
     if st_cfg:
         G.build_pool(S=st_cfg["S"], L=st_cfg["L"], K=st_cfg["K"], alpha=alpha, seed=st_cfg["seed"])
     info = G.info()
@@ -203,7 +206,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64 integer",
         "data": "synthetic (seeded R-MAT; stands in for the paper's SNAP graphs)",
         "config": {"workload": wname, "n": g.n, "m": g.m, "R": R, "alpha": alpha, "seed": seed,
-                   "topk": k, "hubs": info["hubs"], "small_nodes": info["small"]},
+                   "topk": k, "tree_rows": info["hubs"], "small_nodes": info["small"],
+                   "rows_over_4096": int((g.degrees() > 4096).sum())},
         "sources_per_s": round(sources_per_s, 1),
         "walk_stats_per_step": st_last,
         "aggregate_ms": round(float(np.mean(agg_ms)), 3),

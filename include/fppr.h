@@ -75,7 +75,7 @@ typedef struct fppr_graph fppr_graph;
  * (dst, w)). */
 typedef struct {
   uint32_t n;                  /* nodes, 1 <= n <= 2^32 - 2 */
-  uint64_t m;                  /* edges, m < 2^40 */
+  uint64_t m;                  /* edges, m < 2^36 */
   const uint64_t* row_offsets; /* [n+1]: 0 = off[0] <= off[1] <= ... <= off[n] = m */
   const uint32_t* col;         /* [m]: destination of each edge, < n */
   const uint32_t* w;           /* [m]: weight of each edge, >= 1 */
@@ -86,29 +86,29 @@ typedef struct {
 } fppr_csr;
 
 typedef struct {
-  /* Rows with more than hub_threshold out-edges ("hubs", the large nodes of
-   * Sec. 4.1) are searched in two levels: a top-level table of every
-   * chunk-th prefix, then one chunk. This is the integer counterpart of the
-   * alias tree (Algorithm 3, Lemma 1): it picks exactly the same edge as a
-   * flat search, so it never changes results. 0 selects 4096; UINT32_MAX
-   * disables splitting (rows of 2^23 or more edges are split regardless). */
+  /* Rows with more than hub_threshold out-edges (the large nodes of Sec. 4.1)
+   * carry an 8-ary prefix tree, the integer counterpart of the alias tree
+   * (Algorithm 3, Lemma 1): the row is cut into groups of 8 edges whose
+   * running totals form the next level, recursively, and a pick descends
+   * one 64-byte node per level. It returns exactly the edge a flat search
+   * returns, so the threshold never changes results. 0 selects 8 (the
+   * fastest); values below 8 act as 8; UINT32_MAX disables trees (rows of
+   * more than 8 edges are then binary-searched). */
   uint32_t hub_threshold;
-  /* Chunk size of hub rows: a power of two in [64, 2^20]; 0 selects 4096. */
-  uint32_t chunk;
 } fppr_graph_opts;
 
 /* Creates the device graph: validates the CSR (device-side; INVALID_ARGUMENT
- * on n == 0, n > 2^32-2, m >= 2^40, a non-monotone offset array, off[0] != 0,
- * off[n] != m, col >= n, w == 0, more than 2^23-1 hubs), computes the
+ * on n == 0, n > 2^32-2, m >= 2^36, a non-monotone offset array, off[0] != 0,
+ * off[n] != m, col >= n, w == 0, a row of 2^27 or more edges), computes the
  * per-row inclusive uint64 weight prefixes, the 16-byte node records and the
- * hub tables. Synchronous: returns after the graph is ready. The library
+ * prefix trees. Synchronous: returns after the graph is ready. The library
  * allocates its own device arrays (freed by fppr_graph_destroy).
  * opts may be NULL (defaults). */
 FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opts* opts,
                                        void* stream, fppr_graph** out);
 FPPR_API fppr_status fppr_graph_destroy(fppr_graph* g);
 
-/* Recomputes every derived array (prefixes, records, hub tables; the pool if
+/* Recomputes every derived array (prefixes, records, prefix trees; the pool if
  * one was built) from the CSR the graph was created from, asynchronously on
  * `stream`, without allocating. For a borrowed CSR whose col/w contents were
  * rewritten in place; row_offsets must be unchanged. Validation failures are
@@ -119,7 +119,9 @@ FPPR_API fppr_status fppr_graph_rebuild(fppr_graph* g, void* stream);
  * fppr_graph_rebuild (INVALID_ARGUMENT) or FPPR_OK. */
 FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream);
 
-/* Basic facts of a created graph (host outputs; any pointer may be NULL). */
+/* Basic facts of a created graph (host outputs; any pointer may be NULL):
+ * n_hubs = rows carrying a prefix tree, n_small = small nodes of the pool
+ * (0 without a pool), device_bytes = bytes the library allocated. */
 FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t* m,
                                      uint32_t* n_hubs, uint64_t* n_small, uint64_t* device_bytes);
 

@@ -144,10 +144,171 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
   }
 }
 
+// ---------------------------------------------------------------------------
+// R <= 256: one wave per source, E = ceil(R/64) endpoints per lane (element
+// index idx = e * 64 + lane), sorted across the wave with shuffles.
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint32_t (&v)[E]) {
+  const uint32_t lane = __lane_id();
+  constexpr uint32_t N = 64 * E;
+#pragma unroll
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {  // partner in another register of the same lane
+        const uint32_t je = j / 64;
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+          const uint32_t pe = e ^ je;
+          if (pe > e) {
+            const bool up = (((e * 64 + lane) & k) == 0);
+            const uint32_t a = v[e], b = v[pe];
+            const bool sw = (a > b) == up;
+            v[e] = sw ? b : a;
+            v[pe] = sw ? a : b;
+          }
+        }
+      } else {  // partner in lane ^ j of the same register
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+          const uint32_t idx = e * 64 + lane;
+          const uint32_t other = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v[e]), static_cast<int>(j), 64));
+          const bool up = (idx & k) == 0;
+          const bool lower = (lane & j) == 0;  // this lane holds the lower index
+          const bool take_min = (lower == up);
+          v[e] = take_min ? (v[e] < other ? v[e] : other) : (v[e] > other ? v[e] : other);
+        }
+      }
+    }
+  }
+}
+
+template <int E>
+__global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
+  constexpr uint32_t N = 64 * E;
+  __shared__ uint32_t run_t[kThreads / 64][N];
+  __shared__ uint32_t run_key[kThreads / 64][N];
+  const uint32_t lane = __lane_id();
+  const uint32_t wv = threadIdx.x / 64;
+  const uint32_t R = a.R;
+  const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (kThreads / 64);
+  for (uint64_t row = blockIdx.x * static_cast<uint64_t>(kThreads / 64) + wv; row < a.n_src;
+       row += nwaves) {
+    uint32_t v[E];
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t idx = e * 64 + lane;
+      v[e] = idx < R ? a.endpoints[row * R + idx] : kPad;
+    }
+    wave_bitonic<E>(v);
+
+    // run heads: first element of each group of equal endpoints
+    uint64_t hm[E];
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      uint32_t prev = static_cast<uint32_t>(__shfl_up(static_cast<int>(v[e]), 1, 64));
+      if (e > 0) {
+        const uint32_t wrap = static_cast<uint32_t>(__shfl(static_cast<int>(v[e - 1]), 63, 64));
+        if (lane == 0) prev = wrap;
+      }
+      const bool first = (e == 0 && lane == 0);
+      hm[e] = __ballot(v[e] != kPad && (first || prev != v[e]));
+    }
+    uint32_t nd = 0;
+    uint32_t before[E];
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      before[e] = nd;
+      nd += static_cast<uint32_t>(__popcll(hm[e]));
+    }
+    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
+    uint64_t dig = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t idx = e * 64 + lane;
+      if ((hm[e] >> lane) & 1ull) {
+        const uint32_t rank = before[e] + mask_rank(hm[e]);
+        // next head after idx, or R (end of the valid endpoints)
+        const uint64_t above = lane == 63 ? 0ull : (hm[e] & (~0ull << (lane + 1)));
+        uint32_t nxt = R;
+        if (above) {
+          nxt = e * 64 + static_cast<uint32_t>(__builtin_ctzll(above));
+        } else {
+#pragma unroll
+          for (uint32_t e2 = E - 1; e2 > e; --e2)
+            if (hm[e2]) nxt = e2 * 64 + static_cast<uint32_t>(__builtin_ctzll(hm[e2]));
+        }
+        const uint32_t c = nxt - idx;
+        if (a.counts) {
+          a.counts[(row * R + rank) * 2] = v[e];
+          a.counts[(row * R + rank) * 2 + 1] = c;
+        }
+        if (a.digest) dig += digest_term(src, v[e], c);
+        run_t[wv][rank] = v[e];
+        // ranking key: count descending, then rank (= node id) ascending
+        run_key[wv][rank] = ((N - c) << 8) | rank;
+      }
+      if (a.counts && idx >= nd && idx < R) {
+        a.counts[(row * R + idx) * 2] = 0;
+        a.counts[(row * R + idx) * 2 + 1] = 0;
+      }
+    }
+    if (a.n_distinct && lane == 0) a.n_distinct[row] = nd;
+    if (a.digest) {
+      dig = wave_sum_u64(dig);
+      if (lane == 0) a.digest[row] = dig;
+    }
+    if (a.topk && a.k) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint32_t kv[E];
+#pragma unroll
+      for (uint32_t e = 0; e < E; ++e) {
+        const uint32_t idx = e * 64 + lane;
+        kv[e] = idx < nd ? run_key[wv][idx] : 0xFFFFFFFFu;
+      }
+      wave_bitonic<E>(kv);
+#pragma unroll
+      for (uint32_t e = 0; e < E; ++e) {
+        const uint32_t q = e * 64 + lane;
+        if (q < a.k) {
+          uint32_t t = kNoNode, c = 0;
+          if (q < nd) {
+            t = run_t[wv][kv[e] & 0xFFu];
+            c = N - (kv[e] >> 8);
+          }
+          a.topk[(row * a.k + q) * 2] = t;
+          a.topk[(row * a.k + q) * 2 + 1] = c;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 }  // namespace
 
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s) {
   if (a.n_src == 0) return hipSuccess;
+  if (a.R <= 256) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    uint64_t blocks = static_cast<uint64_t>(cus) * 16;
+    const uint64_t need = (a.n_src + 3) / 4;
+    if (blocks > need) blocks = need;
+    const dim3 grid(static_cast<uint32_t>(blocks)), block(kThreads);
+    if (a.R <= 64) hipLaunchKernelGGL(k_aggregate_wave<1>, grid, block, 0, s, a);
+    else if (a.R <= 128) hipLaunchKernelGGL(k_aggregate_wave<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_aggregate_wave<4>, grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   uint32_t Rp = kMinSeg;
   while (Rp < a.R) Rp <<= 1;
   const uint32_t spt = kTile / Rp;

@@ -1,12 +1,14 @@
-// Graph ingest: CSR validation, per-row inclusive uint64 weight prefixes,
-// 16-byte node records and hub top-level tables.
+// Graph ingest: CSR validation, per-row inclusive uint64 weight prefixes laid
+// out with the destination ids in 128-byte leaf blocks, 16-byte node records
+// and the rows' 16-ary prefix trees.
 //
 // Routing probability r(s,t) = w(s,t) / sum_v w(s,v) (Sec. 2.1) is realised
 // on exact integers: the prefix P of a row is strictly increasing (w >= 1),
 // so "first prefix above X" picks edge j for exactly P[j] - P[j-1] of the W
-// values of X. Large rows (Sec. 4.1, alias tree) get a top-level table of
-// every chunk-th prefix; searching it first and then one chunk returns the
-// same edge as a flat search (Lemma 1's telescoping product, on integers).
+// values of X. Large rows (Sec. 4.1, alias tree) are split recursively into
+// groups whose running totals form the next level; descending the tree
+// returns the same edge as a flat search (Lemma 1's telescoping product, on
+// integers), with one 128-byte node per level.
 #include "fppr_internal.hpp"
 
 namespace fppr {
@@ -41,120 +43,172 @@ __global__ void k_validate_edges(const uint32_t* __restrict__ col, const uint32_
   if (e) atomicOr(err, e);
 }
 
-// Short rows: one thread accumulates its row. Long rows are queued.
-__global__ void k_prefix_short(const uint64_t* __restrict__ off, const uint32_t* __restrict__ w,
-                               uint64_t* __restrict__ P, uint32_t n, uint32_t* rows,
-                               uint32_t* n_rows) {
+// Region size (blocks) of every row, the input of the region-offset scan.
+__global__ void k_region_sizes(const uint64_t* __restrict__ off, uint32_t n, uint32_t tree_min,
+                               uint32_t* __restrict__ flag) {
   for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
        u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t a = off[u], b = off[u + 1];
-    if (b <= a) continue;
-    if (b - a > kShortRow) {
+    const uint64_t d = off[u + 1] - off[u];
+    flag[u] = d <= kMaxDeg ? static_cast<uint32_t>(region_blocks(d, tree_min)) : 0u;
+  }
+}
+
+__device__ __forceinline__ void write_record(uint4* rec, uint64_t u, uint64_t W, uint64_t region,
+                                             uint64_t d) {
+  const uint64_t od = (region << kRegionShift) | d;
+  rec[u] = make_uint4(static_cast<uint32_t>(W), static_cast<uint32_t>(W >> 32),
+                      static_cast<uint32_t>(od), static_cast<uint32_t>(od >> 32));
+}
+
+// Short rows: one thread accumulates its row into its leaf blocks and writes
+// its record. Long rows are queued for a block each.
+__global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
+                               const uint32_t* __restrict__ w, const uint64_t* __restrict__ region,
+                               uint32_t n, uint32_t tree_min, uint64_t cap, Block* __restrict__ blk,
+                               uint4* __restrict__ rec, uint32_t* rows, uint32_t* n_rows,
+                               uint32_t* err) {
+  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
+       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t a = off[u];
+    const uint64_t d = off[u + 1] - a;
+    const uint64_t r0 = region[u];
+    if (d > kMaxDeg) {
+      atomicOr(err, kErrDegree);
+      continue;
+    }
+    if (r0 + region_blocks(d, tree_min) > cap) {
+      atomicOr(err, kErrCapacity);
+      continue;
+    }
+    if (d == 0) {
+      write_record(rec, u, 0, r0, 0);
+      continue;
+    }
+    if (d > kShortRow) {
       rows[atomicAdd(n_rows, 1u)] = static_cast<uint32_t>(u);
       continue;
     }
+    Block* leaves = blk + r0 + tree_nodes(d, tree_min);
     uint64_t acc = 0;
-    for (uint64_t e = a; e < b; ++e) {
-      acc += w[e];
-      P[e] = acc;
+    for (uint64_t j = 0; j < d; ++j) {
+      acc += w[a + j];
+      leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = acc;
+      leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = col[a + j];
     }
+    for (uint64_t j = d; j < leaf_blocks(d) * kLeafEdges; ++j) {
+      leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = ~0ull;
+      leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = 0u;
+    }
+    write_record(rec, u, acc, r0, d);
   }
 }
 
 // Long rows: one block per row, scanning tiles of kThreads*4 weights.
-__global__ void __launch_bounds__(kThreads) k_prefix_long(const uint64_t* __restrict__ off,
+__global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __restrict__ off,
+                                                          const uint32_t* __restrict__ col,
                                                           const uint32_t* __restrict__ w,
-                                                          uint64_t* __restrict__ P,
+                                                          const uint64_t* __restrict__ region,
+                                                          uint32_t tree_min, Block* __restrict__ blk,
+                                                          uint4* __restrict__ rec,
                                                           const uint32_t* rows,
                                                           const uint32_t* n_rows) {
   __shared__ uint64_t lds[kThreads / 64];
   const uint32_t nr = *n_rows;
   for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
     const uint32_t u = rows[r];
-    const uint64_t a = off[u], b = off[u + 1];
+    const uint64_t a = off[u];
+    const uint64_t d = off[u + 1] - a;
+    const uint64_t r0 = region[u];
+    Block* leaves = blk + r0 + tree_nodes(d, tree_min);
     uint64_t carry = 0;
-    for (uint64_t t0 = a; t0 < b; t0 += kThreads * 4) {
-      const uint64_t e0 = t0 + threadIdx.x * 4ull;
+    for (uint64_t t0 = 0; t0 < d; t0 += kThreads * 4) {
+      const uint64_t j0 = t0 + threadIdx.x * 4ull;
       uint64_t v[4];
       uint64_t local = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint64_t e = e0 + k;
-        local += (e < b) ? w[e] : 0u;
+        const uint64_t j = j0 + k;
+        local += (j < d) ? w[a + j] : 0u;
         v[k] = local;
       }
       uint64_t total;
       const uint64_t excl = block_exclusive_scan_u64<kThreads>(local, lds, &total);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint64_t e = e0 + k;
-        if (e < b) P[e] = carry + excl + v[k];
+        const uint64_t j = j0 + k;
+        if (j < d) {
+          leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = carry + excl + v[k];
+          leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = col[a + j];
+          if (j == d - 1) write_record(rec, u, carry + excl + v[k], r0, d);
+        } else if (j < leaf_blocks(d) * kLeafEdges) {
+          leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = ~0ull;
+          leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = 0u;
+        }
       }
       carry += total;
     }
   }
 }
 
-__device__ __forceinline__ bool is_hub(uint64_t deg, uint32_t H) {
-  return deg > H || deg > kMaxPlainDeg;
-}
-
-__global__ void k_hub_flags(const uint64_t* __restrict__ off, uint32_t n, uint32_t H,
-                            uint32_t* flag) {
-  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
-       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    flag[u] = is_hub(off[u + 1] - off[u], H) ? 1u : 0u;
-  }
-}
-
-__global__ void k_hub_chunks(const uint64_t* __restrict__ off, uint32_t n, uint32_t H,
-                             uint32_t chunk_log2, uint32_t* flag) {
-  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
-       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t deg = off[u + 1] - off[u];
-    flag[u] = is_hub(deg, H)
-                  ? static_cast<uint32_t>((deg + (1ull << chunk_log2) - 1) >> chunk_log2)
-                  : 0u;
-  }
-}
-
-// Records, hub entries and top-level tables. hub_id = exclusive scan of hub
-// flags, tl = exclusive scan of chunk counts; capacities guard rebuilds.
-__global__ void k_records(const uint64_t* __restrict__ off, const uint64_t* __restrict__ P,
-                          uint32_t n, uint32_t H, uint32_t chunk_log2,
-                          const uint64_t* __restrict__ hub_id, const uint64_t* __restrict__ tl,
-                          uint32_t hub_cap, uint64_t tl_cap, uint4* __restrict__ rec,
-                          HubEntry* __restrict__ hubs, uint64_t* __restrict__ TL, uint32_t* err) {
-  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
-       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t a = off[u];
-    const uint64_t deg = off[u + 1] - a;
-    uint64_t W = 0;
-    uint32_t code = 0;
-    if (deg > 0) {
-      W = P[a + deg - 1];
-      if (is_hub(deg, H)) {
-        const uint64_t h = hub_id[u];
-        const uint64_t nch = (deg + (1ull << chunk_log2) - 1) >> chunk_log2;
-        const uint64_t t0 = tl[u];
-        if (h >= hub_cap || h >= kMaxHubs || t0 + nch > tl_cap) {
-          atomicOr(err, kErrHubs);
-          continue;
-        }
-        code = kHubFlag | static_cast<uint32_t>(h);
-        hubs[h] = HubEntry{static_cast<uint32_t>(deg), static_cast<uint32_t>(nch), t0};
-        for (uint64_t c = 0; c < nch; ++c) {
-          uint64_t last = ((c + 1) << chunk_log2) - 1;
-          if (last > deg - 1) last = deg - 1;
-          TL[t0 + c] = P[a + last];
-        }
-      } else {
-        code = static_cast<uint32_t>(deg);
-      }
+// Node `b` of level `l` of the tree of a row: 16 keys read from its leaves.
+__device__ __forceinline__ void tree_node(const Block* __restrict__ leaves, uint64_t d, uint32_t l,
+                                          uint64_t b, Block* __restrict__ dst) {
+  const uint32_t sh = 3 + 4 * (l - 1);  // edges covered by one key of level l: 8 * 16^(l-1)
+  const uint64_t nkeys = (d + (1ull << sh) - 1) >> sh;
+#pragma unroll
+  for (uint32_t t = 0; t < kNodeKeys; ++t) {
+    const uint64_t k = b * kNodeKeys + t;
+    uint64_t v = ~0ull;
+    if (k < nkeys) {
+      uint64_t last = (k + 1) << sh;
+      if (last > d) last = d;
+      v = leaves[(last - 1) / kLeafEdges].lf.p[(last - 1) % kLeafEdges];
     }
-    const uint64_t od = (a << kCodeBits) | code;
-    rec[u] = make_uint4(static_cast<uint32_t>(W), static_cast<uint32_t>(W >> 32),
-                        static_cast<uint32_t>(od), static_cast<uint32_t>(od >> 32));
+    dst->key[t] = v;
+  }
+}
+
+// Rows with a tree: short trees by one thread, large ones queued for a block.
+__global__ void k_tree_short(const uint64_t* __restrict__ off, const uint64_t* __restrict__ region,
+                             uint32_t n, uint32_t tree_min, Block* __restrict__ blk,
+                             uint32_t* rows, uint32_t* n_rows, uint32_t* n_tree_rows) {
+  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
+       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t d = off[u + 1] - off[u];
+    if (d <= tree_min || d > kMaxDeg) continue;
+    atomicAdd(n_tree_rows, 1u);
+    const uint64_t nodes = tree_nodes(d, tree_min);
+    if (nodes > 16) {
+      rows[atomicAdd(n_rows, 1u)] = static_cast<uint32_t>(u);
+      continue;
+    }
+    Block* dst = blk + region[u];
+    const Block* leaves = dst + nodes;
+    for (uint32_t l = tree_levels(d); l >= 1; --l) {
+      const uint64_t nl = tree_level_nodes(d, l);
+      for (uint64_t b = 0; b < nl; ++b) tree_node(leaves, d, l, b, dst + b);
+      dst += nl;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_tree_long(const uint64_t* __restrict__ off,
+                                                        const uint64_t* __restrict__ region,
+                                                        uint32_t tree_min, Block* __restrict__ blk,
+                                                        const uint32_t* rows,
+                                                        const uint32_t* n_rows) {
+  const uint32_t nr = *n_rows;
+  for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
+    const uint32_t u = rows[r];
+    const uint64_t d = off[u + 1] - off[u];
+    const uint64_t nodes = tree_nodes(d, tree_min);
+    Block* dst = blk + region[u];
+    const Block* leaves = dst + nodes;
+    for (uint32_t l = tree_levels(d); l >= 1; --l) {
+      const uint64_t nl = tree_level_nodes(d, l);
+      for (uint64_t b = threadIdx.x; b < nl; b += kThreads) tree_node(leaves, d, l, b, dst + b);
+      dst += nl;
+    }
   }
 }
 
@@ -242,34 +296,31 @@ hipError_t launch_validate(const fppr_graph* g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_row_prefix(fppr_graph* g, hipStream_t s) {
-  if (g->m == 0) return hipSuccess;
-  uint32_t* n_rows = g->d_err + 1;
-  hipLaunchKernelGGL(k_prefix_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->w,
-                     g->P, g->n, g->rows, n_rows);
-  hipLaunchKernelGGL(k_prefix_long, dim3(2048), dim3(kThreads), 0, s, g->off, g->w, g->P, g->rows,
-                     n_rows);
-  return hipGetLastError();
-}
-
-hipError_t launch_hub_flags(fppr_graph* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_hub_flags, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->n, g->H,
-                     g->flag);
-  return launch_scan_u32(g->flag, g->scan, g->n, g->scan_blocks,
+hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_region_sizes, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->n,
+                     g->tree_min, g->flag);
+  return launch_scan_u32(g->flag, g->region, g->n, g->scan_blocks,
                          reinterpret_cast<uint64_t*>(g->d_err + 2), s);
 }
 
-hipError_t launch_hub_chunks(fppr_graph* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_hub_chunks, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->n, g->H,
-                     g->chunk_log2, g->flag);
-  return launch_scan_u32(g->flag, g->scan2, g->n, g->scan_blocks,
-                         reinterpret_cast<uint64_t*>(g->d_err + 4), s);
+hipError_t launch_leaves(fppr_graph* g, hipStream_t s) {
+  uint32_t* n_long = g->d_err + 1;
+  hipLaunchKernelGGL(k_leaves_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->col,
+                     g->w, g->region, g->n, g->tree_min, g->n_blocks, g->blocks, g->rec, g->rows,
+                     n_long, g->d_err);
+  hipLaunchKernelGGL(k_leaves_long, dim3(2048), dim3(kThreads), 0, s, g->off, g->col, g->w,
+                     g->region, g->tree_min, g->blocks, g->rec, g->rows, n_long);
+  return hipGetLastError();
 }
 
-hipError_t launch_records(fppr_graph* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_records, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->P, g->n,
-                     g->H, g->chunk_log2, g->scan, g->scan2, g->n_hub, g->n_tl, g->rec, g->hubs,
-                     g->TL, g->d_err);
+hipError_t launch_trees(fppr_graph* g, hipStream_t s) {
+  if (g->m == 0 || g->tree_min == 0xFFFFFFFFu) return hipSuccess;
+  uint32_t* n_long = g->d_err + 8;
+  uint32_t* n_tree = g->d_err + 9;
+  hipLaunchKernelGGL(k_tree_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->region,
+                     g->n, g->tree_min, g->blocks, g->rows, n_long, n_tree);
+  hipLaunchKernelGGL(k_tree_long, dim3(1024), dim3(kThreads), 0, s, g->off, g->region,
+                     g->tree_min, g->blocks, g->rows, n_long);
   return hipGetLastError();
 }
 

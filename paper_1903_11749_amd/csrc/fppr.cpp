@@ -51,13 +51,11 @@ void free_graph(fppr_graph* g) {
     dfree(g->col);
     dfree(g->w);
   }
-  dfree(g->P);
   dfree(g->rec);
-  dfree(g->hubs);
-  dfree(g->TL);
+  dfree(g->blocks);
+  dfree(g->region);
   dfree(g->flag);
   dfree(g->scan);
-  dfree(g->scan2);
   dfree(g->rows);
   dfree(g->scan_blocks);
   dfree(g->d_err);
@@ -73,8 +71,7 @@ std::string err_bits(uint32_t e) {
   if (e & kErrOffsets) s += " row_offsets not monotone / off[0] != 0 / off[n] != m;";
   if (e & kErrCol) s += " col >= n;";
   if (e & kErrWeight) s += " weight == 0;";
-  if (e & kErrHubs) s += " too many hubs or hub table overflow;";
-  if (e & kErrDegree) s += " a row has 2^32 or more edges;";
+  if (e & kErrDegree) s += " a row has 2^27 or more edges;";
   if (e & kErrCapacity) s += " pool table overflow (graph changed shape);";
   return s;
 }
@@ -88,22 +85,22 @@ fppr_status invalid(const std::string& msg) {
 struct Ctl {
   uint32_t err;
   uint32_t n_rows;
-  uint64_t hubs;
-  uint64_t tl;
+  uint64_t blocks;
   uint64_t small;
+  uint32_t n_tree;
 };
 
 hipError_t read_ctl(const fppr_graph* g, hipStream_t s, Ctl* c) {
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  uint32_t raw[8];
+  uint32_t raw[16];
   e = hipMemcpy(raw, g->d_err, sizeof raw, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return e;
   c->err = raw[0];
   c->n_rows = raw[1];
-  std::memcpy(&c->hubs, raw + 2, 8);
-  std::memcpy(&c->tl, raw + 4, 8);
+  std::memcpy(&c->blocks, raw + 2, 8);
   std::memcpy(&c->small, raw + 6, 8);
+  c->n_tree = raw[9];
   return hipSuccess;
 }
 
@@ -111,13 +108,14 @@ hipError_t zero_ctl(fppr_graph* g, hipStream_t s) {
   return launch_zero_u64(reinterpret_cast<uint64_t*>(g->d_err), 8, s);
 }
 
-// prefixes, hub scans, records (no host sync); caps must already be sized
+// region offsets, leaf blocks + records, prefix trees (no host sync; the
+// region scan reproduces the block count of the first build when row_offsets
+// are unchanged, and the kernels refuse to write past it otherwise)
 hipError_t derive(fppr_graph* g, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_row_prefix(g, s)) != hipSuccess) return e;
-  if ((e = launch_hub_flags(g, s)) != hipSuccess) return e;
-  if ((e = launch_hub_chunks(g, s)) != hipSuccess) return e;
-  return launch_records(g, s);
+  if ((e = launch_region_sizes(g, s)) != hipSuccess) return e;
+  if ((e = launch_leaves(g, s)) != hipSuccess) return e;
+  return launch_trees(g, s);
 }
 
 uint32_t log2_exact(uint32_t v) {
@@ -166,24 +164,19 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   *out = nullptr;
   if (!csr) return invalid("csr is NULL");
   if (csr->n == 0 || csr->n > 0xFFFFFFFEu) return invalid("n must be in [1, 2^32-2]");
-  if (csr->m >= (1ull << 40)) return invalid("m must be below 2^40");
+  if (csr->m >= kMaxEdges) return invalid("m must be below 2^36");
   if (!csr->row_offsets) return invalid("row_offsets is NULL");
   if (csr->m && (!csr->col || !csr->w)) return invalid("col or w is NULL");
   if (csr->mem != FPPR_MEM_HOST && csr->mem != FPPR_MEM_DEVICE) return invalid("mem must be HOST or DEVICE");
-  uint32_t H = 4096, C = 4096;
-  if (opts) {
-    if (opts->hub_threshold) H = opts->hub_threshold;
-    if (opts->chunk) C = opts->chunk;
-  }
-  if (!is_pow2(C) || C < 64 || C > (1u << 20)) return invalid("chunk must be a power of two in [64, 2^20]");
+  uint32_t H = kLeafEdges;
+  if (opts && opts->hub_threshold) H = opts->hub_threshold;
+  if (H < kLeafEdges) H = kLeafEdges;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   fppr_graph* g = new fppr_graph();
   g->n = csr->n;
   g->m = csr->m;
-  g->H = H;
-  g->chunk = C;
-  g->chunk_log2 = log2_exact(C);
+  g->tree_min = H;
   hipError_t e = hipGetDevice(&g->device);
   if (e != hipSuccess) {
     delete g;
@@ -221,11 +214,10 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     g->col = csr->col;
     g->w = csr->w;
   }
-  FPPR_TRY(dmalloc(&g->P, m, acc), "hipMalloc(P)");
   FPPR_TRY(dmalloc(&g->rec, n, acc), "hipMalloc(rec)");
+  FPPR_TRY(dmalloc(&g->region, n, acc), "hipMalloc(region)");
   FPPR_TRY(dmalloc(&g->flag, n, acc), "hipMalloc(flag)");
   FPPR_TRY(dmalloc(&g->scan, n, acc), "hipMalloc(scan)");
-  FPPR_TRY(dmalloc(&g->scan2, n, acc), "hipMalloc(scan2)");
   FPPR_TRY(dmalloc(&g->rows, n, acc), "hipMalloc(rows)");
   FPPR_TRY(dmalloc(&g->scan_blocks, scan_block_count(n) + 1, acc), "hipMalloc(scan blocks)");
   FPPR_TRY(dmalloc(&g->d_err, 16, acc), "hipMalloc(ctl)");
@@ -239,26 +231,20 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     free_graph(g);
     return invalid(msg);
   }
-  FPPR_TRY(launch_row_prefix(g, s), "row prefix");
-  FPPR_TRY(launch_hub_flags(g, s), "hub flags");
-  FPPR_TRY(launch_hub_chunks(g, s), "hub chunks");
-  FPPR_TRY(read_ctl(g, s, &c), "read hub counts");
-  if (c.hubs >= kMaxHubs) {
-    free_graph(g);
-    return invalid("too many hub rows (raise hub_threshold)");
-  }
-  g->n_hub = static_cast<uint32_t>(c.hubs);
-  g->n_tl = c.tl;
-  FPPR_TRY(dmalloc(&g->hubs, g->n_hub, acc), "hipMalloc(hubs)");
-  FPPR_TRY(dmalloc(&g->TL, g->n_tl, acc), "hipMalloc(TL)");
-  FPPR_TRY(launch_records(g, s), "records");
-  FPPR_TRY(read_ctl(g, s, &c), "read records status");
+  FPPR_TRY(launch_region_sizes(g, s), "region sizes");
+  FPPR_TRY(read_ctl(g, s, &c), "read region sizes");
+  g->n_blocks = c.blocks;
+  FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
+  FPPR_TRY(launch_leaves(g, s), "leaf blocks");
+  FPPR_TRY(launch_trees(g, s), "prefix trees");
+  FPPR_TRY(read_ctl(g, s, &c), "read build status");
   if (c.err) {
     std::string msg = "graph build failed:" + err_bits(c.err);
     free_graph(g);
     return invalid(msg);
   }
 #undef FPPR_TRY
+  g->n_tree = c.n_tree;
   *out = g;
   return FPPR_OK;
 }
@@ -275,7 +261,7 @@ FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t*
   if (!g) return invalid("graph is NULL");
   if (n) *n = g->n;
   if (m) *m = g->m;
-  if (n_hubs) *n_hubs = g->n_hub;
+  if (n_hubs) *n_hubs = g->n_tree;
   if (n_small) *n_small = g->has_pool ? g->n_small : 0;
   if (device_bytes) *device_bytes = g->device_bytes;
   return FPPR_OK;

@@ -1,5 +1,6 @@
 // Device building blocks shared by the kernels of this library: the
-// counter-based generator, the integer weighted pick and wave helpers.
+// counter-based generator, the node record format, the integer weighted pick
+// and wave helpers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,27 +8,79 @@
 namespace fppr {
 
 // ---------------------------------------------------------------------------
-// Node records (16 bytes, one per node, read with one 128-bit load):
-//   x,y  : low/high words of the row's total weight W (plain record), or of
-//          the pool base index (stitched record of a small node)
-//   z,w  : low/high words of  (row offset << 24) | code
-// code: 0 -> no out-edges; 1..0x7FFFFF -> out-degree; 0x800000 | h -> hub h;
-//       0xFFFFFF -> small node served by the pool (stitched table only).
+// Node record: 16 bytes, one per node, read with one 128-bit load.
+//   word 0 (64 bit): total weight W of the row (plain record), or the first
+//                    pool entry of the node (stitched record of a small node)
+//   word 1 (64 bit): (first block of the row's region << 28) | flags
+// flags: bits 0..26 out-degree, bit 27 = small node served by the pool.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kCodeBits = 24;
-constexpr uint32_t kCodeMask = 0xFFFFFFu;
-constexpr uint32_t kHubFlag = 0x800000u;
-constexpr uint32_t kMaxPlainDeg = 0x7FFFFFu;
-constexpr uint32_t kMaxHubs = 0x7FFFFFu;   // hub ids 0 .. kMaxHubs-1
-constexpr uint32_t kPoolCode = 0xFFFFFFu;
+constexpr uint32_t kRegionShift = 28;
+constexpr uint64_t kDegMask = (1u << 27) - 1;
+constexpr uint64_t kPoolFlag = 1u << 27;
+constexpr uint64_t kMaxDeg = kDegMask;           // rows up to 2^27 - 1 edges
+constexpr uint64_t kMaxEdges = 1ull << 36;
 constexpr uint32_t kMoveCap = 65536u;
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
-struct HubEntry {  // 16 bytes
-  uint32_t deg;
-  uint32_t nchunks;
-  uint64_t tl_off;  // first entry of this hub in the top-level table
+// ---------------------------------------------------------------------------
+// Row regions. Every row owns a run of 128-byte blocks (one memory line):
+//   [prefix-tree nodes, top level first][leaf blocks]
+// Leaf block b holds edges 8b .. 8b+7 of the row: their inclusive weight
+// prefixes P (8 x u64) and destination ids (8 x u32); slots past the row's
+// end hold P = ~0. A pick that knows its leaf block reads one line.
+// Prefix tree (integer form of the alias tree, Sec. 4.1 and Algorithm 3: the
+// row is cut into groups whose total weights form the next level,
+// recursively, and a pick walks from the root down to one group): rows with
+// more than the tree threshold of edges carry it. Level 1 has one key per
+// leaf block, level l one key per 16 nodes of level l-1; key k of level l is
+// P[min((k+1) * 8 * 16^(l-1), d) - 1]. A node is 16 keys (128 bytes; unused
+// keys ~0); the top level L is the first with at most 16 keys. Taking the
+// first key > X at every level and then the first prefix > X in the leaf
+// returns exactly the edge a flat search over P returns.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kLeafEdges = 8;
+constexpr uint32_t kNodeKeys = 16;
+
+struct LeafBlock {
+  uint64_t p[kLeafEdges];  // inclusive prefixes (~0 past the row's end)
+  uint32_t c[kLeafEdges];  // destination ids
+  uint32_t pad[kLeafEdges];
 };
+union alignas(128) Block {
+  uint64_t key[kNodeKeys];  // tree node
+  LeafBlock lf;             // leaf block
+};
+static_assert(sizeof(Block) == 128, "one memory line per block");
+
+__host__ __device__ __forceinline__ uint64_t leaf_blocks(uint64_t d) {
+  return (d + kLeafEdges - 1) / kLeafEdges;
+}
+// levels of the tree of a row with d edges (d > 8)
+__host__ __device__ __forceinline__ uint32_t tree_levels(uint64_t d) {
+  uint32_t L = 1;
+  uint64_t span = kLeafEdges * kNodeKeys;  // edges covered by one level-L node
+  while (d > span) {
+    ++L;
+    span *= kNodeKeys;
+  }
+  return L;
+}
+// nodes of level l >= 1: ceil(d / (8 * 16^l))
+__host__ __device__ __forceinline__ uint64_t tree_level_nodes(uint64_t d, uint32_t l) {
+  const uint32_t sh = 3 + 4 * l;
+  return (d + (1ull << sh) - 1) >> sh;
+}
+// tree nodes of a row (0 when it has no tree)
+__host__ __device__ __forceinline__ uint64_t tree_nodes(uint64_t d, uint32_t tree_min) {
+  if (d <= tree_min) return 0;
+  const uint32_t L = tree_levels(d);
+  uint64_t t = 0;
+  for (uint32_t l = 1; l <= L; ++l) t += tree_level_nodes(d, l);
+  return t;
+}
+__host__ __device__ __forceinline__ uint64_t region_blocks(uint64_t d, uint32_t tree_min) {
+  return d ? tree_nodes(d, tree_min) + leaf_blocks(d) : 0;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds, key bumped by
@@ -41,16 +94,15 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
                                        uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // 32x32 -> 64-bit products: one v_mad_u64_u32 each
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = static_cast<uint32_t>(p1);
     c2 = n2;
-    c3 = lo0;
+    c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -62,45 +114,50 @@ __device__ __forceinline__ uint64_t scaled_draw(uint32_t x0, uint32_t x1, uint64
   return __umul64hi((static_cast<uint64_t>(x1) << 32) | x0, W);
 }
 
-// First index j in [lo, hi] of P with P[j] > X, given P[hi] > X.
-__device__ __forceinline__ uint64_t upper_bound(const uint64_t* __restrict__ P, uint64_t lo,
-                                                uint64_t hi, uint64_t X) {
-  while (lo < hi) {
-    const uint64_t mid = lo + ((hi - lo) >> 1);
-    if (P[mid] > X) hi = mid; else lo = mid + 1;
-  }
-  return lo;
-}
-
 struct GraphView {
-  const uint4* __restrict__ rec;       // plain records
-  const uint64_t* __restrict__ P;      // inclusive row prefixes
-  const uint32_t* __restrict__ col;
-  const HubEntry* __restrict__ hubs;
-  const uint64_t* __restrict__ TL;     // hub top-level tables
-  uint32_t chunk_log2;
+  const uint4* __restrict__ rec;     // plain records
+  const Block* __restrict__ blocks;  // row regions
+  uint32_t tree_min;                 // rows with deg > tree_min (>= 8) have a tree
 };
-
-// Edge index (global, into col) chosen by draw X at a node with record
-// fields (off, code), code != 0 and code != kPoolCode.
-__device__ __forceinline__ uint64_t pick_edge(const GraphView& g, uint64_t off, uint32_t code,
-                                              uint64_t X) {
-  if (code & kHubFlag) {
-    const HubEntry h = g.hubs[code & ~kHubFlag];
-    const uint64_t c = upper_bound(g.TL + h.tl_off, 0, h.nchunks - 1, X);
-    const uint64_t lo = c << g.chunk_log2;
-    uint64_t hi = lo + (1ull << g.chunk_log2) - 1;
-    if (hi > h.deg - 1) hi = h.deg - 1;
-    return off + upper_bound(g.P + off, lo, hi, X);
-  }
-  return off + upper_bound(g.P + off, 0, code - 1, X);
-}
 
 __device__ __forceinline__ uint64_t rec_w(uint4 r) {
   return (static_cast<uint64_t>(r.y) << 32) | r.x;
 }
 __device__ __forceinline__ uint64_t rec_od(uint4 r) {
   return (static_cast<uint64_t>(r.w) << 32) | r.z;
+}
+
+// Destination of the first edge whose prefix exceeds X (P[deg-1] = W > X),
+// with ordinary dependent loads: tree descent or a binary search over the
+// leaf blocks' last prefixes, then one leaf block.
+__device__ __forceinline__ uint32_t pick_blocking(const GraphView& g, uint64_t region, uint32_t deg,
+                                                  uint64_t X) {
+  uint64_t leaf;
+  if (deg > g.tree_min) {
+    const uint32_t L = tree_levels(deg);
+    uint64_t base = 0, b = 0;
+    for (uint32_t l = L; l >= 1; --l) {
+      const Block& nd = g.blocks[region + base + b];
+      uint32_t cnt = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kNodeKeys; ++k) cnt += (nd.key[k] <= X) ? 1u : 0u;
+      base += tree_level_nodes(deg, l);
+      b = b * kNodeKeys + cnt;
+    }
+    leaf = region + base + b;
+  } else {
+    uint64_t lo = 0, hi = leaf_blocks(deg) - 1;
+    while (lo < hi) {
+      const uint64_t mid = lo + ((hi - lo) >> 1);
+      if (g.blocks[region + mid].lf.p[kLeafEdges - 1] > X) hi = mid; else lo = mid + 1;
+    }
+    leaf = region + lo;
+  }
+  const LeafBlock& lb = g.blocks[leaf].lf;
+  uint32_t j = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kLeafEdges; ++k) j += (lb.p[k] <= X) ? 1u : 0u;
+  return lb.c[j];
 }
 
 __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t d) {
@@ -118,10 +175,9 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   return k;
 }
 __device__ __forceinline__ uint64_t digest_term(uint32_t s, uint32_t t, uint32_t c) {
-  return fmix64(fmix64((static_cast<uint64_t>(s) << 32) | t) ^ (static_cast<uint64_t>(c) * 0x9E3779B97F4A7C15ull));
+  return fmix64(fmix64((static_cast<uint64_t>(s) << 32) | t) ^
+                (static_cast<uint64_t>(c) * 0x9E3779B97F4A7C15ull));
 }
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // rank of this lane among the lanes set in mask (lanes below it)
 __device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {

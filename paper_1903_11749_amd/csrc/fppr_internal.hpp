@@ -16,14 +16,8 @@ enum : uint32_t {
   kErrOffsets = 1u,
   kErrCol = 2u,
   kErrWeight = 4u,
-  kErrHubs = 8u,
   kErrDegree = 16u,
   kErrCapacity = 32u,
-};
-
-struct DeviceBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
 };
 
 }  // namespace fppr
@@ -38,20 +32,18 @@ struct fppr_graph {
   const uint32_t* w = nullptr;
   bool owns_csr = false;
   // derived arrays
-  uint64_t* P = nullptr;            // [m]
-  uint4* rec = nullptr;             // [n]
-  uint32_t H = 4096, chunk = 4096, chunk_log2 = 12;
-  uint32_t n_hub = 0;
-  uint64_t n_tl = 0;
-  fppr::HubEntry* hubs = nullptr;   // [n_hub]
-  uint64_t* TL = nullptr;           // [n_tl]
+  uint4* rec = nullptr;             // [n] node records
+  fppr::Block* blocks = nullptr;    // [n_blocks] row regions: tree nodes, leaf blocks
+  uint64_t n_blocks = 0;
+  uint64_t* region = nullptr;       // [n] first block of each row's region
+  uint32_t tree_min = 8;            // rows with more edges carry a prefix tree
+  uint32_t n_tree = 0;              // rows with a tree
   // scratch (kept for rebuilds)
   uint32_t* flag = nullptr;         // [n]   per-node u32 input of scans
   uint64_t* scan = nullptr;         // [n]   exclusive scan output
-  uint64_t* scan2 = nullptr;        // [n]
   uint32_t* rows = nullptr;         // [n]   list of long rows
   uint64_t* scan_blocks = nullptr;  // block sums of the scans
-  uint32_t* d_err = nullptr;        // [4]   error bits, counters
+  uint32_t* d_err = nullptr;        // [16]  error bits and counters
   // pool
   bool has_pool = false;
   fppr_pool_opts pool_opts{};
@@ -72,11 +64,11 @@ fppr_status hip_fail(hipError_t e, const char* what);
 
 // build.hip
 hipError_t launch_validate(const fppr_graph* g, hipStream_t s);
-hipError_t launch_row_prefix(fppr_graph* g, hipStream_t s);
-// flag[u] = 1 for hub rows, scan -> hub ids; flag[u] = nchunks, scan2 -> TL offsets
-hipError_t launch_hub_flags(fppr_graph* g, hipStream_t s);
-hipError_t launch_hub_chunks(fppr_graph* g, hipStream_t s);
-hipError_t launch_records(fppr_graph* g, hipStream_t s);
+// region sizes + scan -> g->region, total blocks at d_err[2..3]
+hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s);
+// prefixes and destinations into leaf blocks, node records
+hipError_t launch_leaves(fppr_graph* g, hipStream_t s);
+hipError_t launch_trees(fppr_graph* g, hipStream_t s);
 // exclusive scan of u32 input to u64 output; writes the total to *total_dev
 hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* blocks,
                            uint64_t* total_dev, hipStream_t s);
@@ -89,7 +81,7 @@ hipError_t launch_pool(fppr_graph* g, hipStream_t s);
 
 // walk.hip
 struct WalkLaunch {
-  const uint4* rec;
+  const uint4* rec;  // plain or stitched record table
   const uint32_t* sources;
   uint64_t n_src;
   uint32_t R;

@@ -50,7 +50,7 @@ __global__ void k_small_compact(const uint32_t* __restrict__ flag,
       } else {
         small_nodes[k] = static_cast<uint32_t>(u);
         const uint64_t base = k << K_log2;
-        const uint64_t od = (rec_od(r) & ~static_cast<uint64_t>(kCodeMask)) | kPoolCode;
+        const uint64_t od = rec_od(r) | kPoolFlag;
         r = make_uint4(static_cast<uint32_t>(base), static_cast<uint32_t>(base >> 32),
                        static_cast<uint32_t>(od), static_cast<uint32_t>(od >> 32));
       }
@@ -73,11 +73,11 @@ __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* 
     for (uint32_t t = 0; t < L; ++t) {
       const uint4 r = g.rec[cur];
       const uint64_t od = rec_od(r);
-      const uint32_t code = static_cast<uint32_t>(od) & kCodeMask;
-      if (code == 0) break;  // arrived at a node without out-edges: stays active
+      const uint32_t deg = static_cast<uint32_t>(od & kDegMask);
+      if (deg == 0) break;  // arrived at a node without out-edges: stays active
       const U4 x = philox10(j, t, v, 1u, key0, key1);
       const uint64_t X = scaled_draw(x.x0, x.x1, rec_w(r));
-      cur = g.col[pick_edge(g, od >> kCodeBits, code, X)];
+      cur = pick_blocking(g, od >> kRegionShift, deg, X);
       steps += 1;
       if (x.x2 < T) {
         mark = 1;
@@ -107,7 +107,7 @@ hipError_t launch_small_compact(fppr_graph* g, uint32_t /*S*/, hipStream_t s) {
 hipError_t launch_pool(fppr_graph* g, hipStream_t s) {
   const uint64_t total = g->n_small << g->K_log2;
   if (total == 0) return hipSuccess;
-  GraphView gv{g->rec, g->P, g->col, g->hubs, g->TL, g->chunk_log2};
+  GraphView gv{g->rec, g->blocks, g->tree_min};
   const uint64_t seed = g->pool_opts.seed;
   hipLaunchKernelGGL(k_pool, dim3(grid_for(total)), dim3(kThreads), 0, s, gv, g->small_nodes,
                      g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,

@@ -5,13 +5,19 @@
 // (parallel pipelines, Fig. 2, Sec. 4.3). On the GPU the same effect comes
 // without rounds: a persistent grid of 64-lane waves, one walk per lane in
 // registers; a lane whose walk terminated takes the next walk id at once
-// (ballot + mbcnt over the idle lanes, one atomic per wave per chunk of
-// ids), so the number of walks in flight stays at the lane count.
+// (ballot + mbcnt over the idle lanes, one atomic per wave per chunk of ids).
+//
+// Each lane runs its walk as a small state machine that needs exactly one
+// dependent load per loop iteration (node record, one 128-byte tree node, one
+// 128-byte leaf block of prefixes and destinations, or one pool entry). Lanes therefore
+// advance independently: an iteration costs one memory latency, not the
+// longest move in the wave. The head's record stays in registers, so the
+// restart from a node without out-edges (Sec. 2.1) costs no load at all.
 //
 // One move (integer only):
 //   x = Philox4x32-10(key = seed, counter = (i, m, s, 0))
-//   node without out-edges: tail = s (restart from the head, Sec. 2.1)
-//   small node (stitched runs): take pool entry floor(x0 * K / 2^32)
+//   node without out-edges: tail = s
+//   small node (stitched runs): pool entry floor(x0 * K / 2^32) of the node
 //   otherwise: X = floor((x1:x0) * W / 2^64), first edge with prefix > X
 //   stop iff x2 < T (or the stitched entry is terminated), or m hits the cap
 #include "fppr_internal.hpp"
@@ -21,7 +27,19 @@ namespace fppr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint64_t kChunk = 256;  // walk ids claimed per wave at a time
+constexpr uint64_t kChunk = 256;          // walk ids claimed per wave at a time
+constexpr uint32_t kInlineRestarts = 8;   // restarts handled per iteration
+
+enum : uint32_t {
+  kIdle = 0,
+  kSrcRec = 1,  // load the head's record (kept in registers)
+  kRec = 2,     // load the tail's record
+  kTree = 3,    // load one prefix-tree node (128 bytes)
+  kBsearch = 4, // load one leaf block's last prefix (rows without a tree, > 8 edges)
+  kLeaf = 5,    // load one leaf block: 8 prefixes and their destinations
+  kPool = 6,    // load one pool entry
+  kCont = 7,    // no load: continue restarts at the head
+};
 
 struct WalkArgs {
   GraphView g;
@@ -39,25 +57,67 @@ struct WalkArgs {
   fppr_stats* stats;
 };
 
+struct Lane {
+  // walk
+  uint64_t g;
+  uint32_t s, i, m, len, tail;
+  // head record
+  uint64_t sW, s_od;
+  // current move
+  uint32_t ph;
+  uint64_t X;     // draw, or the pool entry index
+  uint64_t off;   // first block of the row's region
+  uint32_t deg, x2;
+  // search state (blocks relative to the region): tree descent (lvl; lo =
+  // node within the level, hi = first node of the level) or candidate leaf
+  // blocks [lo, hi]; a leaf load reads block hi + lo
+  uint32_t lvl;
+  uint32_t lo;
+  uint32_t hi;
+  // statistics (restart moves = moves - picks - stitched; walks counted per
+  // wave); 32-bit per lane, flushed to the global counters before overflow
+  uint32_t st_moves, st_steps, st_plain, st_stitch, st_log;
+};
+
+// Orders this wave's LDS writes before its later LDS reads (the wave's own
+// lanes only; no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over each aligned group of 8 lanes, in every lane of the group (DPP:
+// swap neighbours, swap pairs, then mirror the two quads of the half-row).
+__device__ __forceinline__ uint32_t sum8(uint32_t x) {
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x4E, 0xF, 0xF, false));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x141, 0xF, 0xF, false));
+  return x;
+}
+
 template <bool kStitch, bool kStats>
 __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
+  __shared__ uint64_t sh_blk[kThreads / 64][64];
+  __shared__ uint64_t sh_x[kThreads / 64][64];
+  __shared__ uint32_t sh_res[kThreads / 64][64];
   const uint32_t lane = __lane_id();
-  bool active = false;
-  uint64_t g = 0;
-  uint32_t s = 0, i = 0, m = 0, tail = 0, len = 0;
-  uint64_t cur = 0, end = 0;  // wave-uniform chunk of walk ids
+  const uint32_t wv = threadIdx.x / 64;
+  Lane L{};
+  L.ph = kIdle;
+  uint64_t cur = 0, end = 0;  // wave-uniform chunk of walk ids (scalar registers)
   bool exhausted = false;
-  uint64_t st_moves = 0, st_steps = 0;
-  uint32_t st_walks = 0, st_capped = 0, st_dang = 0, st_plain = 0, st_stitch = 0, st_log = 0;
+  uint64_t walks = 0;         // walks started by this wave
 
   for (;;) {
     // ---- refill idle lanes from the wave's chunk of walk ids ----
-    uint64_t idle = __ballot(!active);
+    uint64_t idle = __ballot(L.ph == kIdle);
     while (idle != 0 && !exhausted) {
       if (cur >= end) {
         unsigned long long c = 0;
         if (lane == 0) c = atomicAdd(a.work_counter, static_cast<unsigned long long>(kChunk));
-        c = __shfl(c, 0, 64);
+        c = static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(c))) |
+            (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(c >> 32))) << 32);
         if (c >= a.total) {
           exhausted = true;
           break;
@@ -68,91 +128,238 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
       const uint64_t avail = end - cur;
       const uint32_t nidle = static_cast<uint32_t>(__popcll(idle));
       const uint32_t take = avail < nidle ? static_cast<uint32_t>(avail) : nidle;
-      if (!active) {
+      if (L.ph == kIdle) {
         const uint32_t r = mask_rank(idle);
         if (r < take) {
-          g = cur + r;
-          uint64_t q = __umul64hi(g, a.R_magic);
-          uint64_t rem = g - q * a.R;
+          L.g = cur + r;
+          uint64_t q = __umul64hi(L.g, a.R_magic);
+          uint64_t rem = L.g - q * a.R;
           if (rem >= a.R) {
             q += 1;
             rem -= a.R;
           }
-          s = a.sources ? a.sources[q] : static_cast<uint32_t>(q);
-          i = static_cast<uint32_t>(rem);
-          tail = s;
-          m = 0;
-          len = 0;
-          active = true;
-          if (s >= a.n) {  // invalid source: no walk, recorded for the caller
-            a.endpoints[g] = kNoNode;
+          L.s = a.sources ? a.sources[q] : static_cast<uint32_t>(q);
+          L.i = static_cast<uint32_t>(rem);
+          L.tail = L.s;
+          L.m = 0;
+          L.len = 0;
+          L.ph = kSrcRec;
+          if (L.s >= a.n) {  // invalid source: no walk, recorded for the caller
+            a.endpoints[L.g] = kNoNode;
             atomicOr(a.work_counter + 1, 1ull);
-            active = false;
+            if (kStats) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->walks), ~0ull);
+            L.ph = kIdle;
           }
         }
       }
       cur += take;
-      idle = __ballot(!active);
+      walks += take;
+      idle = __ballot(L.ph == kIdle);
     }
-    if (__ballot(active) == 0) break;
+    if (__ballot(L.ph != kIdle) == 0) break;
 
-    // ---- one move ----
-    if (active) {
-      const U4 x = philox10(i, m, s, 0u, a.key0, a.key1);
-      const uint4 r = a.rec[tail];
-      const uint64_t od = rec_od(r);
-      const uint32_t code = static_cast<uint32_t>(od) & kCodeMask;
-      bool stop;
-      if (code == 0) {
-        tail = s;
-        len += 1;
-        stop = x.x2 < a.T;
-        if (kStats) ++st_dang;
-      } else if (kStitch && code == kPoolCode) {
-        const uint64_t slot = (static_cast<uint64_t>(x.x0) << a.K_log2) >> 32;
-        const uint64_t e = a.pool[rec_w(r) + slot];
-        tail = static_cast<uint32_t>(e);
-        len += static_cast<uint32_t>(e >> 32) & 0xFFFFu;
-        stop = ((e >> 48) & 1u) != 0;
-        if (kStats) ++st_stitch;
-      } else {
-        const uint64_t X = scaled_draw(x.x0, x.x1, rec_w(r));
-        const uint64_t e = pick_edge(a.g, od >> kCodeBits, code, X);
-        tail = a.g.col[e];
-        len += 1;
-        stop = x.x2 < a.T;
-        if (kStats) {
-          ++st_plain;
-          const uint32_t deg = (code & kHubFlag) ? a.g.hubs[code & ~kHubFlag].deg : code;
-          st_log += ceil_log2_u32(deg);
+    // ---- this iteration's loads ----
+    // Records, pool entries and probes are one small load per lane. Tree nodes
+    // and leaf blocks are whole 128-byte lines: lanes load them cooperatively,
+    // 8 lanes x 16 bytes per line, the line of lane 8r + g by group g in round
+    // r, so every load instruction touches 8 lines instead of 64.
+    const uint32_t ph = L.ph;
+    uint64_t v0 = 0, v1 = 0;
+    if (ph == kSrcRec || ph == kRec) {
+      const uint4 r = a.rec[L.tail];
+      v0 = rec_w(r);
+      v1 = rec_od(r);
+    } else if (ph == kBsearch) {
+      v0 = a.g.blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)].lf.p[kLeafEdges - 1];
+    } else if (kStitch && ph == kPool) {
+      v0 = a.pool[L.X];
+    }
+    const bool want_line = (ph == kTree || ph == kLeaf);
+    const uint64_t line_mask = __ballot(want_line);
+    const uint64_t leaf_mask = __ballot(ph == kLeaf);
+    uint32_t line_res = 0;  // tree: keys <= X in the node; leaf: destination
+    if (line_mask) {
+      // owners publish their line and draw in the wave's LDS table; groups
+      // read them back with broadcast loads, reduce with DPP, and leave the
+      // answer in the owner's slot
+      sh_blk[wv][lane] = want_line ? L.off + L.hi + L.lo : 0;
+      sh_x[wv][lane] = L.X;
+      wave_sync();
+      const uint32_t part = lane & 7u, grp = lane >> 3;
+      const uint4* base = reinterpret_cast<const uint4*>(a.g.blocks);
+      uint4 q[8];
+#pragma unroll
+      for (uint32_t r = 0; r < 8; ++r) {
+        const uint32_t owner = 8 * r + grp;
+        q[r] = make_uint4(0, 0, 0, 0);
+        if ((line_mask >> owner) & 1ull) q[r] = base[sh_blk[wv][owner] * 8 + part];
+      }
+#pragma unroll
+      for (uint32_t r = 0; r < 8; ++r) {
+        if (((line_mask >> (8 * r)) & 0xFFull) == 0) continue;
+        const uint32_t owner = 8 * r + grp;
+        const uint64_t xo = sh_x[wv][owner];
+        const bool leaf = (leaf_mask >> owner) & 1ull;
+        const uint64_t k0 = (static_cast<uint64_t>(q[r].y) << 32) | q[r].x;
+        const uint64_t k1 = (static_cast<uint64_t>(q[r].w) << 32) | q[r].z;
+        // tree: 16 keys over the 8 parts; leaf: prefixes in parts 0..3
+        const bool keys = !leaf || part < 4;
+        const uint32_t cnt = sum8((keys && k0 <= xo ? 1u : 0u) + (keys && k1 <= xo ? 1u : 0u));
+        if (leaf) {  // destination j = cnt sits in part 4 + j/4, word j%4
+          if (part == 4 + (cnt >> 2)) {
+            const uint32_t jw = cnt & 3u;
+            sh_res[wv][owner] = jw == 0 ? q[r].x : (jw == 1 ? q[r].y : (jw == 2 ? q[r].z : q[r].w));
+          }
+        } else if (part == 0) {
+          sh_res[wv][owner] = cnt;
         }
       }
-      m += 1;
-      if (!stop && m == kMoveCap) {
-        stop = true;
-        if (kStats) ++st_capped;
+      wave_sync();
+      line_res = sh_res[wv][lane];
+      wave_sync();
+    }
+
+    // ---- consume: a finished step, a new move to start, or a search step ----
+    bool begin = false, step = false, coin = false;
+    uint64_t bw = L.sW, bod = L.s_od;  // record of the move to start
+    if (ph == kSrcRec || ph == kRec) {
+      if (ph == kSrcRec) {
+        L.sW = v0;
+        L.s_od = v1;
       }
-      if (stop) {
-        a.endpoints[g] = tail;
-        active = false;
+      bw = v0;
+      bod = v1;
+      begin = true;
+    } else if (ph == kTree) {
+      L.hi += static_cast<uint32_t>(tree_level_nodes(L.deg, L.lvl));
+      L.lo = L.lo * kNodeKeys + line_res;
+      if (--L.lvl == 0) {  // leaves start right after the tree: block hi + lo
+        L.lo += L.hi;
+        L.hi = 0;
+        L.ph = kLeaf;
+      }
+    } else if (ph == kBsearch) {  // over leaf blocks: their last prefixes
+      const uint32_t mid = L.lo + ((L.hi - L.lo) >> 1);
+      if (v0 > L.X) L.hi = mid; else L.lo = mid + 1;
+      if (L.lo == L.hi) {
+        L.hi = 0;
+        L.ph = kLeaf;
+      }
+    } else if (ph == kLeaf) {
+      L.tail = line_res;
+      L.len += 1;
+      step = true;
+      coin = L.x2 < a.T;
+    } else if (kStitch && ph == kPool) {
+      const uint64_t e = v0;
+      L.tail = static_cast<uint32_t>(e);
+      L.len += static_cast<uint32_t>(e >> 32) & 0xFFFFu;
+      if (kStats) ++L.st_stitch;
+      step = true;
+      coin = ((e >> 48) & 1u) != 0;
+    } else if (ph == kCont) {
+      begin = true;
+    }
+
+    bool done = false, capped = false;
+    if (step) {
+      L.m += 1;
+      if (coin || L.m == kMoveCap) {
+        done = true;
+        capped = !coin;
+      } else if (L.tail == L.s) {
+        begin = true;  // back at the head: its record is in registers
+      } else {
+        L.ph = kRec;
+      }
+    }
+
+    // ---- start a move at the tail with record (bw, bod) ----
+    if (begin) {
+      for (uint32_t restarts = 0;; ++restarts) {
+        const U4 x = philox10(L.i, L.m, L.s, 0u, a.key0, a.key1);
+        const uint32_t d = static_cast<uint32_t>(bod & kDegMask);
+        if (d == 0) {  // no out-edges: back to the head, then the coin
+          L.tail = L.s;
+          L.len += 1;
+          L.m += 1;
+          const bool cn = x.x2 < a.T;
+          if (cn || L.m == kMoveCap) {
+            done = true;
+            capped = !cn;
+            break;
+          }
+          bw = L.sW;
+          bod = L.s_od;
+          if (restarts + 1 >= kInlineRestarts) {
+            L.ph = kCont;
+            break;
+          }
+          continue;
+        }
+        if (kStitch && (bod & kPoolFlag)) {
+          L.X = bw + ((static_cast<uint64_t>(x.x0) << a.K_log2) >> 32);
+          L.ph = kPool;
+          break;
+        }
+        L.X = scaled_draw(x.x0, x.x1, bw);
+        L.x2 = x.x2;
+        L.off = bod >> kRegionShift;  // first block of the row's region
+        L.deg = d;
         if (kStats) {
-          ++st_walks;
-          st_moves += m;
-          st_steps += len;
+          ++L.st_plain;
+          L.st_log += ceil_log2_u32(d);
+        }
+        L.lo = 0;
+        L.hi = 0;
+        if (d > a.g.tree_min) {
+          L.lvl = tree_levels(d);  // lo: node within the level, hi: first node of the level
+          L.ph = kTree;
+        } else if (d > kLeafEdges) {
+          L.hi = static_cast<uint32_t>(leaf_blocks(d)) - 1;  // candidate leaf blocks [lo, hi]
+          L.ph = kBsearch;
+        } else {
+          L.ph = kLeaf;  // the one leaf block
+        }
+        break;
+      }
+    }
+
+    // ---- a terminated walk writes its endpoint and frees the lane ----
+    if (done) {
+      a.endpoints[L.g] = L.tail;
+      L.ph = kIdle;
+      if (kStats) {
+        L.st_moves += L.m;
+        L.st_steps += L.len;
+        if (capped) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->capped), 1ull);
+        // one walk adds at most 2^16 moves and 2^24 steps: flush well before 2^32
+        if ((L.st_steps | L.st_moves | L.st_log) >= 0x40000000u) {
+          unsigned long long* out = reinterpret_cast<unsigned long long*>(a.stats);
+          atomicAdd(out + 1, static_cast<unsigned long long>(L.st_moves));
+          atomicAdd(out + 2, static_cast<unsigned long long>(L.st_steps));
+          atomicAdd(out + 4, static_cast<unsigned long long>(L.st_moves - L.st_plain - L.st_stitch));
+          atomicAdd(out + 5, static_cast<unsigned long long>(L.st_plain));
+          atomicAdd(out + 6, static_cast<unsigned long long>(L.st_stitch));
+          atomicAdd(out + 7, static_cast<unsigned long long>(L.st_log));
+          L.st_moves = L.st_steps = L.st_plain = L.st_stitch = L.st_log = 0;
         }
       }
     }
   }
 
   if (kStats) {
-    const uint64_t v[8] = {st_walks, st_moves, st_steps, st_capped,
-                           st_dang, st_plain, st_stitch, st_log};
+    // fppr_stats order: walks, moves, steps, capped, dangling, plain, stitched, log
+    const uint64_t dang = static_cast<uint64_t>(L.st_moves) - L.st_plain - L.st_stitch;
+    const uint64_t vals[6] = {L.st_moves, L.st_steps, dang, L.st_plain, L.st_stitch, L.st_log};
+    const int slot[6] = {1, 2, 4, 5, 6, 7};
     unsigned long long* out = reinterpret_cast<unsigned long long*>(a.stats);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint64_t t = wave_sum_u64(v[k]);
-      if (lane == 0 && t) atomicAdd(out + k, static_cast<unsigned long long>(t));
+    for (int k = 0; k < 6; ++k) {
+      const uint64_t t = wave_sum_u64(vals[k]);
+      if (lane == 0 && t) atomicAdd(out + slot[k], static_cast<unsigned long long>(t));
     }
+    if (lane == 0 && walks) atomicAdd(out, static_cast<unsigned long long>(walks));
   }
 }
 
@@ -193,7 +400,7 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s) {
 
 hipError_t launch_walk(const fppr_graph* g, const WalkLaunch& w, hipStream_t s) {
   WalkArgs a{};
-  a.g = GraphView{g->rec, g->P, g->col, g->hubs, g->TL, g->chunk_log2};
+  a.g = GraphView{g->rec, g->blocks, g->tree_min};
   a.rec = w.rec;
   a.sources = w.sources;
   a.total = w.n_src * w.R;

@@ -48,7 +48,7 @@ class fppr_csr(ctypes.Structure):
 
 
 class fppr_graph_opts(ctypes.Structure):
-    _fields_ = [("hub_threshold", ctypes.c_uint32), ("chunk", ctypes.c_uint32)]
+    _fields_ = [("hub_threshold", ctypes.c_uint32)]
 
 
 class fppr_pool_opts(ctypes.Structure):
@@ -147,7 +147,7 @@ class Graph:
     """Device graph. `csr` is a CSR object with n, row_offsets, col, w (numpy
     arrays: copied) or torch device tensors (borrowed: kept referenced here)."""
 
-    def __init__(self, csr=None, hub_threshold: int = 0, chunk: int = 0, stream=None, *, n=None,
+    def __init__(self, csr=None, hub_threshold: int = 0, stream=None, *, n=None,
                  row_offsets=None, col=None, w=None):
         import torch
 
@@ -174,7 +174,7 @@ class Graph:
             c.w = ww.ctypes.data if ww.size else None
             c.mem = FPPR_MEM_HOST
         self.m = int(c.m)
-        o = fppr_graph_opts(hub_threshold, chunk)
+        o = fppr_graph_opts(hub_threshold)
         h = ctypes.c_void_p()
         _check(lib().fppr_graph_create(ctypes.byref(c), ctypes.byref(o), _stream_ptr(stream),
                                        ctypes.byref(h)))

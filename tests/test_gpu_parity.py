@@ -83,26 +83,29 @@ def test_small_plain_all_sources(fp, small):
     stats_equal(out, ref.stats)
 
 
-@pytest.mark.parametrize("H,C", [(2, 64), (64, 64), (4096, 4096), (UINT32_MAX, 4096), (100, 128)])
-def test_hub_threshold_is_results_invariant(fp, small, H, C):
-    """Splitting rows into a top-level table plus chunks picks the same edge
-    as a flat search (integer form of Lemma 1)."""
-    say(f"case: hub threshold H={H} C={C}")
-    G = fp.Graph(small, hub_threshold=H, chunk=C)
+@pytest.mark.parametrize("H", [2, 8, 9, 64, 100, 4096, UINT32_MAX])
+def test_hub_threshold_is_results_invariant(fp, small, H):
+    """Rows above the threshold are searched through their 8-ary prefix tree,
+    the others by binary search: both pick the same edge as a flat search
+    (integer form of Lemma 1)."""
+    say(f"case: hub threshold H={H}")
+    G = fp.Graph(small, hub_threshold=H)
     info = G.info()
     deg = small.degrees()
-    assert info["hubs"] == int(np.count_nonzero(deg > min(H, 0x7FFFFF)))
+    want = 0 if H == UINT32_MAX else int(np.count_nonzero(deg > max(H, 8)))
+    assert info["hubs"] == want
     out = fp.run(G, 0.2, 100, 1, topk=16)
     ref = O.run(O.Graph.from_csr(small), 0.2, 100, 1, topk=16)
     compare(out, ref, 100, 16)
     stats_equal(out, ref.stats)
 
 
-@pytest.mark.parametrize("S,L,K,H", [(8, 3, 16, 4096), (32, 3, 64, 64), (4, 1, 1, 2), (64, 5, 8, 16)])
+@pytest.mark.parametrize("S,L,K,H", [(8, 3, 16, 4096), (32, 3, 64, 64), (4, 1, 1, 2), (64, 5, 8, 16),
+                                     (16, 2, 32, UINT32_MAX)])
 def test_small_stitched_and_pool(fp, small, S, L, K, H):
     say(f"case: stitched S={S} L={L} K={K} H={H}")
     alpha = 0.2
-    G = fp.Graph(small, hub_threshold=H, chunk=64)
+    G = fp.Graph(small, hub_threshold=H)
     G.build_pool(S=S, L=L, K=K, alpha=alpha, seed=99)
     og = O.Graph.from_csr(small)
     pool = O.Pool(og, S=S, L=L, K=K, alpha=alpha, seed=99)
