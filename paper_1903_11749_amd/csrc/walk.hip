@@ -9,7 +9,10 @@
 //
 // Each lane runs its walk as a small state machine that needs exactly one
 // dependent load per loop iteration (node record, one 128-byte tree node, one
-// 128-byte leaf block of prefixes and destinations, or one pool entry). Lanes therefore
+// 128-byte leaf block of prefixes and destinations, or one pool entry). Tree
+// nodes and leaf blocks are read by lane pairs, 64 bytes per lane: on gfx950
+// random 128-byte lines stream at full rate only when each lane takes at most
+// half a line (a lane reading a whole line of its own runs 3.7x slower). Lanes therefore
 // advance independently: an iteration costs one memory latency, not the
 // longest move in the wave. The head's record stays in registers, so the
 // restart from a node without out-edges (Sec. 2.1) costs no load at all.
@@ -87,13 +90,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over each aligned group of 8 lanes, in every lane of the group (DPP:
-// swap neighbours, swap pairs, then mirror the two quads of the half-row).
-__device__ __forceinline__ uint32_t sum8(uint32_t x) {
-  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
-  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x4E, 0xF, 0xF, false));
-  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x141, 0xF, 0xF, false));
-  return x;
+// The value of the other lane of this lane's aligned pair (DPP quad
+// permutation [1, 0, 3, 2]).
+__device__ __forceinline__ uint32_t swap_pair(uint32_t x) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
 }
 
 template <bool kStitch, bool kStats>
@@ -179,38 +179,50 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
     const uint64_t leaf_mask = __ballot(ph == kLeaf);
     uint32_t line_res = 0;  // tree: keys <= X in the node; leaf: destination
     if (line_mask) {
-      // owners publish their line and draw in the wave's LDS table; groups
-      // read them back with broadcast loads, reduce with DPP, and leave the
-      // answer in the owner's slot
+      // Owners publish their line and draw in the wave's LDS table. Lane pairs
+      // load lines: in round r the pair p reads the line of lane 32 r + p, the
+      // even lane its first 64 bytes (tree keys 0..7, or the leaf's 8
+      // prefixes), the odd lane the rest (keys 8..15, or the 8 destinations).
       sh_blk[wv][lane] = want_line ? L.off + L.hi + L.lo : 0;
       sh_x[wv][lane] = L.X;
       wave_sync();
-      const uint32_t part = lane & 7u, grp = lane >> 3;
+      const uint32_t half = lane & 1u, pair = lane >> 1;
       const uint4* base = reinterpret_cast<const uint4*>(a.g.blocks);
-      uint4 q[8];
+      uint4 q[2][4];
 #pragma unroll
-      for (uint32_t r = 0; r < 8; ++r) {
-        const uint32_t owner = 8 * r + grp;
-        q[r] = make_uint4(0, 0, 0, 0);
-        if ((line_mask >> owner) & 1ull) q[r] = base[sh_blk[wv][owner] * 8 + part];
+      for (uint32_t r = 0; r < 2; ++r) {
+        const uint32_t owner = 32 * r + pair;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) q[r][k] = make_uint4(0, 0, 0, 0);
+        if ((line_mask >> owner) & 1ull) {
+          const uint4* src = base + sh_blk[wv][owner] * 8 + half * 4;
+#pragma unroll
+          for (uint32_t k = 0; k < 4; ++k) q[r][k] = src[k];
+        }
       }
 #pragma unroll
-      for (uint32_t r = 0; r < 8; ++r) {
-        if (((line_mask >> (8 * r)) & 0xFFull) == 0) continue;
-        const uint32_t owner = 8 * r + grp;
+      for (uint32_t r = 0; r < 2; ++r) {
+        if (((line_mask >> (32 * r)) & 0xFFFFFFFFull) == 0) continue;
+        const uint32_t owner = 32 * r + pair;
         const uint64_t xo = sh_x[wv][owner];
         const bool leaf = (leaf_mask >> owner) & 1ull;
-        const uint64_t k0 = (static_cast<uint64_t>(q[r].y) << 32) | q[r].x;
-        const uint64_t k1 = (static_cast<uint64_t>(q[r].w) << 32) | q[r].z;
-        // tree: 16 keys over the 8 parts; leaf: prefixes in parts 0..3
-        const bool keys = !leaf || part < 4;
-        const uint32_t cnt = sum8((keys && k0 <= xo ? 1u : 0u) + (keys && k1 <= xo ? 1u : 0u));
-        if (leaf) {  // destination j = cnt sits in part 4 + j/4, word j%4
-          if (part == 4 + (cnt >> 2)) {
-            const uint32_t jw = cnt & 3u;
-            sh_res[wv][owner] = jw == 0 ? q[r].x : (jw == 1 ? q[r].y : (jw == 2 ? q[r].z : q[r].w));
+        uint32_t cnt = 0;
+        if (!leaf || half == 0) {
+#pragma unroll
+          for (uint32_t k = 0; k < 4; ++k) {
+            const uint64_t k0 = (static_cast<uint64_t>(q[r][k].y) << 32) | q[r][k].x;
+            const uint64_t k1 = (static_cast<uint64_t>(q[r][k].w) << 32) | q[r][k].z;
+            cnt += (k0 <= xo ? 1u : 0u) + (k1 <= xo ? 1u : 0u);
           }
-        } else if (part == 0) {
+        }
+        cnt += swap_pair(cnt);  // both lanes of the pair hold the total
+        if (leaf) {  // destination j = cnt: word j of the odd lane's 8 ids
+          if (half == 1) {
+            const uint4 w = (cnt < 4) ? q[r][0] : q[r][1];
+            const uint32_t jw = cnt & 3u;
+            sh_res[wv][owner] = jw == 0 ? w.x : (jw == 1 ? w.y : (jw == 2 ? w.z : w.w));
+          }
+        } else if (half == 0) {
           sh_res[wv][owner] = cnt;
         }
       }
