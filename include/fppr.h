@@ -237,6 +237,56 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
                               uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
                               const fppr_out* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many graphs or source sets in one persistent walk launch.
+ * Algorithm 2 runs all walks of all nodes together; a batch extends that to
+ * several independent problems of uneven sizes so that small ones do not
+ * leave the GPU idle and launch overheads are paid once. Every item keeps
+ * its own seed, alpha, R, k and outputs; its results are bit-identical to
+ * fppr_run of that item alone (draws depend only on the item's seed and the
+ * source, walk and move indices).
+ * ---------------------------------------------------------------------- */
+typedef struct fppr_batch fppr_batch;
+
+typedef struct {
+  fppr_graph* graph;         /* device graph (pool built if FPPR_STITCH) */
+  fppr_params params;        /* as for fppr_run */
+  const uint32_t* sources;   /* device uint32 [n_sources], or NULL = all nodes */
+  uint64_t n_sources;
+  fppr_out out;              /* device outputs of this item (profile ignored) */
+} fppr_batch_item;
+
+/* Workspace bytes for a batch (control words, the walk table, one endpoint
+ * buffer per item). Pure host computation. */
+FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t count,
+                                     uint64_t* workspace_bytes);
+
+/* Validates every item as fppr_run would, lays out `workspace` (device,
+ * >= fppr_batch_plan bytes) and uploads the walk table (synchronous). Items
+ * are ordered by decreasing walk count in the table. The batch keeps a copy
+ * of `items`; graphs, sources, outputs and the workspace must outlive it. */
+FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t count,
+                                       void* workspace, uint64_t workspace_bytes,
+                                       fppr_batch** out);
+
+/* Enqueues the batch on `stream`: one persistent walk launch over every
+ * item's walks, then each item's counting and top-k. `stats` (device, may be
+ * NULL) accumulates over the whole batch; `profile` (may be NULL) times the
+ * walk launch and the aggregation launches. */
+FPPR_API fppr_status fppr_batch_run(fppr_batch* b, fppr_stats* stats, fppr_profile* profile,
+                                    void* stream);
+
+/* Captures fppr_batch_run(b, stats, NULL, stream) into a HIP graph owned by
+ * the batch (replacing an earlier capture); fppr_batch_launch replays it on
+ * `stream`. The capture records kernels only (counters are cleared by a fill
+ * kernel, not a memset). */
+FPPR_API fppr_status fppr_batch_capture(fppr_batch* b, fppr_stats* stats, void* stream);
+FPPR_API fppr_status fppr_batch_launch(fppr_batch* b, void* stream);
+
+/* Synchronises `stream`; INVALID_ARGUMENT if a batch run met a source id >= n. */
+FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream);
+FPPR_API fppr_status fppr_batch_destroy(fppr_batch* b);
+
 /* Synchronises `stream` and reports whether a run that used `workspace` met
  * a source id >= n (INVALID_ARGUMENT; such a source gets no walks and its
  * endpoints read FPPR_NO_NODE) or FPPR_OK. */

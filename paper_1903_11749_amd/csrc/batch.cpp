@@ -1,0 +1,212 @@
+// Batches: several graphs or source sets served by one persistent walk
+// launch (the walk table holds one descriptor per item), then each item's
+// counting and top-k; optionally captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "fppr_internal.hpp"
+
+using namespace fppr;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr uint64_t kCtlBytes = 256;
+
+fppr_status invalid(const std::string& msg) {
+  set_error(msg);
+  return FPPR_INVALID_ARGUMENT;
+}
+
+uint64_t item_sources(const fppr_batch_item& it) {
+  return it.sources ? it.n_sources : it.graph->n;
+}
+
+}  // namespace
+
+struct fppr_batch {
+  std::vector<fppr_batch_item> items;
+  std::vector<WalkDesc> host_table;
+  std::vector<uint32_t*> endpoints;   // per item
+  unsigned long long* ctl = nullptr;  // in the workspace
+  WalkDesc* table = nullptr;          // in the workspace
+  uint64_t total = 0;                 // padded walk ids
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+fppr_status check_items(const fppr_batch_item* items, uint32_t count) {
+  if (!items || count == 0) return invalid("batch needs at least one item");
+  for (uint32_t k = 0; k < count; ++k) {
+    const fppr_batch_item& it = items[k];
+    if (!it.graph) return invalid("batch item " + std::to_string(k) + ": graph is NULL");
+    fppr_status st = check_params(it.graph, &it.params);
+    if (st != FPPR_OK) return st;
+    if (!it.sources && it.n_sources != it.graph->n && it.n_sources != 0)
+      return invalid("batch item " + std::to_string(k) + ": sources == NULL needs n_sources == n");
+    if ((st = check_outputs(&it.params, &it.out)) != FPPR_OK) return st;
+    if (item_sources(it) > (1ull << 40) / it.params.R)
+      return invalid("batch item " + std::to_string(k) + ": n_sources * R too large");
+  }
+  return FPPR_OK;
+}
+
+uint64_t endpoint_bytes(const fppr_batch_item& it) {
+  return align_up(item_sources(it) * it.params.R * 4ull);
+}
+
+void free_batch(fppr_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+}
+
+fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStream_t s) {
+  hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(b->ctl), kCtlBytes / 8, s);
+  if (e != hipSuccess) return hip_fail(e, "zero control words");
+  if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
+  e = launch_walk(b->table, static_cast<uint32_t>(b->host_table.size()), b->total, b->ctl, stats, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "walk kernel");
+  if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
+  if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
+  for (size_t k = 0; k < b->items.size(); ++k) {
+    const fppr_batch_item& it = b->items[k];
+    const AggLaunch a = make_agg(&it.params, b->endpoints[k], it.sources, item_sources(it), &it.out);
+    if (a.topk || a.counts || a.digest) {
+      if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");
+    }
+  }
+  if (prof && (e = hipEventRecord(prof->ev[3], s)) != hipSuccess) return hip_fail(e, "event");
+  return FPPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t count,
+                                     uint64_t* workspace_bytes) {
+  fppr_status st = check_items(items, count);
+  if (st != FPPR_OK) return st;
+  if (!workspace_bytes) return invalid("workspace_bytes is NULL");
+  uint64_t bytes = kCtlBytes + align_up(count * sizeof(WalkDesc));
+  for (uint32_t k = 0; k < count; ++k) bytes += endpoint_bytes(items[k]);
+  *workspace_bytes = bytes;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t count,
+                                       void* workspace, uint64_t workspace_bytes,
+                                       fppr_batch** out) {
+  if (!out) return invalid("out is NULL");
+  *out = nullptr;
+  uint64_t need = 0;
+  fppr_status st = fppr_batch_plan(items, count, &need);
+  if (st != FPPR_OK) return st;
+  if (!workspace || workspace_bytes < need) return invalid("workspace missing or smaller than fppr_batch_plan");
+  auto* b = new fppr_batch();
+  b->items.assign(items, items + count);
+  char* base = static_cast<char*>(workspace);
+  b->ctl = reinterpret_cast<unsigned long long*>(base);
+  b->table = reinterpret_cast<WalkDesc*>(base + kCtlBytes);
+  char* ep = base + kCtlBytes + align_up(count * sizeof(WalkDesc));
+  b->endpoints.resize(count);
+  for (uint32_t k = 0; k < count; ++k) {
+    b->endpoints[k] = reinterpret_cast<uint32_t*>(ep);
+    ep += endpoint_bytes(items[k]);
+  }
+  // largest items first, so that small ones fill the tail of the launch
+  std::vector<uint32_t> order(count);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    return item_sources(items[x]) * items[x].params.R > item_sources(items[y]) * items[y].params.R;
+  });
+  uint64_t first = 0;
+  for (uint32_t k : order) {
+    const fppr_batch_item& it = items[k];
+    const uint64_t walks = item_sources(it) * it.params.R;
+    if (walks == 0) continue;
+    b->host_table.push_back(
+        make_desc(it.graph, &it.params, it.sources, item_sources(it), b->endpoints[k], first, 0, walks));
+    first += (walks + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
+  }
+  b->total = first;
+  if (!b->host_table.empty()) {
+    hipError_t e = hipMemcpy(b->table, b->host_table.data(), b->host_table.size() * sizeof(WalkDesc),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(e, "upload walk table");
+    }
+  }
+  *out = b;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_batch_run(fppr_batch* b, fppr_stats* stats, fppr_profile* profile,
+                                    void* stream) {
+  if (!b) return invalid("batch is NULL");
+  return enqueue(b, stats, profile, static_cast<hipStream_t>(stream));
+}
+
+FPPR_API fppr_status fppr_batch_capture(fppr_batch* b, fppr_stats* stats, void* stream) {
+  if (!b) return invalid("batch is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!s) return invalid("capture needs a non-null stream");
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  fppr_status st = enqueue(b, stats, nullptr, s);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (st != FPPR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  b->graph = g;
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_batch_launch(fppr_batch* b, void* stream) {
+  if (!b) return invalid("batch is NULL");
+  if (!b->exec) return invalid("no captured graph (fppr_batch_capture)");
+  hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream) {
+  if (!b) return invalid("batch is NULL");
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  unsigned long long ctl[2];
+  e = hipMemcpy(ctl, b->ctl, sizeof ctl, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "read batch status");
+  if (ctl[1]) return invalid("a source id was >= n (its walks were skipped)");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_batch_destroy(fppr_batch* b) {
+  free_batch(b);
+  return FPPR_OK;
+}
+
+}  // extern "C"

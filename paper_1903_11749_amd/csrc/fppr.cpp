@@ -8,10 +8,6 @@
 
 #include "fppr_internal.hpp"
 
-struct fppr_profile {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-};
-
 namespace fppr {
 
 namespace {
@@ -20,8 +16,11 @@ thread_local std::string g_last_error;
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Workspace layout: [0, 256) control words, then the endpoint buffer.
+// Run workspace: [0, 256) control words, [256, 512) the walk descriptor,
+// then the endpoint buffer.
 constexpr uint64_t kCtlBytes = 256;
+constexpr uint64_t kDescBytes = 256;
+static_assert(sizeof(WalkDesc) <= kDescBytes, "descriptor slot");
 
 template <typename T>
 hipError_t dmalloc(T** p, uint64_t count, uint64_t* acc) {
@@ -133,6 +132,60 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 fppr_status hip_fail(hipError_t e, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   return e == hipErrorOutOfMemory ? FPPR_OUT_OF_MEMORY : FPPR_DEVICE_ERROR;
+}
+
+WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* sources,
+                   uint64_t n_sources, uint32_t* endpoints, uint64_t first, uint64_t walk0,
+                   uint64_t count) {
+  (void)n_sources;
+  const bool stitch = (p->flags & FPPR_STITCH) != 0;
+  WalkDesc D{};
+  D.rec = stitch ? g->rec_st : g->rec;
+  D.blocks = g->blocks;
+  D.sources = sources;
+  D.endpoints = endpoints;
+  D.first = first;
+  D.count = count;
+  D.walk0 = walk0;
+  D.R_magic = ~0ull / p->R;
+  D.R = p->R;
+  D.n = g->n;
+  D.key0 = static_cast<uint32_t>(p->seed);
+  D.key1 = static_cast<uint32_t>(p->seed >> 32);
+  D.T = fppr_alpha_threshold(p->alpha);
+  D.tree_min = g->tree_min;
+  D.K_log2 = stitch ? g->K_log2 : 0;
+  return D;
+}
+
+AggLaunch make_agg(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
+                   uint64_t n_sources, const fppr_out* out) {
+  AggLaunch a{};
+  a.endpoints = endpoints;
+  a.sources = sources;
+  a.n_src = n_sources;
+  a.R = p->R;
+  a.k = p->topk;
+  a.topk = p->topk ? out->topk : nullptr;
+  a.counts = (p->flags & FPPR_COUNTS) ? out->counts : nullptr;
+  a.n_distinct = (p->flags & FPPR_COUNTS) ? out->n_distinct : nullptr;
+  a.digest = (p->flags & FPPR_DIGESTS) ? out->digest : nullptr;
+  return a;
+}
+
+fppr_status check_outputs(const fppr_params* p, const fppr_out* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return FPPR_INVALID_ARGUMENT;
+  }
+  std::string msg;
+  if (p->topk && !out->topk) msg = "topk > 0 needs out->topk";
+  else if ((p->flags & FPPR_COUNTS) && (!out->counts || !out->n_distinct))
+    msg = "FPPR_COUNTS needs out->counts and out->n_distinct";
+  else if ((p->flags & FPPR_DIGESTS) && !out->digest) msg = "FPPR_DIGESTS needs out->digest";
+  if (msg.empty()) return FPPR_OK;
+  set_error(msg);
+  return FPPR_INVALID_ARGUMENT;
 }
 
 }  // namespace fppr
@@ -350,7 +403,9 @@ FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream) {
   return FPPR_OK;
 }
 
-static fppr_status check_params(const fppr_graph* g, const fppr_params* p) {
+}  // extern "C"
+
+fppr_status fppr::check_params(const fppr_graph* g, const fppr_params* p) {
   if (!g || !p) return invalid("graph or params is NULL");
   if (!fppr_alpha_threshold(p->alpha)) return invalid("alpha must be in (0, 1)");
   if (p->R < 1 || p->R > kAggMaxR) return invalid("R must be in [1, 4096]");
@@ -363,12 +418,14 @@ static fppr_status check_params(const fppr_graph* g, const fppr_params* p) {
   return FPPR_OK;
 }
 
+extern "C" {
+
 FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,
                                uint64_t* workspace_bytes) {
   fppr_status st = check_params(g, p);
   if (st != FPPR_OK) return st;
   if (!workspace_bytes) return invalid("workspace_bytes is NULL");
-  *workspace_bytes = kCtlBytes + align_up(n_sources * p->R * 4ull);
+  *workspace_bytes = kCtlBytes + kDescBytes + align_up(n_sources * p->R * 4ull);
   return FPPR_OK;
 }
 
@@ -384,49 +441,26 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
   uint64_t need = 0;
   fppr_plan(g, p, n_sources, &need);
   if (!workspace || workspace_bytes < need) return invalid("workspace missing or smaller than fppr_plan");
-  if (p->topk && !out->topk) return invalid("topk > 0 needs out->topk");
-  if ((p->flags & FPPR_COUNTS) && (!out->counts || !out->n_distinct)) return invalid("FPPR_COUNTS needs out->counts and out->n_distinct");
-  if ((p->flags & FPPR_DIGESTS) && !out->digest) return invalid("FPPR_DIGESTS needs out->digest");
+  if ((st = check_outputs(p, out)) != FPPR_OK) return st;
   if ((p->flags & FPPR_STATS) && !out->stats) return invalid("FPPR_STATS needs out->stats");
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto* ctl = static_cast<unsigned long long*>(workspace);
+  auto* desc = reinterpret_cast<WalkDesc*>(static_cast<char*>(workspace) + kCtlBytes);
   uint32_t* endpoints = out->endpoints
                             ? out->endpoints
-                            : reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + kCtlBytes);
+                            : reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + kCtlBytes +
+                                                          kDescBytes);
   hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(ctl), kCtlBytes / 8, s);
   if (e != hipSuccess) return hip_fail(e, "zero control words");
-
-  WalkLaunch w{};
-  const bool stitch = (p->flags & FPPR_STITCH) != 0;
-  w.rec = stitch ? g->rec_st : g->rec;
-  w.sources = sources;
-  w.n_src = n_sources;
-  w.R = p->R;
-  w.R_magic = ~0ull / p->R;
-  w.key0 = static_cast<uint32_t>(p->seed);
-  w.key1 = static_cast<uint32_t>(p->seed >> 32);
-  w.T = fppr_alpha_threshold(p->alpha);
-  w.pool = stitch ? g->pool : nullptr;
-  w.K_log2 = stitch ? g->K_log2 : 0;
-  w.stitch = stitch;
-  w.endpoints = endpoints;
-  w.work_counter = ctl;
-  w.stats = (p->flags & FPPR_STATS) ? out->stats : nullptr;
+  const WalkDesc D = make_desc(g, p, sources, n_sources, endpoints, 0, 0, n_sources * p->R);
+  if ((e = launch_set_desc(D, desc, s)) != hipSuccess) return hip_fail(e, "walk descriptor");
+  const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
+  fppr_stats* stats = (p->flags & FPPR_STATS) ? out->stats : nullptr;
   fppr_profile* prof = out->profile;
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = launch_walk(g, w, s)) != hipSuccess) return hip_fail(e, "walk kernel");
+  if ((e = launch_walk(desc, 1, total, ctl, stats, 0, s)) != hipSuccess) return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
-
-  AggLaunch a{};
-  a.endpoints = endpoints;
-  a.sources = sources;
-  a.n_src = n_sources;
-  a.R = p->R;
-  a.k = p->topk;
-  a.topk = p->topk ? out->topk : nullptr;
-  a.counts = (p->flags & FPPR_COUNTS) ? out->counts : nullptr;
-  a.n_distinct = (p->flags & FPPR_COUNTS) ? out->n_distinct : nullptr;
-  a.digest = (p->flags & FPPR_DIGESTS) ? out->digest : nullptr;
+  const AggLaunch a = make_agg(p, endpoints, sources, n_sources, out);
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
   if (a.topk || a.counts || a.digest) {
     if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");

@@ -57,10 +57,16 @@ struct fppr_graph {
   uint64_t device_bytes = 0;
 };
 
+struct fppr_profile {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
 namespace fppr {
 
 void set_error(const std::string& msg);
 fppr_status hip_fail(hipError_t e, const char* what);
+fppr_status check_params(const fppr_graph* g, const fppr_params* p);
+fppr_status check_outputs(const fppr_params* p, const fppr_out* out);
 
 // build.hip
 hipError_t launch_validate(const fppr_graph* g, hipStream_t s);
@@ -80,21 +86,29 @@ hipError_t launch_small_compact(fppr_graph* g, uint32_t S, hipStream_t s);
 hipError_t launch_pool(fppr_graph* g, hipStream_t s);
 
 // walk.hip
-struct WalkLaunch {
-  const uint4* rec;  // plain or stitched record table
-  const uint32_t* sources;
-  uint64_t n_src;
-  uint32_t R;
-  uint64_t R_magic;   // floor((2^64 - 1) / R)
-  uint32_t key0, key1, T;
-  const uint64_t* pool;
-  uint32_t K_log2;
-  bool stitch;
+// One descriptor of the walk table: a run of walks on one graph. Ids
+// [first, first + count) of the launch map to walk indices walk0 + (id -
+// first) of the run; walk index w is walk w % R of source row w / R, and its
+// endpoint goes to endpoints[w]. first is a multiple of kWalkChunk.
+constexpr uint64_t kWalkChunk = 256;
+struct WalkDesc {
+  const uint4* rec;          // plain records, or the stitched table
+  const Block* blocks;       // row regions
+  const uint32_t* sources;   // source ids by row, or null for row = node id
   uint32_t* endpoints;
-  unsigned long long* work_counter;  // zeroed before launch
-  fppr_stats* stats;                 // may be null
+  uint64_t first;
+  uint64_t count;
+  uint64_t walk0;
+  uint64_t R_magic;          // floor((2^64 - 1) / R)
+  uint32_t R, n, key0, key1, T, tree_min, K_log2, pad;
 };
-hipError_t launch_walk(const fppr_graph* g, const WalkLaunch& a, hipStream_t s);
+hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
+                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s);
+hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s);
+// descriptor of walks [walk0, walk0 + count) of a run of `p` on graph g
+WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* sources,
+                   uint64_t n_sources, uint32_t* endpoints, uint64_t first, uint64_t walk0,
+                   uint64_t count);
 hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s);
 
 // aggregate.hip
@@ -110,6 +124,8 @@ struct AggLaunch {
   uint64_t* digest;
 };
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s);
+AggLaunch make_agg(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
+                   uint64_t n_sources, const fppr_out* out);
 constexpr uint32_t kAggMaxR = 4096;
 
 }  // namespace fppr

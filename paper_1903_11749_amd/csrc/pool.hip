@@ -34,10 +34,11 @@ __global__ void k_small_flags(const uint64_t* __restrict__ off, uint32_t n, uint
 }
 
 // small_nodes[rank] = u and the stitched record table: small nodes point at
-// their pool block, every other node keeps its plain record.
+// their pool block (absolute address), every other node keeps its plain
+// record.
 __global__ void k_small_compact(const uint32_t* __restrict__ flag,
                                 const uint64_t* __restrict__ rank, const uint4* __restrict__ rec,
-                                uint32_t n, uint32_t K_log2, uint64_t cap,
+                                uint32_t n, uint32_t K_log2, uint64_t cap, const uint64_t* pool,
                                 uint32_t* __restrict__ small_nodes, uint4* __restrict__ rec_st,
                                 uint32_t* err) {
   for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
@@ -49,7 +50,8 @@ __global__ void k_small_compact(const uint32_t* __restrict__ flag,
         atomicOr(err, kErrCapacity);
       } else {
         small_nodes[k] = static_cast<uint32_t>(u);
-        const uint64_t base = k << K_log2;
+        // the stitched record carries the address of the node's first entry
+        const uint64_t base = reinterpret_cast<uint64_t>(pool + (k << K_log2));
         const uint64_t od = rec_od(r) | kPoolFlag;
         r = make_uint4(static_cast<uint32_t>(base), static_cast<uint32_t>(base >> 32),
                        static_cast<uint32_t>(od), static_cast<uint32_t>(od >> 32));
@@ -100,7 +102,8 @@ hipError_t launch_small_flags(fppr_graph* g, uint32_t S, hipStream_t s) {
 
 hipError_t launch_small_compact(fppr_graph* g, uint32_t /*S*/, hipStream_t s) {
   hipLaunchKernelGGL(k_small_compact, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->flag, g->scan,
-                     g->rec, g->n, g->K_log2, g->n_small, g->small_nodes, g->rec_st, g->d_err);
+                     g->rec, g->n, g->K_log2, g->n_small, g->pool, g->small_nodes, g->rec_st,
+                     g->d_err);
   return hipGetLastError();
 }
 

@@ -7,15 +7,24 @@
 // registers; a lane whose walk terminated takes the next walk id at once
 // (ballot + mbcnt over the idle lanes, one atomic per wave per chunk of ids).
 //
+// Work comes from a table of descriptors. Each covers a run of walks on one
+// graph with its own seed, coin threshold, walks per source, sources and
+// endpoint buffer; its ids are padded to whole chunks so a chunk never mixes
+// descriptors. A plain run is a one-entry table; a batch of graphs or source
+// sets, or the slices of many queries, are longer tables served by the same
+// launch. Draws depend only on (seed, source, walk, move), never on the table.
+// A wave serves one descriptor at a time, so all of its values sit in scalar
+// registers; a wave that claims a chunk of another descriptor lets its running
+// walks finish before it switches.
+//
 // Each lane runs its walk as a small state machine that needs exactly one
 // dependent load per loop iteration (node record, one 128-byte tree node, one
 // 128-byte leaf block of prefixes and destinations, or one pool entry). Tree
 // nodes and leaf blocks are read by lane pairs, 64 bytes per lane: on gfx950
 // random 128-byte lines stream at full rate only when each lane takes at most
-// half a line (a lane reading a whole line of its own runs 3.7x slower). Lanes therefore
-// advance independently: an iteration costs one memory latency, not the
-// longest move in the wave. The head's record stays in registers, so the
-// restart from a node without out-edges (Sec. 2.1) costs no load at all.
+// half a line (a lane reading a whole line of its own runs 3.7x slower). The
+// head's record stays in registers, so the restart from a node without
+// out-edges (Sec. 2.1) costs no load at all.
 //
 // One move (integer only):
 //   x = Philox4x32-10(key = seed, counter = (i, m, s, 0))
@@ -30,8 +39,7 @@ namespace fppr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint64_t kChunk = 256;          // walk ids claimed per wave at a time
-constexpr uint32_t kInlineRestarts = 8;   // restarts handled per iteration
+constexpr uint32_t kInlineRestarts = 8;  // restarts handled per iteration
 
 enum : uint32_t {
   kIdle = 0,
@@ -44,31 +52,23 @@ enum : uint32_t {
   kCont = 7,    // no load: continue restarts at the head
 };
 
-struct WalkArgs {
-  GraphView g;
-  const uint4* __restrict__ rec;  // plain or stitched records
-  const uint32_t* __restrict__ sources;
-  uint64_t total;  // n_src * R
-  uint32_t R;
-  uint64_t R_magic;
-  uint32_t n;
-  uint32_t key0, key1, T;
-  const uint64_t* __restrict__ pool;
-  uint32_t K_log2;
-  uint32_t* __restrict__ endpoints;
-  unsigned long long* work_counter;  // [0] next id, [1] invalid-source flag
+struct WalkTable {
+  const WalkDesc* __restrict__ descs;
+  uint32_t ndesc;
+  uint64_t total;                    // ids over all descriptors (padded)
+  unsigned long long* ctl;           // [0] next id, [1] invalid-source flag
   fppr_stats* stats;
 };
 
 struct Lane {
   // walk
-  uint64_t g;
+  uint32_t* ep;  // endpoint slot
   uint32_t s, i, m, len, tail;
   // head record
   uint64_t sW, s_od;
   // current move
   uint32_t ph;
-  uint64_t X;     // draw, or the pool entry index
+  uint64_t X;     // draw, or the address of the pool entry
   uint64_t off;   // first block of the row's region
   uint32_t deg, x2;
   // search state (blocks relative to the region): tree descent (lvl; lo =
@@ -96,34 +96,90 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t x) {
   return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
 }
 
-template <bool kStitch, bool kStats>
-__global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
-  __shared__ uint64_t sh_blk[kThreads / 64][64];
+__device__ __forceinline__ uint32_t sread(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t sread64(uint64_t x) {
+  return static_cast<uint64_t>(sread(static_cast<uint32_t>(x))) |
+         (static_cast<uint64_t>(sread(static_cast<uint32_t>(x >> 32))) << 32);
+}
+
+template <bool kStats>
+__global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
+  __shared__ uint64_t sh_line[kThreads / 64][64];
   __shared__ uint64_t sh_x[kThreads / 64][64];
   __shared__ uint32_t sh_res[kThreads / 64][64];
   const uint32_t lane = __lane_id();
   const uint32_t wv = threadIdx.x / 64;
   Lane L{};
   L.ph = kIdle;
-  uint64_t cur = 0, end = 0;  // wave-uniform chunk of walk ids (scalar registers)
+  // the wave's current chunk [cur, end) of descriptor d and that descriptor's
+  // values (all wave-uniform)
+  constexpr uint64_t kNoChunk = ~0ull;
+  uint64_t cur = 0, end = 0, pend = kNoChunk;
+  uint32_t d = ~0u, pend_d = 0;
   bool exhausted = false;
-  uint64_t walks = 0;         // walks started by this wave
+  uint64_t walks = 0;  // walks started by this wave
+  const uint4* rec = nullptr;
+  const Block* blocks = nullptr;
+  const uint32_t* sources = nullptr;
+  uint32_t* endpoints = nullptr;
+  uint64_t first = 0, walk0 = 0, R_magic = 0;
+  uint32_t R = 1, n = 0, T = 0, key0 = 0, key1 = 0, tree_min = 0, K_log2 = 0;
 
   for (;;) {
     // ---- refill idle lanes from the wave's chunk of walk ids ----
     uint64_t idle = __ballot(L.ph == kIdle);
     while (idle != 0 && !exhausted) {
       if (cur >= end) {
-        unsigned long long c = 0;
-        if (lane == 0) c = atomicAdd(a.work_counter, static_cast<unsigned long long>(kChunk));
-        c = static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(c))) |
-            (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(c >> 32))) << 32);
-        if (c >= a.total) {
-          exhausted = true;
-          break;
+        uint64_t c;
+        uint32_t dn;
+        if (pend != kNoChunk) {
+          c = pend;
+          dn = pend_d;
+        } else {
+          unsigned long long a = 0;
+          if (lane == 0) a = atomicAdd(t.ctl, static_cast<unsigned long long>(kWalkChunk));
+          c = sread64(a);
+          if (c >= t.total) {
+            exhausted = true;
+            break;
+          }
+          // descriptor holding chunk c: the last one with first <= c
+          uint32_t lo = 0, hi = t.ndesc - 1;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (t.descs[mid].first <= c) lo = mid; else hi = mid - 1;
+          }
+          dn = sread(lo);
         }
+        if (dn != d) {
+          if (__ballot(L.ph != kIdle) != 0) {  // finish the running walks first
+            pend = c;
+            pend_d = dn;
+            break;
+          }
+          d = dn;
+          const WalkDesc& D = t.descs[d];
+          rec = D.rec;
+          blocks = D.blocks;
+          sources = D.sources;
+          endpoints = D.endpoints;
+          first = D.first;
+          walk0 = D.walk0;
+          R_magic = D.R_magic;
+          R = D.R;
+          n = D.n;
+          T = D.T;
+          key0 = D.key0;
+          key1 = D.key1;
+          tree_min = D.tree_min;
+          K_log2 = D.K_log2;
+          end = first + D.count;  // limit of the descriptor, clipped below
+        } else {
+          end = t.descs[d].first + t.descs[d].count;
+        }
+        pend = kNoChunk;
         cur = c;
-        end = (c + kChunk < a.total) ? c + kChunk : a.total;
+        if (c + kWalkChunk < end) end = c + kWalkChunk;
       }
       const uint64_t avail = end - cur;
       const uint32_t nidle = static_cast<uint32_t>(__popcll(idle));
@@ -131,23 +187,24 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
       if (L.ph == kIdle) {
         const uint32_t r = mask_rank(idle);
         if (r < take) {
-          L.g = cur + r;
-          uint64_t q = __umul64hi(L.g, a.R_magic);
-          uint64_t rem = L.g - q * a.R;
-          if (rem >= a.R) {
+          const uint64_t w = walk0 + (cur + r - first);  // walk index within its run
+          uint64_t q = __umul64hi(w, R_magic);
+          uint64_t rem = w - q * R;
+          if (rem >= R) {
             q += 1;
-            rem -= a.R;
+            rem -= R;
           }
-          L.s = a.sources ? a.sources[q] : static_cast<uint32_t>(q);
+          L.s = sources ? sources[q] : static_cast<uint32_t>(q);
           L.i = static_cast<uint32_t>(rem);
+          L.ep = endpoints + w;
           L.tail = L.s;
           L.m = 0;
           L.len = 0;
           L.ph = kSrcRec;
-          if (L.s >= a.n) {  // invalid source: no walk, recorded for the caller
-            a.endpoints[L.g] = kNoNode;
-            atomicOr(a.work_counter + 1, 1ull);
-            if (kStats) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->walks), ~0ull);
+          if (L.s >= n) {  // invalid source: no walk, recorded for the caller
+            *L.ep = kNoNode;
+            atomicOr(t.ctl + 1, 1ull);
+            if (kStats) atomicAdd(reinterpret_cast<unsigned long long*>(&t.stats->walks), ~0ull);
             L.ph = kIdle;
           }
         }
@@ -160,19 +217,17 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
 
     // ---- this iteration's loads ----
     // Records, pool entries and probes are one small load per lane. Tree nodes
-    // and leaf blocks are whole 128-byte lines: lanes load them cooperatively,
-    // 8 lanes x 16 bytes per line, the line of lane 8r + g by group g in round
-    // r, so every load instruction touches 8 lines instead of 64.
+    // and leaf blocks are whole 128-byte lines loaded by lane pairs.
     const uint32_t ph = L.ph;
     uint64_t v0 = 0, v1 = 0;
     if (ph == kSrcRec || ph == kRec) {
-      const uint4 r = a.rec[L.tail];
+      const uint4 r = rec[L.tail];
       v0 = rec_w(r);
       v1 = rec_od(r);
     } else if (ph == kBsearch) {
-      v0 = a.g.blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)].lf.p[kLeafEdges - 1];
-    } else if (kStitch && ph == kPool) {
-      v0 = a.pool[L.X];
+      v0 = blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)].lf.p[kLeafEdges - 1];
+    } else if (ph == kPool) {
+      v0 = *reinterpret_cast<const uint64_t*>(L.X);
     }
     const bool want_line = (ph == kTree || ph == kLeaf);
     const uint64_t line_mask = __ballot(want_line);
@@ -183,11 +238,11 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
       // load lines: in round r the pair p reads the line of lane 32 r + p, the
       // even lane its first 64 bytes (tree keys 0..7, or the leaf's 8
       // prefixes), the odd lane the rest (keys 8..15, or the 8 destinations).
-      sh_blk[wv][lane] = want_line ? L.off + L.hi + L.lo : 0;
+      sh_line[wv][lane] =
+          want_line ? reinterpret_cast<uint64_t>(blocks + L.off + L.hi + L.lo) : 0;
       sh_x[wv][lane] = L.X;
       wave_sync();
       const uint32_t half = lane & 1u, pair = lane >> 1;
-      const uint4* base = reinterpret_cast<const uint4*>(a.g.blocks);
       uint4 q[2][4];
 #pragma unroll
       for (uint32_t r = 0; r < 2; ++r) {
@@ -195,7 +250,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) q[r][k] = make_uint4(0, 0, 0, 0);
         if ((line_mask >> owner) & 1ull) {
-          const uint4* src = base + sh_blk[wv][owner] * 8 + half * 4;
+          const uint4* src = reinterpret_cast<const uint4*>(sh_line[wv][owner]) + half * 4;
 #pragma unroll
           for (uint32_t k = 0; k < 4; ++k) q[r][k] = src[k];
         }
@@ -261,8 +316,8 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
       L.tail = line_res;
       L.len += 1;
       step = true;
-      coin = L.x2 < a.T;
-    } else if (kStitch && ph == kPool) {
+      coin = L.x2 < T;
+    } else if (ph == kPool) {
       const uint64_t e = v0;
       L.tail = static_cast<uint32_t>(e);
       L.len += static_cast<uint32_t>(e >> 32) & 0xFFFFu;
@@ -289,13 +344,13 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
     // ---- start a move at the tail with record (bw, bod) ----
     if (begin) {
       for (uint32_t restarts = 0;; ++restarts) {
-        const U4 x = philox10(L.i, L.m, L.s, 0u, a.key0, a.key1);
-        const uint32_t d = static_cast<uint32_t>(bod & kDegMask);
-        if (d == 0) {  // no out-edges: back to the head, then the coin
+        const U4 x = philox10(L.i, L.m, L.s, 0u, key0, key1);
+        const uint32_t dg = static_cast<uint32_t>(bod & kDegMask);
+        if (dg == 0) {  // no out-edges: back to the head, then the coin
           L.tail = L.s;
           L.len += 1;
           L.m += 1;
-          const bool cn = x.x2 < a.T;
+          const bool cn = x.x2 < T;
           if (cn || L.m == kMoveCap) {
             done = true;
             capped = !cn;
@@ -309,26 +364,26 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
           }
           continue;
         }
-        if (kStitch && (bod & kPoolFlag)) {
-          L.X = bw + ((static_cast<uint64_t>(x.x0) << a.K_log2) >> 32);
+        if (bod & kPoolFlag) {  // small node: its record holds the pool block address
+          L.X = bw + (((static_cast<uint64_t>(x.x0) << K_log2) >> 32) << 3);
           L.ph = kPool;
           break;
         }
         L.X = scaled_draw(x.x0, x.x1, bw);
         L.x2 = x.x2;
         L.off = bod >> kRegionShift;  // first block of the row's region
-        L.deg = d;
+        L.deg = dg;
         if (kStats) {
           ++L.st_plain;
-          L.st_log += ceil_log2_u32(d);
+          L.st_log += ceil_log2_u32(dg);
         }
         L.lo = 0;
         L.hi = 0;
-        if (d > a.g.tree_min) {
-          L.lvl = tree_levels(d);  // lo: node within the level, hi: first node of the level
+        if (dg > tree_min) {
+          L.lvl = tree_levels(dg);  // lo: node within the level, hi: first node of the level
           L.ph = kTree;
-        } else if (d > kLeafEdges) {
-          L.hi = static_cast<uint32_t>(leaf_blocks(d)) - 1;  // candidate leaf blocks [lo, hi]
+        } else if (dg > kLeafEdges) {
+          L.hi = static_cast<uint32_t>(leaf_blocks(dg)) - 1;  // candidate leaf blocks [lo, hi]
           L.ph = kBsearch;
         } else {
           L.ph = kLeaf;  // the one leaf block
@@ -339,15 +394,15 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
 
     // ---- a terminated walk writes its endpoint and frees the lane ----
     if (done) {
-      a.endpoints[L.g] = L.tail;
+      *L.ep = L.tail;
       L.ph = kIdle;
       if (kStats) {
         L.st_moves += L.m;
         L.st_steps += L.len;
-        if (capped) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats->capped), 1ull);
+        if (capped) atomicAdd(reinterpret_cast<unsigned long long*>(&t.stats->capped), 1ull);
         // one walk adds at most 2^16 moves and 2^24 steps: flush well before 2^32
         if ((L.st_steps | L.st_moves | L.st_log) >= 0x40000000u) {
-          unsigned long long* out = reinterpret_cast<unsigned long long*>(a.stats);
+          unsigned long long* out = reinterpret_cast<unsigned long long*>(t.stats);
           atomicAdd(out + 1, static_cast<unsigned long long>(L.st_moves));
           atomicAdd(out + 2, static_cast<unsigned long long>(L.st_steps));
           atomicAdd(out + 4, static_cast<unsigned long long>(L.st_moves - L.st_plain - L.st_stitch));
@@ -365,11 +420,11 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkArgs a) {
     const uint64_t dang = static_cast<uint64_t>(L.st_moves) - L.st_plain - L.st_stitch;
     const uint64_t vals[6] = {L.st_moves, L.st_steps, dang, L.st_plain, L.st_stitch, L.st_log};
     const int slot[6] = {1, 2, 4, 5, 6, 7};
-    unsigned long long* out = reinterpret_cast<unsigned long long*>(a.stats);
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(t.stats);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const uint64_t t = wave_sum_u64(vals[k]);
-      if (lane == 0 && t) atomicAdd(out + slot[k], static_cast<unsigned long long>(t));
+      const uint64_t v = wave_sum_u64(vals[k]);
+      if (lane == 0 && v) atomicAdd(out + slot[k], static_cast<unsigned long long>(v));
     }
     if (lane == 0 && walks) atomicAdd(out, static_cast<unsigned long long>(walks));
   }
@@ -381,22 +436,26 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t count, uint64_t value) {
     p[i] = value;
 }
 
-template <bool kStitch, bool kStats>
-hipError_t launch_walk_t(const WalkArgs& a, hipStream_t s) {
+__global__ void k_set_desc(WalkDesc d, WalkDesc* dst) {
+  if (threadIdx.x == 0) *dst = d;
+}
+
+template <bool kStats>
+hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t s) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStitch, kStats>, kThreads, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats>, kThreads, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
+  if (blocks_per_cu && static_cast<int>(blocks_per_cu) < per_cu) per_cu = static_cast<int>(blocks_per_cu);
   uint64_t blocks = static_cast<uint64_t>(cus) * per_cu;
-  const uint64_t need = (a.total + kThreads - 1) / kThreads;
+  const uint64_t need = (t.total + kThreads - 1) / kThreads;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_walk<kStitch, kStats>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads),
-                     0, s, a);
+  hipLaunchKernelGGL((k_walk<kStats>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, t);
   return hipGetLastError();
 }
 
@@ -410,26 +469,16 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_walk(const fppr_graph* g, const WalkLaunch& w, hipStream_t s) {
-  WalkArgs a{};
-  a.g = GraphView{g->rec, g->blocks, g->tree_min};
-  a.rec = w.rec;
-  a.sources = w.sources;
-  a.total = w.n_src * w.R;
-  a.R = w.R;
-  a.R_magic = w.R_magic;
-  a.n = g->n;
-  a.key0 = w.key0;
-  a.key1 = w.key1;
-  a.T = w.T;
-  a.pool = w.pool;
-  a.K_log2 = w.K_log2;
-  a.endpoints = w.endpoints;
-  a.work_counter = w.work_counter;
-  a.stats = w.stats;
-  if (a.total == 0) return hipSuccess;
-  if (w.stitch) return w.stats ? launch_walk_t<true, true>(a, s) : launch_walk_t<true, false>(a, s);
-  return w.stats ? launch_walk_t<false, true>(a, s) : launch_walk_t<false, false>(a, s);
+hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, s, d, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
+                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s) {
+  if (total == 0 || ndesc == 0) return hipSuccess;
+  WalkTable t{descs, ndesc, total, ctl, stats};
+  return stats ? launch_walk_t<true>(t, blocks_per_cu, s) : launch_walk_t<false>(t, blocks_per_cu, s);
 }
 
 }  // namespace fppr

@@ -68,6 +68,11 @@ class fppr_out(ctypes.Structure):
                 ("profile", ctypes.c_void_p)]
 
 
+class fppr_batch_item(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("params", fppr_params), ("sources", ctypes.c_void_p),
+                ("n_sources", ctypes.c_uint64), ("out", fppr_out)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported symbol
@@ -94,6 +99,14 @@ _SIGS = [
     ("fppr_profile_destroy", ctypes.c_int, [P]),
     ("fppr_profile_read", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
+    ("fppr_batch_plan", ctypes.c_int, [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_batch_create", ctypes.c_int, [P, ctypes.c_uint32, P, ctypes.c_uint64,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    ("fppr_batch_run", ctypes.c_int, [P, P, P, P]),
+    ("fppr_batch_capture", ctypes.c_int, [P, P, P]),
+    ("fppr_batch_launch", ctypes.c_int, [P, P]),
+    ("fppr_batch_check", ctypes.c_int, [P, P]),
+    ("fppr_batch_destroy", ctypes.c_int, [P]),
     ("fppr_last_error", ctypes.c_char_p, []),
 ]
 
@@ -332,3 +345,74 @@ def run(graph: Graph, alpha, R, seed, sources=None, topk=0, stitch=False, counts
         fppr_run_check(ws, stream)
     out._workspace = ws
     return out
+
+
+class Batch:
+    """Several (graph, params, sources) items in one persistent walk launch.
+    items: list of dicts with keys graph (Graph), alpha, R, seed, topk,
+    stitch, sources (None or int sequence), counts, digests. Outputs are
+    allocated here (torch) as Outputs objects in `self.outputs`."""
+
+    def __init__(self, items, counts=True, digests=True, stats=True):
+        import torch
+
+        self._keep = []
+        arr = (fppr_batch_item * len(items))()
+        self.outputs = []
+        for k, it in enumerate(items):
+            G = it["graph"]
+            if it.get("sources") is None:
+                src, n_src = None, G.n
+            else:
+                src = torch.as_tensor(np.asarray(it["sources"], dtype=np.uint32).view(np.int32)).cuda()
+                n_src = int(src.numel())
+            p = make_params(it["alpha"], it["R"], it["seed"], it.get("topk", 0), it.get("stitch", False),
+                            counts, digests, False)
+            o = alloc_outputs(n_src, it["R"], it.get("topk", 0), counts, digests, False)
+            self.outputs.append(o)
+            self._keep.append((G, src))
+            arr[k].graph = G.handle
+            arr[k].params = p
+            arr[k].sources = _dptr(src)
+            arr[k].n_sources = n_src
+            arr[k].out = fppr_out(_dptr(o.topk), _dptr(o.counts), _dptr(o.n_distinct), _dptr(o.digest),
+                                  None, None, None)
+        self._items = arr
+        ws = ctypes.c_uint64()
+        _check(lib().fppr_batch_plan(arr, len(items), ctypes.byref(ws)))
+        self.workspace = torch.empty((ws.value + 7) // 8, dtype=torch.int64, device="cuda")
+        self.stats = torch.zeros(8, dtype=torch.int64, device="cuda") if stats else None
+        h = ctypes.c_void_p()
+        _check(lib().fppr_batch_create(arr, len(items), _dptr(self.workspace), ws.value, ctypes.byref(h)))
+        self._h = h
+
+    def stats_dict(self):
+        if self.stats is None:
+            return None
+        v = self.stats.cpu().numpy().astype(np.uint64)
+        return {k: int(x) for k, x in zip(STATS_FIELDS, v)}
+
+    def run(self, stream=None, profile=None):
+        _check(lib().fppr_batch_run(self._h, _dptr(self.stats),
+                                    profile.handle if profile is not None else None,
+                                    _stream_ptr(stream)))
+
+    def capture(self, stream):
+        _check(lib().fppr_batch_capture(self._h, _dptr(self.stats), _stream_ptr(stream)))
+
+    def launch(self, stream=None):
+        _check(lib().fppr_batch_launch(self._h, _stream_ptr(stream)))
+
+    def check(self, stream=None):
+        _check(lib().fppr_batch_check(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fppr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,142 @@
+"""Batches through the C-ABI: one persistent walk launch over several graphs
+and source sets gives every item exactly its plain-run (and oracle) result;
+a captured HIP graph replays to the same results."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import torch
+
+    from paper_1903_11749_amd import fppr
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fppr.lib()
+    return fppr
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.fixture(scope="module")
+def items(fp):
+    """Six items of uneven size: different graphs, alphas, walk budgets,
+    source subsets, plain and stitched."""
+    specs = [
+        (synth.chung_lu(3000, 30000, 2.1, 255, seed=2001), 0.1, 64, 11, 8, None, False),
+        (synth.chung_lu(500, 4000, 2.5, 255, seed=2002), 0.2, 256, 12, 16, None, True),
+        (synth.chung_lu(20000, 300000, 2.3, 255, seed=2003), 0.15, 64, 13, 32,
+         np.arange(0, 20000, 7, dtype=np.uint32), False),
+        (synth.small_graph(), 0.2, 100, 1, 16, None, False),
+        (synth.chung_lu(1000, 9000, 2.2, 255, seed=2004), 0.15, 33, 14, 5,
+         np.array([3, 999, 3, 0, 500], dtype=np.uint32), True),
+        (synth.chung_lu(64, 300, 2.1, 255, seed=2005), 0.1, 256, 15, 64, None, False),
+    ]
+    out = []
+    for g, alpha, R, seed, k, src, stitch in specs:
+        G = fp.Graph(g)
+        if stitch:
+            G.build_pool(S=16, L=3, K=32, alpha=alpha, seed=seed + 100)
+        out.append(dict(csr=g, graph=G, alpha=alpha, R=R, seed=seed, topk=k, sources=src,
+                        stitch=stitch))
+    return out
+
+
+def test_batch_equals_plain_and_oracle(fp, items):
+    import torch
+
+    say("case: batch of 6 items vs plain runs and the oracle")
+    B = fp.Batch(items)
+    B.run()
+    B.check()
+    total_walks = 0
+    for it, ob in zip(items, B.outputs):
+        op = fp.run(it["graph"], it["alpha"], it["R"], it["seed"], sources=it["sources"],
+                    topk=it["topk"], stitch=it["stitch"])
+        torch.cuda.synchronize()
+        for name in ("counts", "n_distinct", "topk"):
+            assert np.array_equal(u32(getattr(ob, name)), u32(getattr(op, name))), name
+        assert np.array_equal(u64(ob.digest), u64(op.digest))
+        og = O.Graph.from_csr(it["csr"])
+        pool = None
+        if it["stitch"]:
+            pool = O.Pool(og, S=16, L=3, K=32, alpha=it["alpha"], seed=it["seed"] + 100)
+        ref = O.run(og, it["alpha"], it["R"], it["seed"], sources=it["sources"], topk=it["topk"],
+                    pool=pool)
+        assert np.array_equal(u32(ob.counts), ref.counts)
+        assert np.array_equal(u32(ob.topk), ref.topk)
+        assert np.array_equal(u64(ob.digest), ref.digest)
+        total_walks += ref.stats["walks"]
+    assert B.stats_dict()["walks"] == total_walks
+    B.close()
+
+
+def test_batch_capture_replays_match_eager(fp, items):
+    """The captured graph is replayed several times with eager work and
+    synchronisations between replays; every replay reproduces the eager
+    results (outputs are overwritten with junk before each replay)."""
+    import torch
+
+    say("case: batch capture + replays")
+    B = fp.Batch(items)
+    B.run()
+    torch.cuda.synchronize()
+    want = [(u32(o.counts).copy(), u32(o.topk).copy(), u64(o.digest).copy()) for o in B.outputs]
+    stream = torch.cuda.Stream()
+    B.capture(stream)
+    for rep in range(3):
+        for o in B.outputs:
+            o.counts.fill_(-1)
+            o.topk.fill_(-1)
+            o.digest.fill_(-1)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        B.launch(stream)
+        stream.synchronize()
+        for (c, t, d), o in zip(want, B.outputs):
+            assert np.array_equal(u32(o.counts), c), rep
+            assert np.array_equal(u32(o.topk), t), rep
+            assert np.array_equal(u64(o.digest), d), rep
+        del junk
+    B.close()
+
+
+def test_batch_workload_smallest_graphs_vs_oracle(fp):
+    """The 64-graph batch workload: the 8 smallest graphs in one batch, each
+    checked against the oracle."""
+    import torch
+
+    say("case: batch workload, 8 smallest graphs")
+    specs = sorted(synth.batch_specs(), key=lambda s: s["n"])[:8]
+    its = []
+    for sp in specs:
+        g = synth.batch_graph(sp)
+        its.append(dict(csr=g, graph=fp.Graph(g), alpha=sp["alpha"], R=sp["R"],
+                        seed=sp["walk_seed"], topk=16, sources=None, stitch=False))
+    B = fp.Batch(its, counts=False)
+    B.run()
+    torch.cuda.synchronize()
+    for it, o in zip(its, B.outputs):
+        ref = O.run(O.Graph.from_csr(it["csr"]), it["alpha"], it["R"], it["seed"], topk=16,
+                    want_counts=False)
+        assert np.array_equal(u32(o.topk), ref.topk)
+        assert np.array_equal(u64(o.digest), ref.digest)
+    B.close()
