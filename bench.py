@@ -77,12 +77,161 @@ def counted_traffic():
     return int(vals["walk_traffic_bytes_per_launch"])
 
 
+BATCH_TOPK = 16
+BATCH_POOLS = [dict(S=32, L=3, K=64), dict(S=16, L=2, K=32)]
+BATCH_HUB_THRESHOLDS = [8, 64, 0xFFFFFFFF]
+BATCH_BLOCKS_PER_CU = [0, 2]
+
+
+def bench_batch(args, fppr, torch, np):
+    """The 64-graph batch: autotune each graph, then time one captured replay
+    of the whole batch (every graph's rebuild and pool, one walk launch, every
+    graph's counting and top-k) against the same work as 64 plain per-graph
+    launches in sequence; both must give bit-identical outputs. Everything,
+    torch's own fills included, runs on one stream other than the null stream
+    (which capture needs)."""
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        res = _bench_batch(args, fppr, torch, np, stream)
+    torch.cuda.synchronize()
+    return res
+
+
+def _bench_batch(args, fppr, torch, np, stream):
+    import collections
+
+    import synth
+
+    t0 = time.time()
+    specs = synth.batch_specs()
+    graphs = [synth.batch_graph(sp) for sp in specs]
+    log(f"batch: generated {len(graphs)} graphs, {sum(g.n for g in graphs)} nodes, "
+        f"{sum(g.m for g in graphs)} edges in {time.time() - t0:.1f}s")
+    Gs, manifest = [], []
+    t0 = time.time()
+    for sp, g in zip(specs, graphs):
+        G = fppr.Graph(g)
+        pools = [dict(o, seed=6000 + sp["index"]) for o in BATCH_POOLS]
+        r = G.autotune(sp["alpha"], sp["R"], sp["walk_seed"], hub_thresholds=BATCH_HUB_THRESHOLDS,
+                       blocks_per_cu=BATCH_BLOCKS_PER_CU, pools=pools, stream=stream)
+        Gs.append(G)
+        manifest.append(dict(graph=sp["index"], n=g.n, m=g.m, alpha=sp["alpha"], R=sp["R"],
+                             walk_seed=sp["walk_seed"], hub_threshold=r["hub_threshold"],
+                             blocks_per_cu=r["blocks_per_cu"], pool=r["pool_opts"],
+                             est_ms=round(r["est_ms"], 4), plain_est_ms=round(r["plain_est_ms"], 4)))
+    tune_s = time.time() - t0
+    log(f"batch: tuned {len(Gs)} graphs in {tune_s:.1f}s")
+    width = collections.Counter(m["blocks_per_cu"] for m in manifest).most_common(1)[0][0]
+    items = [dict(graph=G, alpha=sp["alpha"], R=sp["R"], seed=sp["walk_seed"], topk=BATCH_TOPK,
+                  stitch=m["pool"] is not None, sources=None)
+             for G, sp, m in zip(Gs, specs, manifest)]
+    B = fppr.Batch(items, counts=False, digests=True, stats=True, rebuild=True, blocks_per_cu=width)
+    B.capture(stream)
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(max(1, args.warmup)):
+        B.launch(stream)
+    B.check(stream)
+    steps, ms = 0, []
+    for i in range(args.steps):
+        B.stats.zero_()
+        e0.record(stream)
+        B.launch(stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        steps = B.stats_dict()["steps"]
+    B.check(stream)
+    walks = B.stats_dict()["walks"]
+    batch_ms = float(np.median(ms))
+    log(f"batch: captured replay {batch_ms:.1f} ms (median of {len(ms)})")
+
+    # the same work as plain launches, one graph after the other
+    plain = []
+    for G, it in zip(Gs, items):
+        p = fppr.make_params(it["alpha"], it["R"], it["seed"], BATCH_TOPK, it["stitch"], counts=False,
+                             digests=True, stats=False,
+                             blocks_per_cu=manifest[len(plain)]["blocks_per_cu"])
+        ws = torch.empty((fppr.fppr_plan(G, p, G.n) + 7) // 8, dtype=torch.int64, device="cuda")
+        out = fppr.alloc_outputs(G.n, it["R"], BATCH_TOPK, counts=False, digests=True, stats=False)
+        plain.append((G, p, ws, out))
+
+    def plain_step():
+        for G, p, ws, out in plain:
+            G.rebuild(stream)
+            fppr.fppr_run(G, p, None, G.n, ws, out, stream)
+
+    for _ in range(max(1, args.warmup)):
+        plain_step()
+    torch.cuda.synchronize()
+    pms = []
+    for i in range(args.steps):
+        e0.record(stream)
+        plain_step()
+        e1.record(stream)
+        e1.synchronize()
+        pms.append(e0.elapsed_time(e1))
+    plain_ms = float(np.median(pms))
+    log(f"batch: 64 plain launches {plain_ms:.1f} ms (median of {len(pms)})")
+    for G, p, ws, out in plain:
+        fppr.fppr_run_check(ws, stream)
+        G.check(stream)
+    same = all(torch.equal(a.digest, b[3].digest) and torch.equal(a.topk, b[3].topk)
+               for a, b in zip(B.outputs, plain))
+
+    # oracle on the smallest graphs
+    from oracle import oracle as O
+
+    small = sorted(range(len(specs)), key=lambda i: specs[i]["n"])[:4]
+    oracle_ok = True
+    for i in small:
+        og = O.Graph.from_csr(graphs[i])
+        pool = None
+        if manifest[i]["pool"] is not None:
+            po = manifest[i]["pool"]
+            pool = O.Pool(og, S=po["S"], L=po["L"], K=po["K"], alpha=specs[i]["alpha"], seed=po["seed"])
+        ref = O.run(og, specs[i]["alpha"], specs[i]["R"], specs[i]["walk_seed"], topk=BATCH_TOPK,
+                    pool=pool, want_counts=False)
+        got = B.outputs[i]
+        oracle_ok &= bool(np.array_equal(got.digest.cpu().numpy().view(np.uint64), ref.digest)
+                          and np.array_equal(got.topk.cpu().numpy().view(np.uint32), ref.topk))
+    n_src = sum(g.n for g in graphs)
+    if args.manifest:
+        with open(args.manifest, "w") as fh:
+            json.dump(dict(graphs=manifest, batch_blocks_per_cu=width), fh, indent=1)
+    res = {
+        "workload": ("64 directed Chung-Lu graphs, n log-uniform in [1e3, 1e6], mean degree U[8,24], "
+                     "exponent U[2.1,2.5], weights U{1..255}, alpha in {.1,.15,.2}, R in {64,256}, "
+                     f"all sources, top-{BATCH_TOPK}"),
+        "graphs": len(graphs), "sources": n_src, "walks": walks, "walk_steps": steps,
+        "batched_ms": round(batch_ms, 3), "plain_ms": round(plain_ms, 3),
+        "batched_walk_steps_per_s": round(steps / (batch_ms / 1e3), 1),
+        "plain_walk_steps_per_s": round(steps / (plain_ms / 1e3), 1),
+        "batched_sources_per_s": round(n_src / (batch_ms / 1e3), 1),
+        "plain_sources_per_s": round(n_src / (plain_ms / 1e3), 1),
+        "speedup": round(plain_ms / batch_ms, 3),
+        "bit_exact_vs_plain": bool(same), "oracle_bit_exact_smallest4": bool(oracle_ok),
+        "tuning_s": round(tune_s, 2),
+        "tuned": {"stitched_graphs": sum(m["pool"] is not None for m in manifest),
+                  "hub_thresholds": dict(collections.Counter(str(m["hub_threshold"]) for m in manifest)),
+                  "launch_blocks_per_cu": width},
+    }
+    B.close()
+    for G in Gs:
+        G.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["scale24", "medium"], default="scale24")
+    ap.add_argument("--workload", choices=["scale24", "medium", "batch"], default="scale24")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-graph batched-vs-plain comparison of the default run")
+    ap.add_argument("--manifest", default="", help="write the batch autotuner's choices here (JSON)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")
@@ -116,6 +265,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nb, "copies": 3}), flush=True)
+        return
+
+    if args.workload == "batch":
+        res = bench_batch(args, fppr, torch, np)
+        print(json.dumps({
+            "metric": METRIC, "value": res["batched_walk_steps_per_s"], "unit": "walk-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["batched_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32/u64 integer", "data": "synthetic (seeded Chung-Lu graphs)",
+            "config": {"workload": res["workload"]}, "batched": res}), flush=True)
         return
 
     if args.workload == "scale24":
@@ -251,6 +410,8 @@ def main():
             result["parity_sample"] = {"sources": len(sample), "bit_exact": ok}
             if not ok:
                 log("PARITY MISMATCH on the sampled sources")
+    if args.workload == "scale24" and not args.no_batch:
+        result["batched"] = bench_batch(args, fppr, torch, np)
     print(json.dumps(result), flush=True)
 
 

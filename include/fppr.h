@@ -87,13 +87,14 @@ typedef struct {
 
 typedef struct {
   /* Rows with more than hub_threshold out-edges (the large nodes of Sec. 4.1)
-   * carry an 8-ary prefix tree, the integer counterpart of the alias tree
-   * (Algorithm 3, Lemma 1): the row is cut into groups of 8 edges whose
-   * running totals form the next level, recursively, and a pick descends
-   * one 64-byte node per level. It returns exactly the edge a flat search
-   * returns, so the threshold never changes results. 0 selects 8 (the
-   * fastest); values below 8 act as 8; UINT32_MAX disables trees (rows of
-   * more than 8 edges are then binary-searched). */
+   * carry a 16-ary prefix tree, the integer counterpart of the alias tree
+   * (Algorithm 3, Lemma 1): the row is cut into blocks of 8 edges whose
+   * running totals form the next level, 16 keys to a 128-byte node,
+   * recursively, and a pick descends one node per level. It returns exactly
+   * the edge a flat search returns, so the threshold never changes results.
+   * 0 selects 8 (the fastest on the graphs measured); values below 8 act as
+   * 8; UINT32_MAX disables trees (rows of more than 8 edges are then
+   * binary-searched over their 8-edge blocks). */
   uint32_t hub_threshold;
 } fppr_graph_opts;
 
@@ -114,6 +115,11 @@ FPPR_API fppr_status fppr_graph_destroy(fppr_graph* g);
  * rewritten in place; row_offsets must be unchanged. Validation failures are
  * recorded on the device and reported by fppr_graph_check. */
 FPPR_API fppr_status fppr_graph_rebuild(fppr_graph* g, void* stream);
+
+/* Lays the graph out again for another hub threshold (same meaning as
+ * fppr_graph_opts.hub_threshold) and rebuilds the pool if one was built.
+ * Results never change. Synchronous; may reallocate the row regions. */
+FPPR_API fppr_status fppr_graph_set_hub_threshold(fppr_graph* g, uint32_t hub_threshold, void* stream);
 
 /* Synchronises `stream` and reports a validation failure recorded by
  * fppr_graph_rebuild (INVALID_ARGUMENT) or FPPR_OK. */
@@ -174,6 +180,9 @@ typedef struct {
   uint64_t seed;   /* Philox key */
   uint32_t topk;   /* k largest counts per source, 0 <= k <= R and k <= 1024 */
   uint32_t flags;  /* FPPR_* bits */
+  uint32_t blocks_per_cu; /* walk-launch width: 256-thread workgroups per
+                             compute unit, 0 = as many as fit; never changes
+                             results */
 } fppr_params;
 
 /* Counters accumulated over a run (device memory, 8 x uint64, added to; the
@@ -256,18 +265,33 @@ typedef struct {
   fppr_out out;              /* device outputs of this item (profile ignored) */
 } fppr_batch_item;
 
+enum {
+  FPPR_BATCH_REBUILD = 1u  /* each run of the batch first rebuilds every
+                              distinct graph of its items (fppr_graph_rebuild:
+                              prefixes, records, trees, pool), on the same
+                              stream, so the captured sequence is the whole
+                              path */
+};
+
+typedef struct {
+  uint32_t flags;          /* FPPR_BATCH_* bits */
+  uint32_t blocks_per_cu;  /* width of the one walk launch (0 = as many as
+                              fit); the items' own blocks_per_cu are ignored */
+} fppr_batch_opts;
+
 /* Workspace bytes for a batch (control words, the walk table, one endpoint
  * buffer per item). Pure host computation. */
 FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t count,
                                      uint64_t* workspace_bytes);
 
 /* Validates every item as fppr_run would, lays out `workspace` (device,
- * >= fppr_batch_plan bytes) and uploads the walk table (synchronous). Items
+ * >= fppr_batch_plan bytes) and uploads the walk table (synchronous); opts
+ * may be NULL (no rebuild, full width). Items
  * are ordered by decreasing walk count in the table. The batch keeps a copy
  * of `items`; graphs, sources, outputs and the workspace must outlive it. */
 FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t count,
-                                       void* workspace, uint64_t workspace_bytes,
-                                       fppr_batch** out);
+                                       const fppr_batch_opts* opts, void* workspace,
+                                       uint64_t workspace_bytes, fppr_batch** out);
 
 /* Enqueues the batch on `stream`: one persistent walk launch over every
  * item's walks, then each item's counting and top-k. `stats` (device, may be
@@ -283,9 +307,59 @@ FPPR_API fppr_status fppr_batch_run(fppr_batch* b, fppr_stats* stats, fppr_profi
 FPPR_API fppr_status fppr_batch_capture(fppr_batch* b, fppr_stats* stats, void* stream);
 FPPR_API fppr_status fppr_batch_launch(fppr_batch* b, void* stream);
 
-/* Synchronises `stream`; INVALID_ARGUMENT if a batch run met a source id >= n. */
+/* Synchronises `stream`; INVALID_ARGUMENT if a batch run met a source id >= n
+ * or (FPPR_BATCH_REBUILD) a graph failed its rebuild's validation. */
 FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream);
 FPPR_API fppr_status fppr_batch_destroy(fppr_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Autotuner. The paper sizes its pipelines from cluster memory and checks the
+ * choice by experiment (Sec. 4.3, the gamma analysis; Sec. 5); here the knobs
+ * are picked per graph by timed trial runs on a sample of sources:
+ *  - hub threshold and walk-launch width, which never change results;
+ *  - the short-walk pool (or none), which does: the chosen candidate is
+ *    reported so that every other run of that graph, and any checker, uses
+ *    the same one.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  const uint32_t* hub_thresholds;  /* host [n_hub_thresholds] candidates, or NULL
+                                      (keep the graph's) */
+  uint32_t n_hub_thresholds;
+  const uint32_t* blocks_per_cu;   /* host [n_blocks_per_cu] candidates, or NULL
+                                      (0 = as many as fit) */
+  uint32_t n_blocks_per_cu;
+  const fppr_pool_opts* pools;     /* host [n_pools] short-walk candidates (their
+                                      alpha is replaced by the run's) */
+  uint32_t n_pools;
+  uint32_t allow_plain;            /* nonzero: runs without stitching compete too
+                                      (always the case when n_pools == 0) */
+  uint64_t n_sources;              /* sources of the real run (0 = n), for the
+                                      cost estimate */
+  uint32_t sample;                 /* trial sources, evenly spread over the
+                                      nodes (0 = min(n, 65536)) */
+  uint32_t reps;                   /* timed repetitions per trial, best kept
+                                      (0 = 3) */
+} fppr_tune_space;
+
+typedef struct {
+  uint32_t hub_threshold;  /* chosen (the graph is left laid out with it) */
+  uint32_t blocks_per_cu;  /* chosen launch width */
+  int32_t pool;            /* index of the chosen pool candidate (the graph
+                              keeps that pool), or -1 = plain walks (the graph
+                              keeps no pool) */
+  uint32_t trials;         /* configurations timed */
+  double est_ms;           /* estimated run: pool build + walks scaled from the
+                              sample to n_sources */
+  double plain_est_ms;     /* the same estimate for plain walks at the chosen
+                              threshold and width (0 if not timed) */
+} fppr_tune_result;
+
+/* Times the candidates (one coordinate at a time: hub threshold with plain
+ * walks, then launch width, then the pools) with p's alpha, R and seed; p's
+ * flags, topk and blocks_per_cu are ignored. Leaves the graph in the chosen
+ * configuration. Synchronous; allocates trial buffers for its own use. */
+FPPR_API fppr_status fppr_autotune(fppr_graph* g, const fppr_params* p, const fppr_tune_space* space,
+                                   fppr_tune_result* result, void* stream);
 
 /* Synchronises `stream` and reports whether a run that used `workspace` met
  * a source id >= n (INVALID_ARGUMENT; such a source gets no walks and its

@@ -31,6 +31,8 @@ uint64_t item_sources(const fppr_batch_item& it) {
 
 struct fppr_batch {
   std::vector<fppr_batch_item> items;
+  fppr_batch_opts opts{};
+  std::vector<fppr_graph*> graphs;    // distinct graphs of the items
   std::vector<WalkDesc> host_table;
   std::vector<uint32_t*> endpoints;   // per item
   unsigned long long* ctl = nullptr;  // in the workspace
@@ -70,10 +72,17 @@ void free_batch(fppr_batch* b) {
 }
 
 fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStream_t s) {
+  if (b->opts.flags & FPPR_BATCH_REBUILD) {
+    for (fppr_graph* g : b->graphs) {
+      const fppr_status st = fppr_graph_rebuild(g, s);
+      if (st != FPPR_OK) return st;
+    }
+  }
   hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(b->ctl), kCtlBytes / 8, s);
   if (e != hipSuccess) return hip_fail(e, "zero control words");
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
-  e = launch_walk(b->table, static_cast<uint32_t>(b->host_table.size()), b->total, b->ctl, stats, 0, s);
+  e = launch_walk(b->table, static_cast<uint32_t>(b->host_table.size()), b->total, b->ctl, stats,
+                  b->opts.blocks_per_cu, s);
   if (e != hipSuccess) return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
@@ -104,16 +113,21 @@ FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t coun
 }
 
 FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t count,
-                                       void* workspace, uint64_t workspace_bytes,
-                                       fppr_batch** out) {
+                                       const fppr_batch_opts* opts, void* workspace,
+                                       uint64_t workspace_bytes, fppr_batch** out) {
   if (!out) return invalid("out is NULL");
   *out = nullptr;
   uint64_t need = 0;
   fppr_status st = fppr_batch_plan(items, count, &need);
   if (st != FPPR_OK) return st;
   if (!workspace || workspace_bytes < need) return invalid("workspace missing or smaller than fppr_batch_plan");
+  if (opts && (opts->flags & ~static_cast<uint32_t>(FPPR_BATCH_REBUILD))) return invalid("unknown batch flag bits");
   auto* b = new fppr_batch();
   b->items.assign(items, items + count);
+  if (opts) b->opts = *opts;
+  for (uint32_t k = 0; k < count; ++k)
+    if (std::find(b->graphs.begin(), b->graphs.end(), items[k].graph) == b->graphs.end())
+      b->graphs.push_back(items[k].graph);
   char* base = static_cast<char*>(workspace);
   b->ctl = reinterpret_cast<unsigned long long*>(base);
   b->table = reinterpret_cast<WalkDesc*>(base + kCtlBytes);
@@ -201,6 +215,12 @@ FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream) {
   e = hipMemcpy(ctl, b->ctl, sizeof ctl, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "read batch status");
   if (ctl[1]) return invalid("a source id was >= n (its walks were skipped)");
+  if (b->opts.flags & FPPR_BATCH_REBUILD) {
+    for (size_t k = 0; k < b->graphs.size(); ++k) {
+      if (fppr_graph_check(b->graphs[k], stream) != FPPR_OK)
+        return invalid("graph " + std::to_string(k) + " of the batch failed its rebuild: " + fppr_last_error());
+    }
+  }
   return FPPR_OK;
 }
 

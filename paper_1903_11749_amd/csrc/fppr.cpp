@@ -129,6 +129,16 @@ bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+void drop_pool(fppr_graph* g) {
+  if (!g->pool) return;
+  (void)hipDeviceSynchronize();
+  g->device_bytes -= align_up(g->pool_cap * 8);
+  dfree(g->pool);
+  g->pool_cap = 0;
+  g->has_pool = false;
+  g->n_small = 0;
+}
+
 fppr_status hip_fail(hipError_t e, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   return e == hipErrorOutOfMemory ? FPPR_OUT_OF_MEMORY : FPPR_DEVICE_ERROR;
@@ -394,6 +404,39 @@ FPPR_API fppr_status fppr_graph_rebuild(fppr_graph* g, void* stream) {
   return FPPR_OK;
 }
 
+FPPR_API fppr_status fppr_graph_set_hub_threshold(fppr_graph* g, uint32_t hub_threshold, void* stream) {
+  if (!g) return invalid("graph is NULL");
+  uint32_t H = hub_threshold ? hub_threshold : kLeafEdges;
+  if (H < kLeafEdges) H = kLeafEdges;
+  if (H == g->tree_min) return FPPR_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+  g->tree_min = H;
+  if ((e = zero_ctl(g, s)) != hipSuccess) return hip_fail(e, "zero control words");
+  if ((e = launch_region_sizes(g, s)) != hipSuccess) return hip_fail(e, "region sizes");
+  Ctl c{};
+  if ((e = read_ctl(g, s, &c)) != hipSuccess) return hip_fail(e, "read region sizes");
+  if (c.blocks != g->n_blocks) {
+    g->device_bytes -= align_up(g->n_blocks * sizeof(Block));
+    dfree(g->blocks);
+    g->n_blocks = 0;
+    if ((e = dmalloc(&g->blocks, c.blocks, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(blocks)");
+    g->n_blocks = c.blocks;
+  }
+  if ((e = launch_leaves(g, s)) != hipSuccess) return hip_fail(e, "leaf blocks");
+  if ((e = launch_trees(g, s)) != hipSuccess) return hip_fail(e, "prefix trees");
+  if ((e = read_ctl(g, s, &c)) != hipSuccess) return hip_fail(e, "read build status");
+  if (c.err) return invalid("graph build failed:" + err_bits(c.err));
+  g->n_tree = c.n_tree;
+  if (g->has_pool) {
+    fppr_status st = pool_kernels(g, s);
+    if (st != FPPR_OK) return st;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+  }
+  return FPPR_OK;
+}
+
 FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream) {
   if (!g) return invalid("graph is NULL");
   Ctl c{};
@@ -458,7 +501,8 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
   fppr_stats* stats = (p->flags & FPPR_STATS) ? out->stats : nullptr;
   fppr_profile* prof = out->profile;
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = launch_walk(desc, 1, total, ctl, stats, 0, s)) != hipSuccess) return hip_fail(e, "walk kernel");
+  if ((e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
+    return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
   const AggLaunch a = make_agg(p, endpoints, sources, n_sources, out);
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");

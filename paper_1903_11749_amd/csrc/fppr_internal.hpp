@@ -67,6 +67,8 @@ void set_error(const std::string& msg);
 fppr_status hip_fail(hipError_t e, const char* what);
 fppr_status check_params(const fppr_graph* g, const fppr_params* p);
 fppr_status check_outputs(const fppr_params* p, const fppr_out* out);
+// frees the pool (the graph then has none)
+void drop_pool(fppr_graph* g);
 
 // build.hip
 hipError_t launch_validate(const fppr_graph* g, hipStream_t s);

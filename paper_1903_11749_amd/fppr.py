@@ -29,6 +29,7 @@ FPPR_STITCH = 1
 FPPR_COUNTS = 2
 FPPR_DIGESTS = 4
 FPPR_STATS = 8
+FPPR_BATCH_REBUILD = 1
 FPPR_MOVE_CAP = 65536
 FPPR_NO_NODE = 0xFFFFFFFF
 
@@ -58,7 +59,8 @@ class fppr_pool_opts(ctypes.Structure):
 
 class fppr_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("R", ctypes.c_uint32), ("seed", ctypes.c_uint64),
-                ("topk", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("topk", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32)]
 
 
 class fppr_out(ctypes.Structure):
@@ -73,6 +75,24 @@ class fppr_batch_item(ctypes.Structure):
                 ("n_sources", ctypes.c_uint64), ("out", fppr_out)]
 
 
+class fppr_batch_opts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+
+
+class fppr_tune_space(ctypes.Structure):
+    _fields_ = [("hub_thresholds", ctypes.c_void_p), ("n_hub_thresholds", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_void_p), ("n_blocks_per_cu", ctypes.c_uint32),
+                ("pools", ctypes.c_void_p), ("n_pools", ctypes.c_uint32),
+                ("allow_plain", ctypes.c_uint32), ("n_sources", ctypes.c_uint64),
+                ("sample", ctypes.c_uint32), ("reps", ctypes.c_uint32)]
+
+
+class fppr_tune_result(ctypes.Structure):
+    _fields_ = [("hub_threshold", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("pool", ctypes.c_int32), ("trials", ctypes.c_uint32),
+                ("est_ms", ctypes.c_double), ("plain_est_ms", ctypes.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported symbol
@@ -82,6 +102,7 @@ _SIGS = [
                                          ctypes.POINTER(ctypes.c_void_p)]),
     ("fppr_graph_destroy", ctypes.c_int, [P]),
     ("fppr_graph_rebuild", ctypes.c_int, [P, P]),
+    ("fppr_graph_set_hub_threshold", ctypes.c_int, [P, ctypes.c_uint32, P]),
     ("fppr_graph_check", ctypes.c_int, [P, P]),
     ("fppr_graph_info", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
@@ -100,13 +121,15 @@ _SIGS = [
     ("fppr_profile_read", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
     ("fppr_batch_plan", ctypes.c_int, [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
-    ("fppr_batch_create", ctypes.c_int, [P, ctypes.c_uint32, P, ctypes.c_uint64,
-                                         ctypes.POINTER(ctypes.c_void_p)]),
+    ("fppr_batch_create", ctypes.c_int, [P, ctypes.c_uint32, ctypes.POINTER(fppr_batch_opts), P,
+                                         ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
     ("fppr_batch_run", ctypes.c_int, [P, P, P, P]),
     ("fppr_batch_capture", ctypes.c_int, [P, P, P]),
     ("fppr_batch_launch", ctypes.c_int, [P, P]),
     ("fppr_batch_check", ctypes.c_int, [P, P]),
     ("fppr_batch_destroy", ctypes.c_int, [P]),
+    ("fppr_autotune", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.POINTER(fppr_tune_space),
+                                     ctypes.POINTER(fppr_tune_result), P]),
     ("fppr_last_error", ctypes.c_char_p, []),
 ]
 
@@ -224,6 +247,35 @@ class Graph:
     def rebuild(self, stream=None):
         _check(lib().fppr_graph_rebuild(self._h, _stream_ptr(stream)))
 
+    def set_hub_threshold(self, hub_threshold: int, stream=None):
+        _check(lib().fppr_graph_set_hub_threshold(self._h, int(hub_threshold), _stream_ptr(stream)))
+
+    def autotune(self, alpha, R, seed, hub_thresholds=None, blocks_per_cu=None, pools=(),
+                 allow_plain=True, n_sources=0, sample=0, reps=0, stream=None):
+        """Runs the library's autotuner (fppr_autotune). pools: sequence of
+        dicts with S, L, K, seed. Returns the chosen configuration as a dict;
+        the graph is left in it (pool built, or none)."""
+        hs = np.asarray(hub_thresholds if hub_thresholds is not None else [], dtype=np.uint32)
+        bs = np.asarray(blocks_per_cu if blocks_per_cu is not None else [], dtype=np.uint32)
+        parr = (fppr_pool_opts * max(1, len(pools)))()
+        for k, o in enumerate(pools):
+            parr[k] = fppr_pool_opts(o["S"], o["L"], o["K"], float(alpha), o["seed"])
+        sp = fppr_tune_space(hs.ctypes.data if hs.size else None, hs.size,
+                             bs.ctypes.data if bs.size else None, bs.size,
+                             ctypes.cast(parr, ctypes.c_void_p) if len(pools) else None, len(pools),
+                             1 if allow_plain else 0, int(n_sources), int(sample), int(reps))
+        p = make_params(alpha, R, seed, 0, False, False, False, False)
+        r = fppr_tune_result()
+        _check(lib().fppr_autotune(self._h, ctypes.byref(p), ctypes.byref(sp), ctypes.byref(r),
+                                   _stream_ptr(stream)))
+        chosen = dict(pools[r.pool]) if r.pool >= 0 else None
+        if chosen is not None:
+            self.pool_opts = dict(chosen, alpha=float(alpha))
+        else:
+            self.pool_opts = None
+        return dict(hub_threshold=r.hub_threshold, blocks_per_cu=r.blocks_per_cu, pool=r.pool,
+                    pool_opts=chosen, trials=r.trials, est_ms=r.est_ms, plain_est_ms=r.plain_est_ms)
+
     def check(self, stream=None):
         _check(lib().fppr_graph_check(self._h, _stream_ptr(stream)))
 
@@ -239,10 +291,11 @@ class Graph:
             pass
 
 
-def make_params(alpha, R, seed, topk=0, stitch=False, counts=True, digests=True, stats=True):
+def make_params(alpha, R, seed, topk=0, stitch=False, counts=True, digests=True, stats=True,
+                blocks_per_cu=0):
     flags = (FPPR_STITCH if stitch else 0) | (FPPR_COUNTS if counts else 0) | \
         (FPPR_DIGESTS if digests else 0) | (FPPR_STATS if stats else 0)
-    return fppr_params(float(alpha), int(R), int(seed), int(topk), flags)
+    return fppr_params(float(alpha), int(R), int(seed), int(topk), flags, int(blocks_per_cu))
 
 
 def fppr_plan(graph: Graph, params: fppr_params, n_sources: int) -> int:
@@ -323,7 +376,7 @@ def fppr_run_check(workspace, stream=None):
 
 
 def run(graph: Graph, alpha, R, seed, sources=None, topk=0, stitch=False, counts=True,
-        digests=True, stats=True, endpoints=False, stream=None, check=True) -> Outputs:
+        digests=True, stats=True, endpoints=False, stream=None, check=True, blocks_per_cu=0) -> Outputs:
     """Allocates workspace and outputs with torch, runs, and returns the outputs
     (device tensors). sources: None (all nodes) or an int sequence / tensor."""
     import torch
@@ -336,7 +389,7 @@ def run(graph: Graph, alpha, R, seed, sources=None, topk=0, stitch=False, counts
                               if not isinstance(sources, torch.Tensor) else sources)
         src = src.to(device="cuda", dtype=torch.int32).contiguous()
         n_src = int(src.numel())
-    p = make_params(alpha, R, seed, topk, stitch, counts, digests, stats)
+    p = make_params(alpha, R, seed, topk, stitch, counts, digests, stats, blocks_per_cu)
     ws_bytes = fppr_plan(graph, p, n_src)
     ws = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device="cuda")
     out = alloc_outputs(n_src, R, topk, counts, digests, stats, endpoints)
@@ -353,7 +406,7 @@ class Batch:
     stitch, sources (None or int sequence), counts, digests. Outputs are
     allocated here (torch) as Outputs objects in `self.outputs`."""
 
-    def __init__(self, items, counts=True, digests=True, stats=True):
+    def __init__(self, items, counts=True, digests=True, stats=True, rebuild=False, blocks_per_cu=0):
         import torch
 
         self._keep = []
@@ -383,7 +436,9 @@ class Batch:
         self.workspace = torch.empty((ws.value + 7) // 8, dtype=torch.int64, device="cuda")
         self.stats = torch.zeros(8, dtype=torch.int64, device="cuda") if stats else None
         h = ctypes.c_void_p()
-        _check(lib().fppr_batch_create(arr, len(items), _dptr(self.workspace), ws.value, ctypes.byref(h)))
+        opts = fppr_batch_opts(FPPR_BATCH_REBUILD if rebuild else 0, int(blocks_per_cu))
+        _check(lib().fppr_batch_create(arr, len(items), ctypes.byref(opts), _dptr(self.workspace), ws.value,
+                                       ctypes.byref(h)))
         self._h = h
 
     def stats_dict(self):

@@ -140,3 +140,88 @@ def test_batch_workload_smallest_graphs_vs_oracle(fp):
         assert np.array_equal(u32(o.topk), ref.topk)
         assert np.array_equal(u64(o.digest), ref.digest)
     B.close()
+
+
+def test_relayout_and_launch_width_never_change_results(fp):
+    """fppr_graph_set_hub_threshold (trees on/off, pool rebuilt) and the
+    walk-launch width leave every result bit-identical."""
+    import torch
+
+    say("case: re-layout + launch width invariance")
+    g = synth.chung_lu(5000, 80000, 2.1, 255, seed=2010)
+    G = fp.Graph(g)
+    G.build_pool(S=16, L=3, K=32, alpha=0.15, seed=9)
+    base = fp.run(G, 0.15, 64, 21, topk=8, stitch=True)
+    want = (u32(base.counts), u64(base.digest), u32(base.topk))
+    for H, bpc in ((0xFFFFFFFF, 0), (64, 1), (8, 2), (8, 3)):
+        G.set_hub_threshold(H)
+        o = fp.run(G, 0.15, 64, 21, topk=8, stitch=True, blocks_per_cu=bpc)
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(o.counts), want[0]), (H, bpc)
+        assert np.array_equal(u64(o.digest), want[1]), (H, bpc)
+        assert np.array_equal(u32(o.topk), want[2]), (H, bpc)
+    info = G.info()
+    assert info["hubs"] == int((g.degrees() > 8).sum())
+
+
+def test_autotune_choice_matches_oracle(fp):
+    """The tuner leaves the graph in its chosen configuration; a run in that
+    configuration equals the oracle given the same pool parameters."""
+    import torch
+
+    say("case: autotune")
+    g = synth.chung_lu(20000, 240000, 2.2, 255, seed=2011)
+    G = fp.Graph(g)
+    pools = [dict(S=16, L=2, K=32, seed=31), dict(S=32, L=3, K=64, seed=32)]
+    r = G.autotune(0.15, 64, 41, hub_thresholds=[8, 64, 0xFFFFFFFF], blocks_per_cu=[0, 2],
+                   pools=pools, sample=4096, reps=2)
+    say(f"  tuned: {r}")
+    assert r["hub_threshold"] in (8, 64, 0xFFFFFFFF)
+    assert r["blocks_per_cu"] in (0, 2)
+    assert r["pool"] in (-1, 0, 1)
+    assert r["trials"] == 3 + 1 + len(pools)
+    stitch = r["pool"] >= 0
+    assert (G.info()["small"] > 0) == stitch
+    o = fp.run(G, 0.15, 64, 41, topk=8, stitch=stitch, blocks_per_cu=r["blocks_per_cu"])
+    torch.cuda.synchronize()
+    og = O.Graph.from_csr(g)
+    pool = None
+    if stitch:
+        po = pools[r["pool"]]
+        pool = O.Pool(og, S=po["S"], L=po["L"], K=po["K"], alpha=0.15, seed=po["seed"])
+    ref = O.run(og, 0.15, 64, 41, topk=8, pool=pool)
+    assert np.array_equal(u32(o.counts), ref.counts)
+    assert np.array_equal(u64(o.digest), ref.digest)
+    # forcing the other choice still works: plain walks on a graph without a pool
+    G.set_hub_threshold(8)
+    o2 = fp.run(G, 0.15, 64, 41, topk=8, stitch=False)
+    ref2 = O.run(og, 0.15, 64, 41, topk=8)
+    assert np.array_equal(u64(o2.digest), ref2.digest)
+
+
+def test_batch_with_rebuild_captured(fp, items):
+    """FPPR_BATCH_REBUILD puts every graph's rebuild (prefixes, records,
+    trees, pools) in front of the walks; captured and replayed it gives the
+    eager results, and the launch width does not matter."""
+    import torch
+
+    say("case: batch with rebuild, captured, narrow launch")
+    B0 = fp.Batch(items)
+    B0.run()
+    torch.cuda.synchronize()
+    want = [(u32(o.counts).copy(), u64(o.digest).copy()) for o in B0.outputs]
+    B0.close()
+    B = fp.Batch(items, rebuild=True, blocks_per_cu=1)
+    stream = torch.cuda.Stream()
+    B.capture(stream)
+    for rep in range(2):
+        for o in B.outputs:
+            o.counts.fill_(-1)
+            o.digest.fill_(-1)
+        torch.cuda.synchronize()
+        B.launch(stream)
+        B.check(stream)
+        for (c, d), o in zip(want, B.outputs):
+            assert np.array_equal(u32(o.counts), c), rep
+            assert np.array_equal(u64(o.digest), d), rep
+    B.close()
