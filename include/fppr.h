@@ -176,7 +176,8 @@ enum {
 
 typedef struct {
   double alpha;    /* termination probability in (0, 1) */
-  uint32_t R;      /* walks per source (omega of Algorithm 2), 1 <= R <= 2^20 */
+  uint32_t R;      /* walks per source (omega of Algorithm 2), 1 <= R <= 2^20;
+                      FPPR_COUNTS needs R <= 4096 */
   uint64_t seed;   /* Philox key */
   uint32_t topk;   /* k largest counts per source, 0 <= k <= R and k <= 1024 */
   uint32_t flags;  /* FPPR_* bits */

@@ -290,10 +290,243 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// R > kAggMaxR (large walk budgets, up to 2^20 per source): one 1024-thread
+// block per source at a time, counting in an open-addressing hash table in
+// global memory (one 8-byte slot = t << 32 | count, empty = kEmpty, at most
+// half full). A pass over the table gives the digest, the number of distinct
+// endpoints and a histogram of min(count, 2047); a block scan of the
+// histogram from the top gives the count threshold of the k-th entry. The
+// entries at or above it are sorted in LDS by (count desc, t asc) when they
+// fit; otherwise an exact radix select over the 64-bit ranking keys finds the
+// k-th key first. The last pass also empties the table for the next source.
+// ---------------------------------------------------------------------------
+constexpr int kBigThreads = 1024;
+constexpr uint32_t kHistBins = 2048;
+constexpr uint32_t kCandCap = 4096;
+constexpr uint64_t kEmpty = 0xFFFFFFFF00000000ull;
+
+// loads that see other threads' atomics (served by L2, not the CU's cache)
+__device__ __forceinline__ uint64_t load_l2(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ranking key: larger = earlier in the top-k (count desc, then t asc)
+__device__ __forceinline__ uint64_t rank_key(uint64_t e) {
+  return (static_cast<uint64_t>(static_cast<uint32_t>(e)) << 32) | static_cast<uint32_t>(~(e >> 32));
+}
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
+  v = wave_sum_u64(v);
+  const uint32_t wave = threadIdx.x / 64;
+  __syncthreads();
+  if (__lane_id() == 0) lds[wave] = v;
+  __syncthreads();
+  uint64_t t = 0;
+  for (uint32_t i = 0; i < kBigThreads / 64; ++i) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
+  __shared__ uint32_t hist[kHistBins];
+  __shared__ uint64_t cand[kCandCap];
+  __shared__ uint64_t red[kBigThreads / 64];
+  __shared__ uint64_t s_key;      // threshold key (radix path)
+  __shared__ uint32_t s_cstar, s_cand, s_n, s_digit, s_rem;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t H = 1u << a.H_log2;
+  uint64_t* tab = a.table + (static_cast<uint64_t>(blockIdx.x) << a.H_log2);
+  const uint32_t R = a.R;
+
+  for (uint64_t row = blockIdx.x; row < a.n_src; row += gridDim.x) {
+    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
+    const uint32_t* ep = a.endpoints + row * R;
+    // 1. count
+    for (uint32_t i = tid; i < R; i += kBigThreads) {
+      const uint32_t t = ep[i];
+      if (t == kNoNode) continue;  // a source that got no walks
+      uint32_t h = (t * 0x9E3779B1u) >> (32 - a.H_log2);
+      for (;;) {
+        const uint64_t cur = load_l2(tab + h);
+        if (cur != kEmpty && (cur >> 32) == t) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), 1ull);
+          break;
+        }
+        if (cur == kEmpty) {
+          const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(tab + h),
+                                         static_cast<unsigned long long>(kEmpty),
+                                         static_cast<unsigned long long>((static_cast<uint64_t>(t) << 32) | 1u));
+          if (old == kEmpty) break;
+          if ((old >> 32) == t) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), 1ull);
+            break;
+          }
+        }
+        h = (h + 1) & (H - 1);
+      }
+    }
+    for (uint32_t b = tid; b < kHistBins; b += kBigThreads) hist[b] = 0;
+    __threadfence();
+    __syncthreads();
+
+    // 2. digest, distinct endpoints, count histogram
+    uint64_t dg = 0, nd = 0;
+    for (uint32_t h = tid; h < H; h += kBigThreads) {
+      const uint64_t e = load_l2(tab + h);
+      if (e != kEmpty) {
+        const uint32_t t = static_cast<uint32_t>(e >> 32), c = static_cast<uint32_t>(e);
+        dg += digest_term(src, t, c);
+        ++nd;
+        atomicAdd(&hist[c < kHistBins - 1 ? c : kHistBins - 1], 1u);
+      }
+    }
+    dg = block_sum_u64(dg, red);
+    nd = block_sum_u64(nd, red);
+    if (tid == 0) {
+      if (a.digest) a.digest[row] = dg;
+      if (a.n_distinct) a.n_distinct[row] = static_cast<uint32_t>(nd);
+    }
+    const uint32_t need = (a.topk && a.k) ? static_cast<uint32_t>(nd < a.k ? nd : a.k) : 0u;
+
+    // 3. threshold: the highest bin b with #(bin >= b) >= need. Thread j owns
+    // bins 2047 - 2j and 2046 - 2j.
+    int mode = 0;  // 0: nothing to select, 1: collect c >= cstar, 2: collect key >= s_key
+    if (need) {
+      const uint32_t bh = kHistBins - 1 - 2 * tid, bl = bh - 1;
+      const uint32_t vh = hist[bh], vl = hist[bl];
+      uint64_t tot;
+      const uint64_t above = block_exclusive_scan_u64<kBigThreads>(vh + vl, red, &tot);
+      if (above < need && above + vh >= need) {
+        s_cstar = bh;
+        s_cand = static_cast<uint32_t>(above + vh);
+      } else if (above + vh < need && above + vh + vl >= need) {
+        s_cstar = bl;
+        s_cand = static_cast<uint32_t>(above + vh + vl);
+      }
+      __syncthreads();
+      mode = s_cand <= kCandCap ? 1 : 2;
+    }
+    const uint32_t cstar = need ? s_cstar : 0u;
+
+    if (mode == 2) {
+      // exact radix select of the need-th largest ranking key among c >= cstar
+      uint64_t prefix = 0;
+      uint32_t rem = need;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        for (uint32_t b = tid; b < 256; b += kBigThreads) hist[b] = 0;
+        __syncthreads();
+        for (uint32_t h = tid; h < H; h += kBigThreads) {
+          const uint64_t e = load_l2(tab + h);
+          if (e == kEmpty || static_cast<uint32_t>(e) < cstar) continue;
+          const uint64_t key = rank_key(e);
+          if (shift == 56 || (key >> (shift + 8)) == (prefix >> (shift + 8)))
+            atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        const uint32_t v = tid < 256 ? hist[255 - tid] : 0u;
+        uint64_t tot;
+        const uint64_t above = block_exclusive_scan_u64<kBigThreads>(v, red, &tot);
+        if (tid < 256 && above < rem && above + v >= rem) {
+          s_digit = 255 - tid;
+          s_rem = rem - static_cast<uint32_t>(above);
+        }
+        __syncthreads();
+        prefix |= static_cast<uint64_t>(s_digit) << shift;
+        rem = s_rem;
+        __syncthreads();
+      }
+      if (tid == 0) s_key = prefix;
+    }
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+
+    // 4. collect the selected entries and empty the table
+    const uint64_t kmin = mode == 2 ? s_key : 0ull;
+    for (uint32_t h = tid; h < H; h += kBigThreads) {
+      const uint64_t e = load_l2(tab + h);
+      if (e == kEmpty) continue;
+      bool take = false;
+      if (mode == 1) take = static_cast<uint32_t>(e) >= cstar;
+      else if (mode == 2) take = rank_key(e) >= kmin;
+      if (take) cand[atomicAdd(&s_n, 1u)] = rank_key(e);
+      tab[h] = kEmpty;
+    }
+    __syncthreads();
+
+    // 5. sort the candidates (descending) and write the top-k row
+    if (a.topk && a.k) {
+      const uint32_t nc = s_n;
+      uint32_t P = 2;
+      while (P < nc) P <<= 1;
+      for (uint32_t i = nc + tid; i < P; i += kBigThreads) cand[i] = 0;
+      __syncthreads();
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          for (uint32_t idx = tid; idx < P; idx += kBigThreads) {
+            const uint32_t q = idx ^ j;
+            if (q > idx) {
+              const uint64_t x = cand[idx], y = cand[q];
+              const bool desc = (idx & k) == 0;
+              if ((x < y) == desc) {
+                cand[idx] = y;
+                cand[q] = x;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t q = tid; q < a.k; q += kBigThreads) {
+        uint32_t t = kNoNode, c = 0;
+        if (q < need) {
+          const uint64_t v = cand[q];
+          t = ~static_cast<uint32_t>(v);
+          c = static_cast<uint32_t>(v >> 32);
+        }
+        a.topk[(row * a.k + q) * 2] = t;
+        a.topk[(row * a.k + q) * 2 + 1] = c;
+      }
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+uint32_t agg_table_log2(uint32_t R) {
+  uint32_t l = 1;
+  while ((1ull << l) < 2ull * R) ++l;
+  return l;
+}
+
+uint32_t agg_table_groups(uint64_t n_src, uint32_t R) {
+  const uint64_t slot_bytes = 8ull << agg_table_log2(R);
+  uint64_t g = (1ull << 30) / slot_bytes;  // about 1 GiB of tables at most
+  if (g > kAggBigGroups) g = kAggBigGroups;
+  if (g < 64) g = 64;
+  if (g > n_src) g = n_src;
+  return static_cast<uint32_t>(g ? g : 1);
+}
+
+uint64_t agg_table_bytes(uint64_t n_src, uint32_t R) {
+  if (R <= kAggMaxR || n_src == 0) return 0;
+  return static_cast<uint64_t>(agg_table_groups(n_src, R)) << (agg_table_log2(R) + 3);
+}
 
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s) {
   if (a.n_src == 0) return hipSuccess;
+  if (a.R > kAggMaxR) {
+    if (!a.table || a.counts) return hipErrorInvalidValue;
+    AggLaunch b = a;
+    b.H_log2 = agg_table_log2(a.R);
+    const uint32_t groups = agg_table_groups(a.n_src, a.R);
+    hipError_t e = launch_fill_u64(b.table, static_cast<uint64_t>(groups) << b.H_log2, kEmpty, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_aggregate_big, dim3(groups), dim3(kBigThreads), 0, s, b);
+    return hipGetLastError();
+  }
   if (a.R <= 256) {
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);

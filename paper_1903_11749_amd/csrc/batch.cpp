@@ -36,6 +36,7 @@ struct fppr_batch {
   std::vector<WalkDesc> host_table;
   std::vector<uint32_t*> endpoints;   // per item
   unsigned long long* ctl = nullptr;  // in the workspace
+  uint64_t* agg_table = nullptr;      // hash tables of items with R > 4096 (shared)
   WalkDesc* table = nullptr;          // in the workspace
   uint64_t total = 0;                 // padded walk ids
   hipGraph_t graph = nullptr;
@@ -64,6 +65,16 @@ uint64_t endpoint_bytes(const fppr_batch_item& it) {
   return align_up(item_sources(it) * it.params.R * 4ull);
 }
 
+// items aggregate one after the other on one stream: one table area serves all
+uint64_t table_bytes(const fppr_batch_item* items, uint32_t count) {
+  uint64_t t = 0;
+  for (uint32_t k = 0; k < count; ++k) {
+    const uint64_t b = align_up(agg_table_bytes(item_sources(items[k]), items[k].params.R));
+    if (b > t) t = b;
+  }
+  return t;
+}
+
 void free_batch(fppr_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -88,7 +99,8 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
   for (size_t k = 0; k < b->items.size(); ++k) {
     const fppr_batch_item& it = b->items[k];
-    const AggLaunch a = make_agg(&it.params, b->endpoints[k], it.sources, item_sources(it), &it.out);
+    AggLaunch a = make_agg(&it.params, b->endpoints[k], it.sources, item_sources(it), &it.out);
+    a.table = b->agg_table;
     if (a.topk || a.counts || a.digest) {
       if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");
     }
@@ -106,7 +118,7 @@ FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t coun
   fppr_status st = check_items(items, count);
   if (st != FPPR_OK) return st;
   if (!workspace_bytes) return invalid("workspace_bytes is NULL");
-  uint64_t bytes = kCtlBytes + align_up(count * sizeof(WalkDesc));
+  uint64_t bytes = kCtlBytes + align_up(count * sizeof(WalkDesc)) + table_bytes(items, count);
   for (uint32_t k = 0; k < count; ++k) bytes += endpoint_bytes(items[k]);
   *workspace_bytes = bytes;
   return FPPR_OK;
@@ -131,7 +143,8 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
   char* base = static_cast<char*>(workspace);
   b->ctl = reinterpret_cast<unsigned long long*>(base);
   b->table = reinterpret_cast<WalkDesc*>(base + kCtlBytes);
-  char* ep = base + kCtlBytes + align_up(count * sizeof(WalkDesc));
+  b->agg_table = reinterpret_cast<uint64_t*>(base + kCtlBytes + align_up(count * sizeof(WalkDesc)));
+  char* ep = base + kCtlBytes + align_up(count * sizeof(WalkDesc)) + table_bytes(items, count);
   b->endpoints.resize(count);
   for (uint32_t k = 0; k < count; ++k) {
     b->endpoints[k] = reinterpret_cast<uint32_t*>(ep);

@@ -451,7 +451,8 @@ FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream) {
 fppr_status fppr::check_params(const fppr_graph* g, const fppr_params* p) {
   if (!g || !p) return invalid("graph or params is NULL");
   if (!fppr_alpha_threshold(p->alpha)) return invalid("alpha must be in (0, 1)");
-  if (p->R < 1 || p->R > kAggMaxR) return invalid("R must be in [1, 4096]");
+  if (p->R < 1 || p->R > kMaxR) return invalid("R must be in [1, 2^20]");
+  if ((p->flags & FPPR_COUNTS) && p->R > kAggMaxR) return invalid("FPPR_COUNTS needs R <= 4096");
   if (p->topk > p->R || p->topk > 1024) return invalid("topk must be <= R and <= 1024");
   if (p->flags & ~(FPPR_STITCH | FPPR_COUNTS | FPPR_DIGESTS | FPPR_STATS)) return invalid("unknown flag bits");
   if (p->flags & FPPR_STITCH) {
@@ -468,7 +469,8 @@ FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64
   fppr_status st = check_params(g, p);
   if (st != FPPR_OK) return st;
   if (!workspace_bytes) return invalid("workspace_bytes is NULL");
-  *workspace_bytes = kCtlBytes + kDescBytes + align_up(n_sources * p->R * 4ull);
+  *workspace_bytes = kCtlBytes + kDescBytes + align_up(n_sources * p->R * 4ull) +
+                     agg_table_bytes(n_sources, p->R);
   return FPPR_OK;
 }
 
@@ -504,7 +506,9 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
   if ((e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
     return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
-  const AggLaunch a = make_agg(p, endpoints, sources, n_sources, out);
+  AggLaunch a = make_agg(p, endpoints, sources, n_sources, out);
+  a.table = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + kCtlBytes + kDescBytes +
+                                        align_up(n_sources * p->R * 4ull));
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
   if (a.topk || a.counts || a.digest) {
     if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");

@@ -112,6 +112,7 @@ WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* so
                    uint64_t n_sources, uint32_t* endpoints, uint64_t first, uint64_t walk0,
                    uint64_t count);
 hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
 
 // aggregate.hip
 struct AggLaunch {
@@ -124,10 +125,19 @@ struct AggLaunch {
   uint32_t* counts;
   uint32_t* n_distinct;
   uint64_t* digest;
+  uint64_t* table;   // R > kAggMaxR: agg_table_bytes of scratch (filled here)
+  uint32_t H_log2;   // set by launch_aggregate
 };
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s);
 AggLaunch make_agg(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
                    uint64_t n_sources, const fppr_out* out);
-constexpr uint32_t kAggMaxR = 4096;
+constexpr uint32_t kAggMaxR = 4096;      // largest R of the sorting paths (counts supported)
+constexpr uint32_t kMaxR = 1u << 20;     // largest R (hash path above kAggMaxR: no counts)
+constexpr uint32_t kAggBigGroups = 512;  // blocks (and hash tables) of the hash path
+// hash path: log2 of the slots per table, tables used, scratch bytes (0 when
+// R <= kAggMaxR)
+uint32_t agg_table_log2(uint32_t R);
+uint32_t agg_table_groups(uint64_t n_src, uint32_t R);
+uint64_t agg_table_bytes(uint64_t n_src, uint32_t R);
 
 }  // namespace fppr

@@ -469,6 +469,14 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  uint64_t b = (count + 255) / 256;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_fill_u64, dim3(static_cast<uint32_t>(b)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, s, d, dst);
   return hipGetLastError();

@@ -1,0 +1,141 @@
+"""Large walk budgets (R > 4096: hash-table counting, threshold selection and,
+when many entries tie at the threshold, exact radix selection) against the
+oracle, bit for bit: top-k lists and digests."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import torch
+
+    from paper_1903_11749_amd import fppr
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fppr.lib()
+    return fppr
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def check(o, ref):
+    assert np.array_equal(u32(o.topk), ref.topk)
+    assert np.array_equal(u64(o.digest), ref.digest)
+
+
+def test_big_r_plain(fp):
+    say("case: R=5000 and R=20000, plain walks, sampled sources")
+    g = synth.chung_lu(20000, 200000, 2.1, 255, seed=2020)
+    G = fp.Graph(g)
+    og = O.Graph.from_csr(g)
+    src = np.unique(np.random.default_rng(5).integers(0, g.n, 300)).astype(np.uint32)
+    for R, k in ((5000, 64), (20000, 16)):
+        o = fp.run(G, 0.15, R, 77, sources=src, topk=k, counts=False)
+        ref = O.run(og, 0.15, R, 77, sources=src, topk=k, want_counts=False)
+        check(o, ref)
+
+
+def test_big_r_stitched(fp):
+    say("case: R=12345 stitched")
+    g = synth.chung_lu(5000, 60000, 2.3, 255, seed=2021)
+    G = fp.Graph(g)
+    G.build_pool(S=32, L=3, K=64, alpha=0.2, seed=8)
+    og = O.Graph.from_csr(g)
+    pool = O.Pool(og, S=32, L=3, K=64, alpha=0.2, seed=8)
+    src = np.arange(0, g.n, 97, dtype=np.uint32)
+    o = fp.run(G, 0.2, 12345, 5, sources=src, topk=64, stitch=True, counts=False)
+    ref = O.run(og, 0.2, 12345, 5, sources=src, topk=64, pool=pool, want_counts=False)
+    check(o, ref)
+
+
+def star(n_leaves, weights):
+    """Node 0 points to every leaf; leaves point back to 0."""
+    n = n_leaves + 1
+    src = np.concatenate([np.zeros(n_leaves, np.uint32), np.arange(1, n, dtype=np.uint32)])
+    dst = np.concatenate([np.arange(1, n, dtype=np.uint32), np.zeros(n_leaves, np.uint32)])
+    w = np.concatenate([weights, np.ones(n_leaves, np.uint32)]).astype(np.uint32)
+    return synth.csr_from_edges(n, src, dst, w)
+
+
+def test_big_r_ties_radix_select(fp):
+    """8000 walks over 40000 equally weighted leaves: for k = 1024 the k-th
+    count is 1, about 7000 entries reach it (more than the 4096 the sort
+    holds), so the exact radix select decides, ties broken by id; for k = 64
+    the threshold is 2 and the sort path runs."""
+    say("case: star, many tied counts (radix select)")
+    g = star(40000, np.ones(40000, np.uint32))
+    G = fp.Graph(g)
+    og = O.Graph.from_csr(g)
+    for k in (64, 1024):
+        o = fp.run(G, 0.97, 8000, 3, sources=[0], topk=k, counts=False)
+        ref = O.run(og, 0.97, 8000, 3, sources=np.array([0], np.uint32), topk=k, want_counts=False)
+        check(o, ref)
+
+
+def test_big_r_padding_and_hub(fp):
+    say("case: fewer distinct endpoints than k; weighted hub")
+    rng = np.random.default_rng(11)
+    g = star(4000, rng.integers(1, 1000, 4000).astype(np.uint32))
+    G = fp.Graph(g)
+    og = O.Graph.from_csr(g)
+    src = np.array([0, 1, 4000, 0], np.uint32)
+    o = fp.run(G, 0.5, 8192, 9, sources=src, topk=256, counts=False)
+    ref = O.run(og, 0.5, 8192, 9, sources=src, topk=256, want_counts=False)
+    check(o, ref)
+    tiny = synth.csr_from_edges(4, np.array([0, 1, 2], np.uint32), np.array([1, 2, 0], np.uint32),
+                                np.array([1, 1, 1], np.uint32))
+    T = fp.Graph(tiny)
+    o = fp.run(T, 0.3, 5000, 1, topk=64, counts=False)
+    ref = O.run(O.Graph.from_csr(tiny), 0.3, 5000, 1, topk=64, want_counts=False)
+    check(o, ref)
+
+
+def test_big_r_counts_rejected(fp):
+    g = synth.chung_lu(100, 500, 2.1, 255, seed=2022)
+    G = fp.Graph(g)
+    with pytest.raises(fp.FpprError):
+        fp.run(G, 0.15, 5000, 1, topk=4, counts=True)
+    with pytest.raises(fp.FpprError):
+        fp.run(G, 0.15, (1 << 20) + 1, 1, topk=4, counts=False)
+
+
+def test_batch_mixing_big_and_small_r(fp):
+    import torch
+
+    say("case: batch with R in {64, 6000, 256, 20000}")
+    g1 = synth.chung_lu(3000, 30000, 2.2, 255, seed=2023)
+    g2 = synth.chung_lu(800, 6000, 2.4, 255, seed=2024)
+    G1, G2 = fp.Graph(g1), fp.Graph(g2)
+    s1 = np.arange(0, 3000, 31, dtype=np.uint32)
+    s2 = np.arange(0, 800, 13, dtype=np.uint32)
+    items = [dict(graph=G1, alpha=0.15, R=64, seed=1, topk=16, sources=None),
+             dict(graph=G1, alpha=0.15, R=6000, seed=2, topk=64, sources=s1),
+             dict(graph=G2, alpha=0.2, R=256, seed=3, topk=16, sources=None),
+             dict(graph=G2, alpha=0.1, R=20000, seed=4, topk=32, sources=s2)]
+    B = fp.Batch(items, counts=False)
+    B.run()
+    B.check()
+    torch.cuda.synchronize()
+    for it, o, g in zip(items, B.outputs, (g1, g1, g2, g2)):
+        ref = O.run(O.Graph.from_csr(g), it["alpha"], it["R"], it["seed"], sources=it["sources"],
+                    topk=it["topk"], want_counts=False)
+        check(o, ref)
+    B.close()
