@@ -223,15 +223,146 @@ def _bench_batch(args, fppr, torch, np, stream):
     return res
 
 
+SERVE_TOPK = 64
+SERVE_ALPHA = 0.15
+
+
+def _serve_run(fppr, G, queries, mode, times=None, stitch=True, **kw):
+    """Submits `queries` (at their arrival offsets in `times`, seconds, or all
+    at once) and collects every result. Returns (results by query, per-query
+    latency s, makespan s, server stats)."""
+    import collections
+
+    import numpy as np
+
+    S = fppr.Server(G, mode=mode, **kw)
+    t0 = time.perf_counter()
+    ids = []
+    outstanding = collections.deque()
+    results = {}
+
+    def drain(block=False):
+        while outstanding:
+            qi, qid = outstanding[0]
+            r = S.wait(qid) if block else S.poll(qid)
+            if r is None:
+                return
+            results[qi] = r
+            outstanding.popleft()
+
+    for qi, q in enumerate(queries):
+        if times is not None:
+            due = t0 + times[qi]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                drain()
+                if due - now > 0.0005:
+                    time.sleep(min(0.0005, due - now - 0.0003))
+        qid = S.submit(q["sources"], q["R"], SERVE_ALPHA, q["seed"], SERVE_TOPK, stitch)
+        ids.append(qid)
+        outstanding.append((qi, qid))
+        drain()
+    drain(block=True)
+    st = S.stats()
+    S.close()
+    sub = np.array([results[i][2]["submit_ns"] for i in range(len(queries))], dtype=np.float64)
+    done = np.array([results[i][2]["done_ns"] for i in range(len(queries))], dtype=np.float64)
+    lat = (done - sub) / 1e9
+    makespan = (done.max() - sub.min()) / 1e9
+    return results, lat, makespan, st
+
+
+def bench_serve(args, fppr, torch, G, n_nodes, oracle_pool=None, oracle_graph=None):
+    """Continuous-batching server vs FIFO plain launches on the resident
+    scale-24 graph and pool, at the same Poisson arrival rate."""
+    import numpy as np
+
+    import synth
+
+    torch.cuda.synchronize()
+    nq, warm = args.serve_queries, args.serve_warmup
+    base = synth.poisson_queries(n_nodes, nq + warm, qps=1.0, seed=5000)
+    queries = [dict(sources=q["sources"], R=q["R"], seed=q["seed"]) for q in base]
+    unit_times = np.array([q["arrival"] for q in base])  # arrivals at 1 query/s
+    kw = dict(max_requests=64, memory_bytes=24 << 30, host_bytes=2 << 30, slice_walks=1 << 23)
+    # saturation: everything submitted at once (closed burst)
+    burst = queries[:args.serve_burst]
+    _, _, fifo_span, _ = _serve_run(fppr, G, burst, "fifo", **kw)
+    _, _, cont_span, _ = _serve_run(fppr, G, burst, "continuous", **kw)
+    fifo_sat, cont_sat = len(burst) / fifo_span, len(burst) / cont_span
+    qps = 0.9 * fifo_sat
+    log(f"serve: saturation fifo {fifo_sat:.1f} q/s, continuous {cont_sat:.1f} q/s; open loop at {qps:.1f} q/s")
+    times = unit_times / qps
+    out = {}
+    res_by_mode = {}
+    for mode in ("fifo", "continuous"):
+        res, lat, span, st = _serve_run(fppr, G, queries, mode, times=times, **kw)
+        m = lat[warm:]
+        out[mode] = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
+                     "mean_ms": round(float(m.mean()) * 1e3, 3),
+                     "queries_per_s": round(len(lat) / span, 2),
+                     "sources_per_s": round(sum(q["sources"].size for q in queries) / span, 1),
+                     "walk_steps_per_s": round(st["walk_stats"]["steps"] / span, 1),
+                     "walks": int(st["walk_stats"]["walks"]), "slices": int(st["slices"]),
+                     "peak_in_flight": int(st["peak_in_flight"])}
+        res_by_mode[mode] = res
+        log(f"serve {mode}: p50 {out[mode]['p50_ms']} ms, p99 {out[mode]['p99_ms']} ms, "
+            f"{out[mode]['queries_per_s']} q/s")
+    same = all(np.array_equal(res_by_mode["fifo"][i][0], res_by_mode["continuous"][i][0]) and
+               np.array_equal(res_by_mode["fifo"][i][1], res_by_mode["continuous"][i][1])
+               for i in range(len(queries)))
+    # a sample rerun alone with fppr_run
+    rng = np.random.default_rng(17)
+    alone_ok = True
+    for i in rng.choice(len(queries), 8, replace=False):
+        q = queries[i]
+        o = fppr.run(G, SERVE_ALPHA, q["R"], q["seed"], sources=q["sources"], topk=SERVE_TOPK, stitch=True,
+                     counts=False, stats=False)
+        torch.cuda.synchronize()
+        alone_ok &= bool(np.array_equal(o.topk.cpu().numpy().view(np.uint32), res_by_mode["continuous"][i][0])
+                         and np.array_equal(o.digest.cpu().numpy().view(np.uint64),
+                                            res_by_mode["continuous"][i][1]))
+    oracle_ok = None
+    if oracle_pool is not None:
+        from oracle import oracle as O
+
+        small = sorted(range(len(queries)), key=lambda i: queries[i]["sources"].size * queries[i]["R"])[:3]
+        oracle_ok = True
+        for i in small:
+            q = queries[i]
+            ref = O.run(oracle_graph, SERVE_ALPHA, q["R"], q["seed"], sources=q["sources"], topk=SERVE_TOPK,
+                        pool=oracle_pool, want_counts=False)
+            oracle_ok &= bool(np.array_equal(res_by_mode["continuous"][i][0], ref.topk)
+                              and np.array_equal(res_by_mode["continuous"][i][1], ref.digest))
+    return {
+        "workload": (f"resident rmat-scale24 graph + short-walk pool; {nq} Poisson queries after {warm} "
+                     "warm-up, 1..1024 uniform sources each, R log-uniform in [1e3, 1e5], alpha 0.15, "
+                     "top-64, seed = query id"),
+        "qps": round(qps, 2), "fifo_saturation_qps": round(fifo_sat, 2),
+        "continuous_saturation_qps": round(cont_sat, 2),
+        "fifo": out["fifo"], "continuous": out["continuous"],
+        "p99_speedup": round(out["fifo"]["p99_ms"] / out["continuous"]["p99_ms"], 3),
+        "bit_exact_fifo_vs_continuous": bool(same), "bit_exact_alone_sample8": bool(alone_ok),
+        "oracle_bit_exact_smallest3": oracle_ok,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["scale24", "medium", "batch"], default="scale24")
+    ap.add_argument("--workload", choices=["scale24", "medium", "batch", "serve"], default="scale24")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-graph batched-vs-plain comparison of the default run")
     ap.add_argument("--manifest", default="", help="write the batch autotuner's choices here (JSON)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison of the default run")
+    ap.add_argument("--serve-queries", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-burst", type=int, default=300, help="queries of the saturation bursts")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")
@@ -277,7 +408,7 @@ def main():
             "config": {"workload": res["workload"]}, "batched": res}), flush=True)
         return
 
-    if args.workload == "scale24":
+    if args.workload in ("scale24", "serve"):
         cfg = dict(synth.SCALE24)
         t0 = time.time()
         g = synth.scale24_graph()
@@ -351,7 +482,7 @@ def main():
     walk_avg = float(np.mean(walk_ms))
     ab = alg_bytes(st_last)
     achieved = ab / (walk_avg / 1e3) / 1e9
-    traffic = counted_traffic() if args.workload == "scale24" else None
+    traffic = counted_traffic() if args.workload in ("scale24", "serve") else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
                 "kernel": "k_walk", "kernel_ms": round(walk_avg, 3),
@@ -375,6 +506,7 @@ def main():
     }
 
     # ---- oracle: sampled parity + CPU baseline (rank 0, N = 1) ----
+    og = pool = None
     if args.cpu_sample > 0:
         from oracle import oracle as O
 
@@ -410,6 +542,8 @@ def main():
             result["parity_sample"] = {"sources": len(sample), "bit_exact": ok}
             if not ok:
                 log("PARITY MISMATCH on the sampled sources")
+    if args.workload in ("scale24", "serve") and not args.no_serve:
+        result["serving"] = bench_serve(args, fppr, torch, G, g.n, oracle_pool=pool, oracle_graph=og)
     if args.workload == "scale24" and not args.no_batch:
         result["batched"] = bench_batch(args, fppr, torch, np)
     print(json.dumps(result), flush=True)

@@ -362,6 +362,86 @@ typedef struct {
 FPPR_API fppr_status fppr_autotune(fppr_graph* g, const fppr_params* p, const fppr_tune_space* space,
                                    fppr_tune_result* result, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving. A server keeps one graph (and its pool) resident and answers PPR
+ * queries (sources, walk budget R, alpha, seed, k) that arrive over time.
+ * Continuous mode: a scheduler thread admits queued queries as slots and
+ * device memory free up (each needs n_sources * R * 4 bytes of endpoints plus
+ * its outputs), and advances all admitted queries together in walk slices of
+ * bounded size; a query that arrives while others run joins the next slice.
+ * Algorithm 2's pipelines play the same role (Sec. 4.3: new walks start while
+ * earlier ones are in flight, and the in-flight count is bounded by memory).
+ * When a query's last walks have run, its counting and top-k go to a second
+ * stream and its results are copied to pinned host memory. FIFO mode is the
+ * comparison point: one plain launch per query, in arrival order. Draws are
+ * keyed by the query's seed, source and walk index only, so a query's result
+ * is bit-identical alone, in any mix and in either mode.
+ * ---------------------------------------------------------------------- */
+typedef struct fppr_server fppr_server;
+
+enum { FPPR_SERVE_CONTINUOUS = 0, FPPR_SERVE_FIFO = 1 };
+
+typedef struct {
+  uint32_t mode;           /* FPPR_SERVE_CONTINUOUS or FPPR_SERVE_FIFO */
+  uint32_t max_requests;   /* queries in flight at once (slots), 1..4096 */
+  uint64_t memory_bytes;   /* device memory for in-flight queries' endpoints
+                              and outputs, allocated at create (>= 1 MiB) */
+  uint64_t host_bytes;     /* pinned host memory for queued sources and
+                              finished results until fppr_server_poll takes
+                              them (>= 1 MiB) */
+  uint64_t slice_walks;    /* walks per slice in continuous mode (>= 2^16) */
+  uint32_t blocks_per_cu;  /* walk-launch width (0 = as many as fit) */
+} fppr_server_opts;
+
+typedef struct {
+  const uint32_t* sources; /* host [n_sources], each < n; copied by submit */
+  uint32_t n_sources;      /* >= 1 */
+  uint32_t R;              /* walks per source, 1..2^20 */
+  double alpha;            /* in (0, 1); FPPR_STITCH needs the pool's alpha */
+  uint64_t seed;           /* Philox key of the query's walks */
+  uint32_t topk;           /* 1..1024, <= R */
+  uint32_t flags;          /* FPPR_STITCH or 0 */
+} fppr_query;
+
+typedef struct {
+  uint64_t submit_ns;      /* steady-clock times (ns) of submit, admission */
+  uint64_t admit_ns;
+  uint64_t done_ns;        /* and of the results reaching host memory */
+  uint64_t walks;          /* n_sources * R */
+} fppr_query_info;
+
+typedef struct {
+  uint64_t submitted, completed, slices, walk_launches;
+  uint64_t peak_in_flight;     /* most queries in flight at once */
+  uint64_t peak_device_bytes;  /* most device memory held by queries */
+  fppr_stats walk_stats;       /* summed over all walk launches */
+} fppr_server_counters;
+
+/* Creates the server and its scheduler thread on the current device (the
+ * graph's). The graph (and pool) must stay alive and unchanged until
+ * fppr_server_destroy. */
+FPPR_API fppr_status fppr_server_create(fppr_graph* g, const fppr_server_opts* opts, fppr_server** out);
+
+/* Queues a query (thread-safe, does not block on the GPU) and returns its id.
+ * INVALID_ARGUMENT if it is malformed or could never fit the server's memory
+ * or pinned budget. */
+FPPR_API fppr_status fppr_server_submit(fppr_server* s, const fppr_query* q, uint64_t* id);
+
+/* FPPR_NOT_READY while query `id` runs; FPPR_OK once done: copies its results
+ * (host buffers: topk [n_sources][k][2] uint32 as for fppr_run, digest
+ * [n_sources] uint64; either may be NULL) and `info`, and forgets the id.
+ * fppr_server_wait blocks until done. */
+FPPR_API fppr_status fppr_server_poll(fppr_server* s, uint64_t id, uint32_t* topk, uint64_t* digest,
+                                      fppr_query_info* info);
+FPPR_API fppr_status fppr_server_wait(fppr_server* s, uint64_t id, uint32_t* topk, uint64_t* digest,
+                                      fppr_query_info* info);
+
+/* Counters since create (host output; walk_stats synchronises the device). */
+FPPR_API fppr_status fppr_server_stats(fppr_server* s, fppr_server_counters* out);
+
+/* Finishes every query already submitted, stops the thread, frees everything. */
+FPPR_API fppr_status fppr_server_destroy(fppr_server* s);
+
 /* Synchronises `stream` and reports whether a run that used `workspace` met
  * a source id >= n (INVALID_ARGUMENT; such a source gets no walks and its
  * endpoints read FPPR_NO_NODE) or FPPR_OK. */

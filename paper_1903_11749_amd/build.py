@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfppr.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["build.hip", "pool.hip", "walk.hip", "aggregate.hip", "fppr.cpp", "batch.cpp", "tune.cpp"]
+SOURCES = ["build.hip", "pool.hip", "walk.hip", "aggregate.hip", "fppr.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
 ARCH = os.environ.get("FPPR_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fvisibility=hidden",
@@ -33,7 +33,7 @@ def build(jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

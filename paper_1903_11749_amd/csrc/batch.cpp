@@ -93,7 +93,8 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
   if (e != hipSuccess) return hip_fail(e, "zero control words");
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   e = launch_walk(b->table, static_cast<uint32_t>(b->host_table.size()), b->total, b->ctl, stats,
-                  b->opts.blocks_per_cu, s);
+                  b->opts.blocks_per_cu, s,
+                  same_graph_table(b->host_table.data(), static_cast<uint32_t>(b->host_table.size())));
   if (e != hipSuccess) return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");

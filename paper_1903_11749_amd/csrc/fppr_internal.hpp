@@ -104,8 +104,13 @@ struct WalkDesc {
   uint64_t R_magic;          // floor((2^64 - 1) / R)
   uint32_t R, n, key0, key1, T, tree_min, K_log2, pad;
 };
+// lane_keys: the per-lane-key form of the kernel (for tables whose
+// descriptors all read one graph; see same_graph_table)
 hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
-                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s);
+                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, bool lane_keys = false);
+// true when a table (host copy) has more than one descriptor and all of them
+// read the same graph arrays
+bool same_graph_table(const WalkDesc* h, uint32_t ndesc);
 hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s);
 // descriptor of walks [walk0, walk0 + count) of a run of `p` on graph g
 WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* sources,

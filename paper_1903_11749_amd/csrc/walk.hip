@@ -15,7 +15,10 @@
 // launch. Draws depend only on (seed, source, walk, move), never on the table.
 // A wave serves one descriptor at a time, so all of its values sit in scalar
 // registers; a wave that claims a chunk of another descriptor lets its running
-// walks finish before it switches.
+// walks finish before it switches. When every descriptor of the table reads
+// the same graph (the slices of many queries), a second form of the kernel
+// keeps each walk's Philox key and coin threshold in its lane instead, and
+// waves switch descriptors without waiting.
 //
 // Each lane runs its walk as a small state machine that needs exactly one
 // dependent load per loop iteration (node record, one 128-byte tree node, one
@@ -66,6 +69,8 @@ struct Lane {
   uint32_t s, i, m, len, tail;
   // head record
   uint64_t sW, s_od;
+  // the walk's key and coin threshold (per-lane form of the kernel only)
+  uint32_t k0, k1, T;
   // current move
   uint32_t ph;
   uint64_t X;     // draw, or the address of the pool entry
@@ -102,7 +107,7 @@ __device__ __forceinline__ uint64_t sread64(uint64_t x) {
          (static_cast<uint64_t>(sread(static_cast<uint32_t>(x >> 32))) << 32);
 }
 
-template <bool kStats>
+template <bool kStats, bool kLaneKeys>
 __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   __shared__ uint64_t sh_line[kThreads / 64][64];
   __shared__ uint64_t sh_x[kThreads / 64][64];
@@ -152,7 +157,10 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           dn = sread(lo);
         }
         if (dn != d) {
-          if (__ballot(L.ph != kIdle) != 0) {  // finish the running walks first
+          const WalkDesc& Dn = t.descs[dn];
+          const bool same_graph = kLaneKeys && d != ~0u && Dn.rec == rec && Dn.blocks == blocks &&
+                                  Dn.tree_min == tree_min && Dn.K_log2 == K_log2;
+          if (!same_graph && __ballot(L.ph != kIdle) != 0) {  // finish the running walks first
             pend = c;
             pend_d = dn;
             break;
@@ -196,6 +204,11 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           }
           L.s = sources ? sources[q] : static_cast<uint32_t>(q);
           L.i = static_cast<uint32_t>(rem);
+          if (kLaneKeys) {
+            L.k0 = key0;
+            L.k1 = key1;
+            L.T = T;
+          }
           L.ep = endpoints + w;
           L.tail = L.s;
           L.m = 0;
@@ -316,7 +329,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
       L.tail = line_res;
       L.len += 1;
       step = true;
-      coin = L.x2 < T;
+      coin = L.x2 < (kLaneKeys ? L.T : T);
     } else if (ph == kPool) {
       const uint64_t e = v0;
       L.tail = static_cast<uint32_t>(e);
@@ -344,13 +357,14 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
     // ---- start a move at the tail with record (bw, bod) ----
     if (begin) {
       for (uint32_t restarts = 0;; ++restarts) {
-        const U4 x = philox10(L.i, L.m, L.s, 0u, key0, key1);
+        const U4 x = kLaneKeys ? philox10(L.i, L.m, L.s, 0u, L.k0, L.k1)
+                               : philox10(L.i, L.m, L.s, 0u, key0, key1);
         const uint32_t dg = static_cast<uint32_t>(bod & kDegMask);
         if (dg == 0) {  // no out-edges: back to the head, then the coin
           L.tail = L.s;
           L.len += 1;
           L.m += 1;
-          const bool cn = x.x2 < T;
+          const bool cn = x.x2 < (kLaneKeys ? L.T : T);
           if (cn || L.m == kMoveCap) {
             done = true;
             capped = !cn;
@@ -440,14 +454,14 @@ __global__ void k_set_desc(WalkDesc d, WalkDesc* dst) {
   if (threadIdx.x == 0) *dst = d;
 }
 
-template <bool kStats>
+template <bool kStats, bool kLaneKeys>
 hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t s) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats>, kThreads, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats, kLaneKeys>, kThreads, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   if (blocks_per_cu && static_cast<int>(blocks_per_cu) < per_cu) per_cu = static_cast<int>(blocks_per_cu);
@@ -455,7 +469,7 @@ hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t
   const uint64_t need = (t.total + kThreads - 1) / kThreads;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_walk<kStats>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, t);
+  hipLaunchKernelGGL((k_walk<kStats, kLaneKeys>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, t);
   return hipGetLastError();
 }
 
@@ -483,10 +497,20 @@ hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s) {
 }
 
 hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
-                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s) {
+                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, bool lane_keys) {
   if (total == 0 || ndesc == 0) return hipSuccess;
   WalkTable t{descs, ndesc, total, ctl, stats};
-  return stats ? launch_walk_t<true>(t, blocks_per_cu, s) : launch_walk_t<false>(t, blocks_per_cu, s);
+  if (lane_keys)
+    return stats ? launch_walk_t<true, true>(t, blocks_per_cu, s) : launch_walk_t<false, true>(t, blocks_per_cu, s);
+  return stats ? launch_walk_t<true, false>(t, blocks_per_cu, s) : launch_walk_t<false, false>(t, blocks_per_cu, s);
+}
+
+bool same_graph_table(const WalkDesc* h, uint32_t ndesc) {
+  for (uint32_t k = 1; k < ndesc; ++k)
+    if (h[k].rec != h[0].rec || h[k].blocks != h[0].blocks || h[k].tree_min != h[0].tree_min ||
+        h[k].K_log2 != h[0].K_log2)
+      return false;
+  return ndesc > 1;
 }
 
 }  // namespace fppr

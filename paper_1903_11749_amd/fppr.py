@@ -30,6 +30,8 @@ FPPR_COUNTS = 2
 FPPR_DIGESTS = 4
 FPPR_STATS = 8
 FPPR_BATCH_REBUILD = 1
+FPPR_SERVE_CONTINUOUS = 0
+FPPR_SERVE_FIFO = 1
 FPPR_MOVE_CAP = 65536
 FPPR_NO_NODE = 0xFFFFFFFF
 
@@ -93,6 +95,35 @@ class fppr_tune_result(ctypes.Structure):
                 ("est_ms", ctypes.c_double), ("plain_est_ms", ctypes.c_double)]
 
 
+class fppr_server_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("max_requests", ctypes.c_uint32),
+                ("memory_bytes", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64),
+                ("slice_walks", ctypes.c_uint64), ("blocks_per_cu", ctypes.c_uint32)]
+
+
+class fppr_query(ctypes.Structure):
+    _fields_ = [("sources", ctypes.c_void_p), ("n_sources", ctypes.c_uint32), ("R", ctypes.c_uint32),
+                ("alpha", ctypes.c_double), ("seed", ctypes.c_uint64), ("topk", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class fppr_query_info(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("walks", ctypes.c_uint64)]
+
+
+class fppr_stats_t(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("walks", "moves", "steps", "capped", "dangling_moves",
+                                               "plain_moves", "stitched_moves", "probe_log_sum")]
+
+
+class fppr_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("slices", ctypes.c_uint64), ("walk_launches", ctypes.c_uint64),
+                ("peak_in_flight", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
+                ("walk_stats", fppr_stats_t)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported symbol
@@ -130,6 +161,12 @@ _SIGS = [
     ("fppr_batch_destroy", ctypes.c_int, [P]),
     ("fppr_autotune", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.POINTER(fppr_tune_space),
                                      ctypes.POINTER(fppr_tune_result), P]),
+    ("fppr_server_create", ctypes.c_int, [P, ctypes.POINTER(fppr_server_opts), ctypes.POINTER(ctypes.c_void_p)]),
+    ("fppr_server_submit", ctypes.c_int, [P, ctypes.POINTER(fppr_query), ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_server_poll", ctypes.c_int, [P, ctypes.c_uint64, P, P, ctypes.POINTER(fppr_query_info)]),
+    ("fppr_server_wait", ctypes.c_int, [P, ctypes.c_uint64, P, P, ctypes.POINTER(fppr_query_info)]),
+    ("fppr_server_stats", ctypes.c_int, [P, ctypes.POINTER(fppr_server_counters)]),
+    ("fppr_server_destroy", ctypes.c_int, [P]),
     ("fppr_last_error", ctypes.c_char_p, []),
 ]
 
@@ -465,6 +502,69 @@ class Batch:
         if getattr(self, "_h", None):
             lib().fppr_batch_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A resident-graph query server (fppr_server_*). mode: "continuous" or
+    "fifo". submit() returns an id; poll()/wait() return (topk, digest, info)
+    with topk uint32 [n_sources, k, 2] and digest uint64 [n_sources], or None
+    from poll() while the query runs."""
+
+    def __init__(self, graph: Graph, mode="continuous", max_requests=64, memory_bytes=16 << 30,
+                 host_bytes=256 << 20, slice_walks=1 << 22, blocks_per_cu=0):
+        o = fppr_server_opts(FPPR_SERVE_FIFO if mode == "fifo" else FPPR_SERVE_CONTINUOUS, max_requests,
+                             memory_bytes, host_bytes, slice_walks, blocks_per_cu)
+        h = ctypes.c_void_p()
+        _check(lib().fppr_server_create(graph.handle, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._graph = graph
+        self._shape = {}
+
+    def submit(self, sources, R, alpha, seed, topk, stitch=False) -> int:
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        q = fppr_query(src.ctypes.data, src.size, int(R), float(alpha), int(seed), int(topk),
+                       FPPR_STITCH if stitch else 0)
+        qid = ctypes.c_uint64()
+        _check(lib().fppr_server_submit(self._h, ctypes.byref(q), ctypes.byref(qid)))
+        self._shape[qid.value] = (src.size, int(topk))
+        return qid.value
+
+    def _take(self, fn, qid):
+        n, k = self._shape[qid]
+        topk = np.empty((n, k, 2), dtype=np.uint32)
+        digest = np.empty(n, dtype=np.uint64)
+        info = fppr_query_info()
+        st = fn(self._h, qid, topk.ctypes.data, digest.ctypes.data, ctypes.byref(info))
+        if st == FPPR_NOT_READY:
+            return None
+        _check(st)
+        del self._shape[qid]
+        return topk, digest, dict(submit_ns=info.submit_ns, admit_ns=info.admit_ns, done_ns=info.done_ns,
+                                  walks=info.walks)
+
+    def poll(self, qid):
+        return self._take(lib().fppr_server_poll, qid)
+
+    def wait(self, qid):
+        return self._take(lib().fppr_server_wait, qid)
+
+    def stats(self):
+        st = fppr_server_counters()
+        _check(lib().fppr_server_stats(self._h, ctypes.byref(st)))
+        d = {f: getattr(st, f) for f, _ in fppr_server_counters._fields_ if f != "walk_stats"}
+        d["walk_stats"] = {f: getattr(st.walk_stats, f) for f, _ in fppr_stats_t._fields_}
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(lib().fppr_server_destroy(h))
 
     def __del__(self):
         try:
