@@ -311,6 +311,15 @@ __device__ __forceinline__ uint64_t load_l2(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Makes the block's table writes (atomics performed in L2, plain stores) visible
+// to its later plain loads: release at agent scope, barrier, then an acquire
+// that invalidates the compute unit's vector cache.
+__device__ __forceinline__ void table_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // ranking key: larger = earlier in the top-k (count desc, then t asc)
 __device__ __forceinline__ uint64_t rank_key(uint64_t e) {
   return (static_cast<uint64_t>(static_cast<uint32_t>(e)) << 32) | static_cast<uint32_t>(~(e >> 32));
@@ -328,6 +337,59 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
   return t;
 }
 
+// One pass of the block over its table (H >= 2 slots), two slots per 16-byte
+// load, four loads in flight per thread; f(entry) sees every occupied slot.
+// kReset empties the table behind the pass.
+template <bool kReset, typename F>
+__device__ __forceinline__ void table_pass(uint64_t* tab, uint32_t H, F&& f) {
+  uint4* t4 = reinterpret_cast<uint4*>(tab);
+  const uint32_t n4 = H / 2;
+  const uint4 empty2 = make_uint4(0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu);  // two kEmpty slots
+  auto visit = [&](const uint4& v) {
+    const uint64_t e0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
+    const uint64_t e1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
+    if (e0 != kEmpty) f(e0);
+    if (e1 != kEmpty) f(e1);
+  };
+  uint32_t j = threadIdx.x;
+  for (; j + 3 * kBigThreads < n4; j += 4 * kBigThreads) {
+    uint4 v[4];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) v[u] = t4[j + u * kBigThreads];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      visit(v[u]);
+      if (kReset) t4[j + u * kBigThreads] = empty2;
+    }
+  }
+  for (; j < n4; j += kBigThreads) {
+    const uint4 v = t4[j];
+    visit(v);
+    if (kReset) t4[j] = empty2;
+  }
+}
+
+// Adds one walk ending at t to the table, starting from slot h whose value
+// was read as cur.
+__device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint32_t t, uint32_t h, uint64_t cur) {
+  for (;;) {
+    if (cur != kEmpty) {
+      if ((cur >> 32) == t) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), 1ull);
+        return;
+      }
+      h = (h + 1) & mask;
+      cur = load_l2(tab + h);
+      continue;
+    }
+    const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(tab + h),
+                                   static_cast<unsigned long long>(kEmpty),
+                                   static_cast<unsigned long long>((static_cast<uint64_t>(t) << 32) | 1u));
+    if (old == kEmpty) return;
+    cur = old;  // taken meanwhile: look at what is there now
+  }
+}
+
 __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
   __shared__ uint32_t hist[kHistBins];
   __shared__ uint64_t cand[kCandCap];
@@ -336,51 +398,40 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
   __shared__ uint32_t s_cstar, s_cand, s_n, s_digit, s_rem;
   const uint32_t tid = threadIdx.x;
   const uint32_t H = 1u << a.H_log2;
+  const uint32_t mask = H - 1;
   uint64_t* tab = a.table + (static_cast<uint64_t>(blockIdx.x) << a.H_log2);
   const uint32_t R = a.R;
 
   for (uint64_t row = blockIdx.x; row < a.n_src; row += gridDim.x) {
     const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
     const uint32_t* ep = a.endpoints + row * R;
-    // 1. count
-    for (uint32_t i = tid; i < R; i += kBigThreads) {
-      const uint32_t t = ep[i];
-      if (t == kNoNode) continue;  // a source that got no walks
-      uint32_t h = (t * 0x9E3779B1u) >> (32 - a.H_log2);
-      for (;;) {
-        const uint64_t cur = load_l2(tab + h);
-        if (cur != kEmpty && (cur >> 32) == t) {
-          atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), 1ull);
-          break;
-        }
-        if (cur == kEmpty) {
-          const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(tab + h),
-                                         static_cast<unsigned long long>(kEmpty),
-                                         static_cast<unsigned long long>((static_cast<uint64_t>(t) << 32) | 1u));
-          if (old == kEmpty) break;
-          if ((old >> 32) == t) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), 1ull);
-            break;
-          }
-        }
-        h = (h + 1) & (H - 1);
+    // 1. count: four endpoints per thread at a time, their first probes together
+    for (uint32_t i0 = tid; i0 < R; i0 += 4 * kBigThreads) {
+      uint32_t t[4], h[4];
+      uint64_t cur[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + u * kBigThreads;
+        t[u] = i < R ? ep[i] : kNoNode;  // kNoNode: a source that got no walks
+        h[u] = (t[u] * 0x9E3779B1u) >> (32 - a.H_log2);
       }
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) cur[u] = t[u] != kNoNode ? load_l2(tab + h[u]) : kEmpty;
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u)
+        if (t[u] != kNoNode) table_insert(tab, mask, t[u], h[u], cur[u]);
     }
     for (uint32_t b = tid; b < kHistBins; b += kBigThreads) hist[b] = 0;
-    __threadfence();
-    __syncthreads();
+    table_sync();
 
     // 2. digest, distinct endpoints, count histogram
     uint64_t dg = 0, nd = 0;
-    for (uint32_t h = tid; h < H; h += kBigThreads) {
-      const uint64_t e = load_l2(tab + h);
-      if (e != kEmpty) {
-        const uint32_t t = static_cast<uint32_t>(e >> 32), c = static_cast<uint32_t>(e);
-        dg += digest_term(src, t, c);
-        ++nd;
-        atomicAdd(&hist[c < kHistBins - 1 ? c : kHistBins - 1], 1u);
-      }
-    }
+    table_pass<false>(tab, H, [&](uint64_t e) {
+      const uint32_t t = static_cast<uint32_t>(e >> 32), c = static_cast<uint32_t>(e);
+      dg += digest_term(src, t, c);
+      ++nd;
+      atomicAdd(&hist[c < kHistBins - 1 ? c : kHistBins - 1], 1u);
+    });
     dg = block_sum_u64(dg, red);
     nd = block_sum_u64(nd, red);
     if (tid == 0) {
@@ -416,13 +467,12 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
       for (int shift = 56; shift >= 0; shift -= 8) {
         for (uint32_t b = tid; b < 256; b += kBigThreads) hist[b] = 0;
         __syncthreads();
-        for (uint32_t h = tid; h < H; h += kBigThreads) {
-          const uint64_t e = load_l2(tab + h);
-          if (e == kEmpty || static_cast<uint32_t>(e) < cstar) continue;
+        table_pass<false>(tab, H, [&](uint64_t e) {
+          if (static_cast<uint32_t>(e) < cstar) return;
           const uint64_t key = rank_key(e);
           if (shift == 56 || (key >> (shift + 8)) == (prefix >> (shift + 8)))
             atomicAdd(&hist[(key >> shift) & 255u], 1u);
-        }
+        });
         __syncthreads();
         const uint32_t v = tid < 256 ? hist[255 - tid] : 0u;
         uint64_t tot;
@@ -443,15 +493,12 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
 
     // 4. collect the selected entries and empty the table
     const uint64_t kmin = mode == 2 ? s_key : 0ull;
-    for (uint32_t h = tid; h < H; h += kBigThreads) {
-      const uint64_t e = load_l2(tab + h);
-      if (e == kEmpty) continue;
+    table_pass<true>(tab, H, [&](uint64_t e) {
       bool take = false;
       if (mode == 1) take = static_cast<uint32_t>(e) >= cstar;
       else if (mode == 2) take = rank_key(e) >= kmin;
       if (take) cand[atomicAdd(&s_n, 1u)] = rank_key(e);
-      tab[h] = kEmpty;
-    }
+    });
     __syncthreads();
 
     // 5. sort the candidates (descending) and write the top-k row
@@ -488,8 +535,7 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
         a.topk[(row * a.k + q) * 2 + 1] = c;
       }
     }
-    __threadfence();
-    __syncthreads();
+    table_sync();  // the emptied table is seen by the next row's probes
   }
 }
 

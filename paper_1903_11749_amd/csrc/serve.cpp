@@ -5,7 +5,7 @@
 // made at create). Every admitted query owns its sources, endpoint buffer and
 // outputs. The thread issues walk slices on the walk stream: one walk launch
 // over a table that gives each admitted query with walks left a share of the
-// slice (an equal share first, the rest in admission order), so a query that
+// slice (half in equal shares, the rest in admission order), so a query that
 // arrives while others run joins at the next slice. Walk ids of a query are
 // scheduled in order across slices; the walk index, not the slice, keys the
 // draws. After the slice holding a query's last walks, its counting and top-k
@@ -319,9 +319,12 @@ void loop(fppr_server* S) {
         }
         S->ring_busy[slot] = false;
       }
+      // half of the slice in equal shares (a small query finishes in one
+      // slice), the rest to the oldest queries first (the head keeps at least
+      // half the rate, which bounds the tail latency)
       const uint64_t na = active.size();
       uint64_t budget = S->o.slice_walks;
-      uint64_t fair = budget / na / kWalkChunk * kWalkChunk;
+      uint64_t fair = budget / 2 / na / kWalkChunk * kWalkChunk;
       if (fair < kWalkChunk) fair = kWalkChunk;
       take.assign(na, 0);
       for (uint64_t i = 0; i < na && budget; ++i) {
