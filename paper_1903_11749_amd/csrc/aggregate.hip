@@ -292,18 +292,23 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
 
 // ---------------------------------------------------------------------------
 // R > kAggMaxR (large walk budgets, up to 2^20 per source): one 1024-thread
-// block per source at a time, counting in an open-addressing hash table in
-// global memory (one 8-byte slot = t << 32 | count, empty = kEmpty, at most
-// half full). A pass over the table gives the digest, the number of distinct
-// endpoints and a histogram of min(count, 2047); a block scan of the
-// histogram from the top gives the count threshold of the k-th entry. The
-// entries at or above it are sorted in LDS by (count desc, t asc) when they
-// fit; otherwise an exact radix select over the 64-bit ranking keys finds the
-// k-th key first. The last pass also empties the table for the next source.
+// block per source at a time, the only block on its compute unit. Walks from
+// one source pile up on a few nearby nodes, so counting starts in a
+// 16384-slot hash table in LDS (128 KB), where contended atomics are cheap.
+// An endpoint that finds no LDS slot within 8 probes goes to an
+// open-addressing hash table in global memory (one 8-byte slot = t << 32 |
+// count, empty = kEmpty, at most half full); later steps visit the LDS
+// entries and, when something spilled, the global table. A pass over the
+// entries gives the digest, the number of distinct endpoints
+// and a histogram of min(count, 2047); a block scan of the histogram from the
+// top gives the count threshold of the k-th entry. The entries at or above it
+// are sorted in LDS by (count desc, t asc) when at most 2048; otherwise an
+// exact radix select over the 64-bit ranking keys finds the k-th key first.
+// The last pass over a global table also empties it for the next source.
 // ---------------------------------------------------------------------------
 constexpr int kBigThreads = 1024;
 constexpr uint32_t kHistBins = 2048;
-constexpr uint32_t kCandCap = 4096;
+constexpr uint32_t kCandCap = 2048;
 constexpr uint64_t kEmpty = 0xFFFFFFFF00000000ull;
 
 // loads that see other threads' atomics (served by L2, not the CU's cache)
@@ -311,13 +316,13 @@ __device__ __forceinline__ uint64_t load_l2(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Makes the block's table writes (atomics performed in L2, plain stores) visible
-// to its later plain loads: release at agent scope, barrier, then an acquire
-// that invalidates the compute unit's vector cache.
+// Makes the block's table writes (atomics, plain stores) visible to its later
+// plain loads: only this block touches its table, so release and acquire at
+// workgroup scope around the barrier are enough.
 __device__ __forceinline__ void table_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // ranking key: larger = earlier in the top-k (count desc, then t asc)
@@ -371,11 +376,12 @@ __device__ __forceinline__ void table_pass(uint64_t* tab, uint32_t H, F&& f) {
 
 // Adds one walk ending at t to the table, starting from slot h whose value
 // was read as cur.
-__device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint32_t t, uint32_t h, uint64_t cur) {
+__device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint32_t t, uint32_t c, uint32_t h,
+                                             uint64_t cur) {
   for (;;) {
     if (cur != kEmpty) {
       if ((cur >> 32) == t) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), 1ull);
+        atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), static_cast<unsigned long long>(c));
         return;
       }
       h = (h + 1) & mask;
@@ -384,49 +390,122 @@ __device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint3
     }
     const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(tab + h),
                                    static_cast<unsigned long long>(kEmpty),
-                                   static_cast<unsigned long long>((static_cast<uint64_t>(t) << 32) | 1u));
+                                   static_cast<unsigned long long>((static_cast<uint64_t>(t) << 32) | c));
     if (old == kEmpty) return;
     cur = old;  // taken meanwhile: look at what is there now
   }
 }
 
+constexpr uint32_t kLdsLog2 = 14;
+constexpr uint32_t kLdsSlots = 1u << kLdsLog2;  // LDS counting table: keys + counts, 128 KB
+constexpr uint32_t kLdsProbes = 8;
+static_assert(kLdsSlots % (4 * kBigThreads) == 0, "whole flush rounds");
+
+// Counts t in the LDS table (keys lk, counts lc; empty key kNoNode); false if
+// no slot was free within kLdsProbes probes. Double hashing (an odd stride
+// from a second hash) keeps probe windows from running into each other.
+__device__ __forceinline__ bool lds_insert(uint32_t* lk, uint32_t* lc, uint32_t t) {
+  uint32_t h = (t * 0x9E3779B1u) >> (32 - kLdsLog2);
+  const uint32_t step = ((t * 0x85EBCA6Bu) >> (32 - kLdsLog2)) | 1u;
+  for (uint32_t p = 0; p < kLdsProbes; ++p) {
+    uint32_t k = lk[h];
+    if (k == kNoNode) {
+      k = atomicCAS(&lk[h], kNoNode, t);
+      if (k == kNoNode) k = t;
+    }
+    if (k == t) {
+      atomicAdd(&lc[h], 1u);
+      return true;
+    }
+    h = (h + step) & (kLdsSlots - 1);
+  }
+  return false;
+}
+
+// Adds c[u] walks ending at t[u] to the global table for the live ones of four
+// keys: each first claims its home slot optimistically, all four claims in
+// flight together; a key that meets another key there probes on alone.
+__device__ __forceinline__ void table_insert4(uint64_t* tab, uint32_t log2, const uint32_t (&t)[4],
+                                              const uint32_t (&c)[4], const bool (&live)[4]) {
+  const uint32_t mask = (1u << log2) - 1;
+  uint32_t h[4];
+  uint64_t old[4];
+#pragma unroll
+  for (uint32_t u = 0; u < 4; ++u) {
+    h[u] = (t[u] * 0x9E3779B1u) >> (32 - log2);
+    old[u] = live[u] ? atomicCAS(reinterpret_cast<unsigned long long*>(tab + h[u]),
+                                 static_cast<unsigned long long>(kEmpty),
+                                 static_cast<unsigned long long>((static_cast<uint64_t>(t[u]) << 32) | c[u]))
+                     : kEmpty;
+  }
+#pragma unroll
+  for (uint32_t u = 0; u < 4; ++u)
+    if (live[u] && old[u] != kEmpty) table_insert(tab, mask, t[u], c[u], h[u], old[u]);
+}
+
 __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
+  __shared__ uint32_t lk[kLdsSlots];
+  __shared__ uint32_t lc[kLdsSlots];
   __shared__ uint32_t hist[kHistBins];
   __shared__ uint64_t cand[kCandCap];
   __shared__ uint64_t red[kBigThreads / 64];
   __shared__ uint64_t s_key;      // threshold key (radix path)
-  __shared__ uint32_t s_cstar, s_cand, s_n, s_digit, s_rem;
+  __shared__ uint32_t s_cstar, s_cand, s_n, s_digit, s_rem, s_spill;
   const uint32_t tid = threadIdx.x;
   const uint32_t H = 1u << a.H_log2;
   const uint32_t mask = H - 1;
   uint64_t* tab = a.table + (static_cast<uint64_t>(blockIdx.x) << a.H_log2);
   const uint32_t R = a.R;
+  (void)mask;
 
   for (uint64_t row = blockIdx.x; row < a.n_src; row += gridDim.x) {
     const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
     const uint32_t* ep = a.endpoints + row * R;
-    // 1. count: four endpoints per thread at a time, their first probes together
+    // 1. count: LDS first, the global table for what does not fit there
+    for (uint32_t i = tid; i < kLdsSlots; i += kBigThreads) {
+      lk[i] = kNoNode;
+      lc[i] = 0;
+    }
+    for (uint32_t b = tid; b < kHistBins; b += kBigThreads) hist[b] = 0;
+    if (tid == 0) s_spill = 0;
+    __syncthreads();
+    bool spilled = false;
     for (uint32_t i0 = tid; i0 < R; i0 += 4 * kBigThreads) {
-      uint32_t t[4], h[4];
-      uint64_t cur[4];
+      uint32_t t[4];
+      const uint32_t one[4] = {1u, 1u, 1u, 1u};
+      bool g[4];
 #pragma unroll
       for (uint32_t u = 0; u < 4; ++u) {
         const uint32_t i = i0 + u * kBigThreads;
         t[u] = i < R ? ep[i] : kNoNode;  // kNoNode: a source that got no walks
-        h[u] = (t[u] * 0x9E3779B1u) >> (32 - a.H_log2);
       }
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) cur[u] = t[u] != kNoNode ? load_l2(tab + h[u]) : kEmpty;
-#pragma unroll
-      for (uint32_t u = 0; u < 4; ++u)
-        if (t[u] != kNoNode) table_insert(tab, mask, t[u], h[u], cur[u]);
+      for (uint32_t u = 0; u < 4; ++u) {
+        g[u] = t[u] != kNoNode && !lds_insert(lk, lc, t[u]);
+        spilled |= g[u];
+      }
+      if (g[0] || g[1] || g[2] || g[3]) table_insert4(tab, a.H_log2, t, one, g);
     }
-    for (uint32_t b = tid; b < kHistBins; b += kBigThreads) hist[b] = 0;
+    if (spilled) s_spill = 1;
     table_sync();
+    // A key is in exactly one of the tables: LDS slots only ever go from
+    // empty to a key, so a key whose probe window was full stays out of LDS.
+    const bool spill = s_spill != 0;
+    auto each_lds = [&](auto&& f) {
+      for (uint32_t i = tid; i < kLdsSlots; i += kBigThreads) {
+        const uint32_t k = lk[i];
+        if (k != kNoNode) f((static_cast<uint64_t>(k) << 32) | lc[i]);
+      }
+    };
+    // every entry once
+    auto each = [&](auto&& f) {
+      each_lds(f);
+      if (spill) table_pass<false>(tab, H, f);
+    };
 
     // 2. digest, distinct endpoints, count histogram
     uint64_t dg = 0, nd = 0;
-    table_pass<false>(tab, H, [&](uint64_t e) {
+    each([&](uint64_t e) {
       const uint32_t t = static_cast<uint32_t>(e >> 32), c = static_cast<uint32_t>(e);
       dg += digest_term(src, t, c);
       ++nd;
@@ -467,7 +546,7 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
       for (int shift = 56; shift >= 0; shift -= 8) {
         for (uint32_t b = tid; b < 256; b += kBigThreads) hist[b] = 0;
         __syncthreads();
-        table_pass<false>(tab, H, [&](uint64_t e) {
+        each([&](uint64_t e) {
           if (static_cast<uint32_t>(e) < cstar) return;
           const uint64_t key = rank_key(e);
           if (shift == 56 || (key >> (shift + 8)) == (prefix >> (shift + 8)))
@@ -491,14 +570,16 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
     if (tid == 0) s_n = 0;
     __syncthreads();
 
-    // 4. collect the selected entries and empty the table
+    // 4. collect the selected entries (and empty the global table)
     const uint64_t kmin = mode == 2 ? s_key : 0ull;
-    table_pass<true>(tab, H, [&](uint64_t e) {
+    auto collect = [&](uint64_t e) {
       bool take = false;
       if (mode == 1) take = static_cast<uint32_t>(e) >= cstar;
       else if (mode == 2) take = rank_key(e) >= kmin;
       if (take) cand[atomicAdd(&s_n, 1u)] = rank_key(e);
-    });
+    };
+    each_lds(collect);
+    if (spill) table_pass<true>(tab, H, collect);
     __syncthreads();
 
     // 5. sort the candidates (descending) and write the top-k row

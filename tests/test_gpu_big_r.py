@@ -90,6 +90,24 @@ def test_big_r_ties_radix_select(fp):
         check(o, ref)
 
 
+def test_big_r_spill_to_global_table(fp):
+    """Walks over 60000 leaves reach more distinct endpoints than the
+    16384-slot LDS table holds (about 48000 for R = 100000, 19400 for
+    R = 25000), so counting spills to the global table; for R = 25000 and
+    k = 1024 about 4100 entries reach the threshold count 2, more than the
+    2048 the sort holds, so the radix select runs over the global table."""
+    say("case: star, 60000 leaves, spill to the global table")
+    rng = np.random.default_rng(12)
+    g = star(60000, rng.integers(1, 4, 60000).astype(np.uint32))
+    G = fp.Graph(g)
+    og = O.Graph.from_csr(g)
+    src = np.array([0, 0, 7], np.uint32)
+    for R, k in ((100000, 64), (25000, 1024)):
+        o = fp.run(G, 0.97, R, 4, sources=src, topk=k, counts=False)
+        ref = O.run(og, 0.97, R, 4, sources=src, topk=k, want_counts=False)
+        check(o, ref)
+
+
 def test_big_r_padding_and_hub(fp):
     say("case: fewer distinct endpoints than k; weighted hub")
     rng = np.random.default_rng(11)
