@@ -637,15 +637,17 @@ uint32_t agg_table_groups(uint64_t n_src, uint32_t R) {
   return static_cast<uint32_t>(g ? g : 1);
 }
 
-uint64_t agg_table_bytes(uint64_t n_src, uint32_t R) {
-  if (R <= kAggMaxR || n_src == 0) return 0;
+bool agg_uses_table(uint32_t R, bool counts) { return R > kAggWaveMaxR && !counts; }
+
+uint64_t agg_table_bytes(uint64_t n_src, uint32_t R, bool counts) {
+  if (!agg_uses_table(R, counts) || n_src == 0) return 0;
   return static_cast<uint64_t>(agg_table_groups(n_src, R)) << (agg_table_log2(R) + 3);
 }
 
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s) {
   if (a.n_src == 0) return hipSuccess;
-  if (a.R > kAggMaxR) {
-    if (!a.table || a.counts) return hipErrorInvalidValue;
+  if (agg_uses_table(a.R, a.counts != nullptr)) {
+    if (!a.table) return hipErrorInvalidValue;
     AggLaunch b = a;
     b.H_log2 = agg_table_log2(a.R);
     const uint32_t groups = agg_table_groups(a.n_src, a.R);

@@ -69,7 +69,8 @@ uint64_t endpoint_bytes(const fppr_batch_item& it) {
 uint64_t table_bytes(const fppr_batch_item* items, uint32_t count) {
   uint64_t t = 0;
   for (uint32_t k = 0; k < count; ++k) {
-    const uint64_t b = align_up(agg_table_bytes(item_sources(items[k]), items[k].params.R));
+    const uint64_t b = align_up(agg_table_bytes(item_sources(items[k]), items[k].params.R,
+                                                 (items[k].params.flags & FPPR_COUNTS) != 0));
     if (b > t) t = b;
   }
   return t;

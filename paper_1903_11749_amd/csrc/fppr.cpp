@@ -470,7 +470,7 @@ FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64
   if (st != FPPR_OK) return st;
   if (!workspace_bytes) return invalid("workspace_bytes is NULL");
   *workspace_bytes = kCtlBytes + kDescBytes + align_up(n_sources * p->R * 4ull) +
-                     agg_table_bytes(n_sources, p->R);
+                     agg_table_bytes(n_sources, p->R, (p->flags & FPPR_COUNTS) != 0);
   return FPPR_OK;
 }
 

@@ -130,19 +130,22 @@ struct AggLaunch {
   uint32_t* counts;
   uint32_t* n_distinct;
   uint64_t* digest;
-  uint64_t* table;   // R > kAggMaxR: agg_table_bytes of scratch (filled here)
+  uint64_t* table;   // agg_table_bytes of scratch when agg_uses_table (filled here)
   uint32_t H_log2;   // set by launch_aggregate
 };
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s);
 AggLaunch make_agg(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
                    uint64_t n_sources, const fppr_out* out);
-constexpr uint32_t kAggMaxR = 4096;      // largest R of the sorting paths (counts supported)
+constexpr uint32_t kAggWaveMaxR = 256;   // largest R of the one-wave-per-source path
+constexpr uint32_t kAggMaxR = 4096;      // largest R with counts (the LDS tile sort)
 constexpr uint32_t kMaxR = 1u << 20;     // largest R (hash path above kAggMaxR: no counts)
 constexpr uint32_t kAggBigGroups = 512;  // blocks (and hash tables) of the hash path
-// hash path: log2 of the slots per table, tables used, scratch bytes (0 when
-// R <= kAggMaxR)
+// Counting without per-source counts and R > kAggWaveMaxR takes the hash path,
+// which needs agg_table_bytes of scratch: log2 of the slots per global table,
+// the tables (= blocks) used, and the bytes (0 when the path is not taken).
+bool agg_uses_table(uint32_t R, bool counts);
 uint32_t agg_table_log2(uint32_t R);
 uint32_t agg_table_groups(uint64_t n_src, uint32_t R);
-uint64_t agg_table_bytes(uint64_t n_src, uint32_t R);
+uint64_t agg_table_bytes(uint64_t n_src, uint32_t R, bool counts);
 
 }  // namespace fppr

@@ -443,7 +443,7 @@ FPPR_API fppr_status fppr_server_create(fppr_graph* g, const fppr_server_opts* o
   FPPR_SERVE_TRY(e, "hipGetDevice");
   FPPR_SERVE_TRY(hipMalloc(&S->dev_base, align_up(o.memory_bytes)), "hipMalloc(server memory)");
   FPPR_SERVE_TRY(hipHostMalloc(&S->host_base, align_up(o.host_bytes), hipHostMallocDefault), "hipHostMalloc");
-  FPPR_SERVE_TRY(hipMalloc(&S->agg_table, std::max<uint64_t>(agg_table_bytes(kAggBigGroups, kMaxR), 256)),
+  FPPR_SERVE_TRY(hipMalloc(&S->agg_table, std::max<uint64_t>(agg_table_bytes(kAggBigGroups, kMaxR, false), 256)),
                  "hipMalloc(counting tables)");
   FPPR_SERVE_TRY(hipMalloc(&S->d_stats, sizeof(fppr_stats)), "hipMalloc(stats)");
   FPPR_SERVE_TRY(hipMemset(S->d_stats, 0, sizeof(fppr_stats)), "zero stats");

@@ -157,3 +157,19 @@ def test_batch_mixing_big_and_small_r(fp):
                     topk=it["topk"], want_counts=False)
         check(o, ref)
     B.close()
+
+
+def test_mid_r_hash_path_equals_sort_path(fp):
+    """256 < R <= 4096: with per-source counts the LDS tile sort runs, without
+    them the hash path; both give the oracle's top-k and digests."""
+    say("case: R in {257, 1000, 4096}, sort path vs hash path")
+    g = synth.chung_lu(8000, 90000, 2.2, 255, seed=2025)
+    G = fp.Graph(g)
+    og = O.Graph.from_csr(g)
+    src = np.arange(0, g.n, 41, dtype=np.uint32)
+    for R in (257, 1000, 4096):
+        with_counts = fp.run(G, 0.15, R, 6, sources=src, topk=32, counts=True)
+        hashed = fp.run(G, 0.15, R, 6, sources=src, topk=32, counts=False)
+        ref = O.run(og, 0.15, R, 6, sources=src, topk=32, want_counts=False)
+        check(with_counts, ref)
+        check(hashed, ref)
