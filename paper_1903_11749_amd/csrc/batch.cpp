@@ -1,6 +1,12 @@
 // Batches: several graphs or source sets served by one persistent walk
 // launch (the walk table holds one descriptor per item), then each item's
 // counting and top-k; optionally captured once into a HIP graph and replayed.
+// The per-graph rebuilds in front of the walks and the per-item counting after
+// them are independent of each other, so they are spread over four streams
+// (the caller's and three of the batch's, forked from and joined back into the
+// caller's): the many small kernels of small graphs overlap instead of running
+// one after another. Items whose counting uses the shared hash area stay on
+// the caller's stream, one after the other.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +23,7 @@ namespace {
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr uint64_t kCtlBytes = 256;
+constexpr int kLanes = 4;  // the caller's stream + 3 of the batch's
 
 fppr_status invalid(const std::string& msg) {
   set_error(msg);
@@ -41,6 +48,10 @@ struct fppr_batch {
   uint64_t total = 0;                 // padded walk ids
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipStream_t aux[kLanes - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kLanes - 1] = {};
+  std::vector<int> graph_lane, item_lane;  // lane of each graph's rebuild / item's counting
 };
 
 namespace {
@@ -78,19 +89,64 @@ uint64_t table_bytes(const fppr_batch_item* items, uint32_t count) {
 
 void free_batch(fppr_batch* b) {
   if (!b) return;
+  for (hipStream_t a : b->aux)
+    if (a) (void)hipStreamSynchronize(a);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipStream_t a : b->aux)
+    if (a) (void)hipStreamDestroy(a);
+  for (hipEvent_t e : b->join)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
 }
 
+// Greedy lanes: each job (largest first) goes to the least loaded lane.
+std::vector<int> assign_lanes(const std::vector<uint64_t>& cost, const std::vector<bool>& pinned) {
+  std::vector<uint32_t> order(cost.size());
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+  uint64_t load[kLanes] = {};
+  std::vector<int> lane(cost.size(), 0);
+  for (uint32_t k : order) {
+    int best = 0;
+    if (!pinned[k])
+      for (int l = 1; l < kLanes; ++l)
+        if (load[l] < load[best]) best = l;
+    lane[k] = best;
+    load[best] += cost[k] + 1;
+  }
+  return lane;
+}
+
+// Forks the batch's streams from s (they wait for everything enqueued on s
+// so far), or joins them back into s.
+hipError_t fork_lanes(fppr_batch* b, hipStream_t s) {
+  hipError_t e = hipEventRecord(b->fork, s);
+  for (int a = 0; a < kLanes - 1 && e == hipSuccess; ++a) e = hipStreamWaitEvent(b->aux[a], b->fork, 0);
+  return e;
+}
+hipError_t join_lanes(fppr_batch* b, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int a = 0; a < kLanes - 1 && e == hipSuccess; ++a) {
+    e = hipEventRecord(b->join[a], b->aux[a]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[a], 0);
+  }
+  return e;
+}
+
 fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStream_t s) {
+  auto lane = [&](int l) { return l == 0 ? s : b->aux[l - 1]; };
+  hipError_t e;
   if (b->opts.flags & FPPR_BATCH_REBUILD) {
-    for (fppr_graph* g : b->graphs) {
-      const fppr_status st = fppr_graph_rebuild(g, s);
+    if ((e = fork_lanes(b, s)) != hipSuccess) return hip_fail(e, "fork streams");
+    for (size_t k = 0; k < b->graphs.size(); ++k) {
+      const fppr_status st = fppr_graph_rebuild(b->graphs[k], lane(b->graph_lane[k]));
       if (st != FPPR_OK) return st;
     }
+    if ((e = join_lanes(b, s)) != hipSuccess) return hip_fail(e, "join streams");
   }
-  hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(b->ctl), kCtlBytes / 8, s);
+  e = launch_zero_u64(reinterpret_cast<uint64_t*>(b->ctl), kCtlBytes / 8, s);
   if (e != hipSuccess) return hip_fail(e, "zero control words");
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   e = launch_walk(b->table, static_cast<uint32_t>(b->host_table.size()), b->total, b->ctl, stats,
@@ -99,14 +155,16 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
   if (e != hipSuccess) return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
+  if ((e = fork_lanes(b, s)) != hipSuccess) return hip_fail(e, "fork streams");
   for (size_t k = 0; k < b->items.size(); ++k) {
     const fppr_batch_item& it = b->items[k];
     AggLaunch a = make_agg(&it.params, b->endpoints[k], it.sources, item_sources(it), &it.out);
     a.table = b->agg_table;
     if (a.topk || a.counts || a.digest) {
-      if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");
+      if ((e = launch_aggregate(a, lane(b->item_lane[k]))) != hipSuccess) return hip_fail(e, "aggregate kernel");
     }
   }
+  if ((e = join_lanes(b, s)) != hipSuccess) return hip_fail(e, "join streams");
   if (prof && (e = hipEventRecord(prof->ev[3], s)) != hipSuccess) return hip_fail(e, "event");
   return FPPR_OK;
 }
@@ -168,6 +226,30 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
     first += (walks + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
   }
   b->total = first;
+  {
+    std::vector<uint64_t> gcost(b->graphs.size());
+    std::vector<bool> gpin(b->graphs.size(), false);
+    for (size_t k = 0; k < b->graphs.size(); ++k) gcost[k] = b->graphs[k]->m + b->graphs[k]->n;
+    b->graph_lane = assign_lanes(gcost, gpin);
+    std::vector<uint64_t> icost(count);
+    std::vector<bool> ipin(count);
+    for (uint32_t k = 0; k < count; ++k) {
+      icost[k] = item_sources(items[k]) * items[k].params.R;
+      ipin[k] = agg_uses_table(items[k].params.R, (items[k].params.flags & FPPR_COUNTS) != 0);
+    }
+    b->item_lane = assign_lanes(icost, ipin);
+  }
+  {
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int a = 0; a < kLanes - 1 && e == hipSuccess; ++a) {
+      e = hipStreamCreateWithFlags(&b->aux[a], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[a], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(e, "batch streams");
+    }
+  }
   if (!b->host_table.empty()) {
     hipError_t e = hipMemcpy(b->table, b->host_table.data(), b->host_table.size() * sizeof(WalkDesc),
                              hipMemcpyHostToDevice);
