@@ -239,10 +239,24 @@ typedef struct {
 FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,
                                uint64_t* workspace_bytes);
 
+/* Memory-bounded runs (the bounded injection of Sec. 4.3: only as many walks
+ * as memory holds are in flight). The largest block of sources (<=
+ * n_sources) whose run fits budget_bytes of workspace (host outputs: the
+ * block and its fppr_plan bytes). INVALID_ARGUMENT if not one source fits.
+ * Pure host computation. */
+FPPR_API fppr_status fppr_plan_block(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,
+                                     uint64_t budget_bytes, uint64_t* block_sources,
+                                     uint64_t* workspace_bytes);
+
 /* Runs R walks from each source and aggregates them (Algorithm 2).
  * sources: device uint32 [n_sources] (each < n; duplicates allowed), or NULL
  * for all nodes 0..n-1 (then n_sources must equal n). n_sources == 0 is a
- * no-op. workspace: device, >= fppr_plan bytes. Asynchronous on `stream`. */
+ * no-op. workspace: device; with >= fppr_plan(n_sources) bytes one walk launch
+ * covers every source; with less (and out->endpoints == NULL) the sources run
+ * in blocks of the size fppr_plan_block gives for that many bytes, one walk
+ * launch and one counting launch per block, in order. Walk keys do not
+ * depend on the blocking, so the results are identical; a profile then
+ * reports the whole run as walk time. Asynchronous on `stream`. */
 FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_t* sources,
                               uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
                               const fppr_out* out, void* stream);

@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
             a.counts[(row * R + r) * 2 + 1] = c;
           }
           if (a.digest) {
-            const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
+            const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
             atomicAdd(&dig[seg], static_cast<unsigned long long>(digest_term(src, t, c)));
           }
         } else if (a.counts && r < R) {
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       before[e] = nd;
       nd += static_cast<uint32_t>(__popcll(hm[e]));
     }
-    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
+    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
     uint64_t dig = 0;
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
   (void)mask;
 
   for (uint64_t row = blockIdx.x; row < a.n_src; row += gridDim.x) {
-    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(row);
+    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
     const uint32_t* ep = a.endpoints + row * R;
     // 1. count: LDS first, the global table for what does not fit there
     for (uint32_t i = tid; i < kLdsSlots; i += kBigThreads) {

@@ -1,7 +1,9 @@
 // C-ABI of the library: graph lifetime, pool, planning and runs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -474,6 +476,28 @@ FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64
   return FPPR_OK;
 }
 
+FPPR_API fppr_status fppr_plan_block(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,
+                                     uint64_t budget_bytes, uint64_t* block_sources,
+                                     uint64_t* workspace_bytes) {
+  fppr_status st = check_params(g, p);
+  if (st != FPPR_OK) return st;
+  if (!block_sources || !workspace_bytes) return invalid("block_sources or workspace_bytes is NULL");
+  uint64_t need = 0;
+  fppr_plan(g, p, 1, &need);
+  if (n_sources == 0 || need > budget_bytes) return invalid("not even one source fits the budget");
+  // the plan grows with the block: the largest block that fits, by bisection
+  uint64_t lo = 1, hi = n_sources;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    fppr_plan(g, p, mid, &need);
+    if (need <= budget_bytes) lo = mid; else hi = mid - 1;
+  }
+  fppr_plan(g, p, lo, &need);
+  *block_sources = lo;
+  *workspace_bytes = need;
+  return FPPR_OK;
+}
+
 FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_t* sources,
                               uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
                               const fppr_out* out, void* stream) {
@@ -483,35 +507,59 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
   if (!sources && n_sources != g->n) return invalid("sources == NULL needs n_sources == n");
   if (n_sources == 0) return FPPR_OK;
   if (n_sources > (1ull << 40) / p->R) return invalid("n_sources * R too large");
-  uint64_t need = 0;
-  fppr_plan(g, p, n_sources, &need);
-  if (!workspace || workspace_bytes < need) return invalid("workspace missing or smaller than fppr_plan");
+  if (!workspace) return invalid("workspace is NULL");
   if ((st = check_outputs(p, out)) != FPPR_OK) return st;
   if ((p->flags & FPPR_STATS) && !out->stats) return invalid("FPPR_STATS needs out->stats");
+  uint64_t need = 0, block = n_sources;
+  fppr_plan(g, p, n_sources, &need);
+  if (workspace_bytes < need) {  // memory-bounded run: blocks of sources that fit
+    if (out->endpoints) return invalid("workspace smaller than fppr_plan (a blocked run needs out->endpoints == NULL)");
+    if (fppr_plan_block(g, p, n_sources, workspace_bytes, &block, &need) != FPPR_OK)
+      return invalid("workspace smaller than fppr_plan of one source");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto* ctl = static_cast<unsigned long long*>(workspace);
   auto* desc = reinterpret_cast<WalkDesc*>(static_cast<char*>(workspace) + kCtlBytes);
-  uint32_t* endpoints = out->endpoints
-                            ? out->endpoints
-                            : reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + kCtlBytes +
-                                                          kDescBytes);
-  hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(ctl), kCtlBytes / 8, s);
-  if (e != hipSuccess) return hip_fail(e, "zero control words");
-  const WalkDesc D = make_desc(g, p, sources, n_sources, endpoints, 0, 0, n_sources * p->R);
-  if ((e = launch_set_desc(D, desc, s)) != hipSuccess) return hip_fail(e, "walk descriptor");
-  const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
+  uint32_t* ws_ep = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + kCtlBytes + kDescBytes);
+  uint64_t* table = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + kCtlBytes + kDescBytes +
+                                                align_up(block * p->R * 4ull));
+  const bool blocked = block < n_sources;
   fppr_stats* stats = (p->flags & FPPR_STATS) ? out->stats : nullptr;
   fppr_profile* prof = out->profile;
+  hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t*>(ctl), kCtlBytes / 8, s);
+  if (e != hipSuccess) return hip_fail(e, "zero control words");
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
-  if ((e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
-    return hip_fail(e, "walk kernel");
-  if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
-  AggLaunch a = make_agg(p, endpoints, sources, n_sources, out);
-  a.table = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + kCtlBytes + kDescBytes +
-                                        align_up(n_sources * p->R * 4ull));
-  if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
-  if (a.topk || a.counts || a.digest) {
-    if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");
+  for (uint64_t r0 = 0; r0 < n_sources; r0 += block) {
+    const uint64_t nb = std::min(block, n_sources - r0);
+    // walk ids stay global (walk0 = r0 R): the kernel writes endpoints[w], so
+    // the block buffer is addressed through a pointer moved back by r0 R
+    uint32_t* ep_base = out->endpoints ? out->endpoints
+                                       : reinterpret_cast<uint32_t*>(reinterpret_cast<uintptr_t>(ws_ep) -
+                                                                     r0 * p->R * 4ull);
+    if (r0 > 0 && (e = launch_zero_u64(reinterpret_cast<uint64_t*>(ctl), 1, s)) != hipSuccess)
+      return hip_fail(e, "zero walk counter");  // the invalid-source flag accumulates
+    const WalkDesc D = make_desc(g, p, sources, n_sources, ep_base, 0, r0 * p->R, nb * p->R);
+    if ((e = launch_set_desc(D, desc, s)) != hipSuccess) return hip_fail(e, "walk descriptor");
+    const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
+    if ((e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
+      return hip_fail(e, "walk kernel");
+    if (prof && !blocked && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
+    AggLaunch a = make_agg(p, out->endpoints ? out->endpoints + r0 * p->R : ws_ep, sources ? sources + r0 : nullptr,
+                           nb, out);
+    a.row0 = sources ? 0 : r0;
+    if (a.topk) a.topk += r0 * a.k * 2;
+    if (a.counts) a.counts += r0 * p->R * 2;
+    if (a.n_distinct) a.n_distinct += r0;
+    if (a.digest) a.digest += r0;
+    a.table = table;
+    if (prof && !blocked && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
+    if (a.topk || a.counts || a.digest) {
+      if ((e = launch_aggregate(a, s)) != hipSuccess) return hip_fail(e, "aggregate kernel");
+    }
+  }
+  if (prof && blocked) {  // blocked runs: the walk time covers every block's walks and counting
+    if ((e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
   }
   if (prof && (e = hipEventRecord(prof->ev[3], s)) != hipSuccess) return hip_fail(e, "event");
   return FPPR_OK;

@@ -124,6 +124,7 @@ struct AggLaunch {
   const uint32_t* endpoints;
   const uint32_t* sources;
   uint64_t n_src;
+  uint64_t row0;     // without sources, row r is node row0 + r
   uint32_t R;
   uint32_t k;
   uint32_t* topk;

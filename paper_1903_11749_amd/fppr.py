@@ -144,6 +144,8 @@ _SIGS = [
     ("fppr_walks_for_guarantee", ctypes.c_uint64, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("fppr_plan", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_plan_block", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     ("fppr_run", ctypes.c_int, [P, ctypes.POINTER(fppr_params), P, ctypes.c_uint64, P, ctypes.c_uint64,
                                 ctypes.POINTER(fppr_out), P]),
     ("fppr_run_check", ctypes.c_int, [P, P]),
@@ -335,6 +337,15 @@ def make_params(alpha, R, seed, topk=0, stitch=False, counts=True, digests=True,
     return fppr_params(float(alpha), int(R), int(seed), int(topk), flags, int(blocks_per_cu))
 
 
+def fppr_plan_block(graph: Graph, params: fppr_params, n_sources: int, budget: int):
+    """(block_sources, workspace_bytes) of a memory-bounded run."""
+    b = ctypes.c_uint64()
+    ws = ctypes.c_uint64()
+    _check(lib().fppr_plan_block(graph.handle, ctypes.byref(params), n_sources, budget, ctypes.byref(b),
+                                 ctypes.byref(ws)))
+    return int(b.value), int(ws.value)
+
+
 def fppr_plan(graph: Graph, params: fppr_params, n_sources: int) -> int:
     ws = ctypes.c_uint64()
     _check(lib().fppr_plan(graph.handle, ctypes.byref(params), n_sources, ctypes.byref(ws)))
@@ -413,7 +424,8 @@ def fppr_run_check(workspace, stream=None):
 
 
 def run(graph: Graph, alpha, R, seed, sources=None, topk=0, stitch=False, counts=True,
-        digests=True, stats=True, endpoints=False, stream=None, check=True, blocks_per_cu=0) -> Outputs:
+        digests=True, stats=True, endpoints=False, stream=None, check=True, blocks_per_cu=0,
+        max_workspace=None) -> Outputs:
     """Allocates workspace and outputs with torch, runs, and returns the outputs
     (device tensors). sources: None (all nodes) or an int sequence / tensor."""
     import torch
@@ -428,6 +440,8 @@ def run(graph: Graph, alpha, R, seed, sources=None, topk=0, stitch=False, counts
         n_src = int(src.numel())
     p = make_params(alpha, R, seed, topk, stitch, counts, digests, stats, blocks_per_cu)
     ws_bytes = fppr_plan(graph, p, n_src)
+    if max_workspace is not None and max_workspace < ws_bytes:
+        _, ws_bytes = fppr_plan_block(graph, p, n_src, max_workspace)
     ws = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device="cuda")
     out = alloc_outputs(n_src, R, topk, counts, digests, stats, endpoints)
     fppr_run(graph, p, src, n_src, ws, out, stream)
