@@ -286,7 +286,7 @@ def bench_serve(args, fppr, torch, G, n_nodes, oracle_pool=None, oracle_graph=No
     base = synth.poisson_queries(n_nodes, nq + warm, qps=1.0, seed=5000)
     queries = [dict(sources=q["sources"], R=q["R"], seed=q["seed"]) for q in base]
     unit_times = np.array([q["arrival"] for q in base])  # arrivals at 1 query/s
-    kw = dict(max_requests=64, memory_bytes=24 << 30, host_bytes=2 << 30, slice_walks=1 << 23)
+    kw = dict(max_requests=64, memory_bytes=24 << 30, host_bytes=2 << 30, slice_walks=args.slice_walks)
     # saturation: everything submitted at once (closed burst)
     burst = queries[:args.serve_burst]
     _, _, fifo_span, _ = _serve_run(fppr, G, burst, "fifo", **kw)
@@ -363,6 +363,7 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-burst", type=int, default=300, help="queries of the saturation bursts")
+    ap.add_argument("--slice-walks", type=int, default=1 << 26, help="walks per continuous-batching slice")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled parity check")

@@ -8,7 +8,10 @@
 // slice (half in equal shares, the rest in admission order), so a query that
 // arrives while others run joins at the next slice. Walk ids of a query are
 // scheduled in order across slices; the walk index, not the slice, keys the
-// draws. After the slice holding a query's last walks, its counting and top-k
+// draws. Slices alternate between two walk streams, so the next slice starts
+// on the compute units that the current slice's longest walks leave idle (a
+// launch otherwise ends with ~0.5 ms in which only its last walks run). After
+// the slice holding a query's last walks, its counting and top-k
 // run on the aggregation stream (waiting on that slice's event), the results
 // are copied to pinned host memory and an event marks the query done. At most
 // two slices are in flight, so the host builds the next table while the GPU
@@ -145,6 +148,9 @@ struct fppr_server {
   uint64_t* agg_table = nullptr;  // hash tables of R > 4096 counting (one stream uses them)
   fppr_stats* d_stats = nullptr;
   hipStream_t walk_s = nullptr, agg_s = nullptr;
+  hipStream_t walk2_s = nullptr;  // continuous mode: slices alternate between walk_s and walk2_s
+  hipStream_t up_s = nullptr;     // continuous mode: source uploads
+  hipEvent_t up_ev = nullptr;     // recorded after the latest upload
   WalkDesc* h_tab[kRing] = {};
   WalkDesc* d_tab[kRing] = {};
   unsigned long long* d_ctl[kRing] = {};
@@ -193,18 +199,19 @@ bool enqueue_aggregate(fppr_server* S, Req* r, hipStream_t s) {
   return true;
 }
 
-// Launches one walk table held in ring slot `slot` (host copy filled).
-bool launch_slot(fppr_server* S, int slot, uint32_t nd, uint64_t total) {
+// Launches one walk table held in ring slot `slot` (host copy filled) on
+// stream ws.
+bool launch_slot(fppr_server* S, int slot, uint32_t nd, uint64_t total, hipStream_t ws) {
   hipError_t e;
   if ((e = hipMemcpyAsync(S->d_tab[slot], S->h_tab[slot], nd * sizeof(WalkDesc), hipMemcpyHostToDevice,
-                          S->walk_s)) != hipSuccess)
+                          ws)) != hipSuccess)
     return fail(S, e, "upload walk table");
-  if ((e = launch_zero_u64(reinterpret_cast<uint64_t*>(S->d_ctl[slot]), kCtlBytes / 8, S->walk_s)) != hipSuccess)
+  if ((e = launch_zero_u64(reinterpret_cast<uint64_t*>(S->d_ctl[slot]), kCtlBytes / 8, ws)) != hipSuccess)
     return fail(S, e, "zero control words");
-  if ((e = launch_walk(S->d_tab[slot], nd, total, S->d_ctl[slot], S->d_stats, S->o.blocks_per_cu, S->walk_s,
+  if ((e = launch_walk(S->d_tab[slot], nd, total, S->d_ctl[slot], S->d_stats, S->o.blocks_per_cu, ws,
                        same_graph_table(S->h_tab[slot], nd))) != hipSuccess)
     return fail(S, e, "walk kernel");
-  if ((e = hipEventRecord(S->ev[slot], S->walk_s)) != hipSuccess) return fail(S, e, "event record");
+  if ((e = hipEventRecord(S->ev[slot], ws)) != hipSuccess) return fail(S, e, "event record");
   S->ring_busy[slot] = true;
   std::lock_guard<std::mutex> lk(S->mu);
   ++S->st.walk_launches;
@@ -224,6 +231,7 @@ void loop(fppr_server* S) {
   std::deque<Req*> aggregating;  // done events pending (stream order)
   std::deque<int> slices;        // ring slots in flight (launch order)
   int ring = 0;
+  uint64_t slice_no = 0;
   std::vector<uint64_t> take;
 
   for (;;) {
@@ -277,7 +285,9 @@ void loop(fppr_server* S) {
       }
     }
     for (Req* r : admitted) {
-      hipError_t e = hipMemcpyAsync(r->d_src, r->h_src, r->n * 4ull, hipMemcpyHostToDevice, S->walk_s);
+      hipError_t e = hipMemcpyAsync(r->d_src, r->h_src, r->n * 4ull, hipMemcpyHostToDevice,
+                                    fifo ? S->walk_s : S->up_s);
+      if (e == hipSuccess && !fifo) e = hipEventRecord(S->up_ev, S->up_s);
       if (e != hipSuccess) {
         fail(S, e, "upload sources");
         return;
@@ -301,7 +311,7 @@ void loop(fppr_server* S) {
       S->h_tab[slot][0] = make_desc(S->g, &r->p, r->d_src, r->n, r->d_ep, 0, 0, r->walks);
       r->next = r->walks;
       const uint64_t total = (r->walks + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
-      if (!launch_slot(S, slot, 1, total)) return;
+      if (!launch_slot(S, slot, 1, total, S->walk_s)) return;
       slices.push_back(slot);
       if (!enqueue_aggregate(S, r, S->walk_s)) return;
       aggregating.push_back(r);
@@ -346,7 +356,14 @@ void loop(fppr_server* S) {
         first += (take[i] + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
         r->next += take[i];
       }
-      if (!launch_slot(S, slot, nd, first)) return;
+      // Slices alternate between two streams: the next slice's blocks start
+      // on the compute units that the current slice's last walks leave idle.
+      hipStream_t ws = (slice_no++ & 1) ? S->walk2_s : S->walk_s;
+      if (hipStreamWaitEvent(ws, S->up_ev, 0) != hipSuccess) {
+        fail(S, hipErrorUnknown, "wait for source uploads");
+        return;
+      }
+      if (!launch_slot(S, slot, nd, first, ws)) return;
       slices.push_back(slot);
       {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -360,10 +377,14 @@ void loop(fppr_server* S) {
           continue;
         }
         if (!waited) {
-          hipError_t e = hipStreamWaitEvent(S->agg_s, S->ev[slot], 0);
-          if (e != hipSuccess) {
-            fail(S, e, "stream wait");
-            return;
+          // every slice still in flight (this one and at most one before it,
+          // on the other stream) may hold walks of the finished queries
+          for (int x : slices) {
+            hipError_t e = hipStreamWaitEvent(S->agg_s, S->ev[x], 0);
+            if (e != hipSuccess) {
+              fail(S, e, "stream wait");
+              return;
+            }
           }
           waited = true;
         }
@@ -401,6 +422,9 @@ void free_server(fppr_server* S) {
   if (S->agg_table) (void)hipFree(S->agg_table);
   if (S->d_stats) (void)hipFree(S->d_stats);
   if (S->walk_s) (void)hipStreamDestroy(S->walk_s);
+  if (S->walk2_s) (void)hipStreamDestroy(S->walk2_s);
+  if (S->up_s) (void)hipStreamDestroy(S->up_s);
+  if (S->up_ev) (void)hipEventDestroy(S->up_ev);
   if (S->agg_s) (void)hipStreamDestroy(S->agg_s);
   delete S;
 }
@@ -448,6 +472,10 @@ FPPR_API fppr_status fppr_server_create(fppr_graph* g, const fppr_server_opts* o
   FPPR_SERVE_TRY(hipMalloc(&S->d_stats, sizeof(fppr_stats)), "hipMalloc(stats)");
   FPPR_SERVE_TRY(hipMemset(S->d_stats, 0, sizeof(fppr_stats)), "zero stats");
   FPPR_SERVE_TRY(hipStreamCreateWithFlags(&S->walk_s, hipStreamNonBlocking), "stream");
+  FPPR_SERVE_TRY(hipStreamCreateWithFlags(&S->walk2_s, hipStreamNonBlocking), "stream");
+  FPPR_SERVE_TRY(hipStreamCreateWithFlags(&S->up_s, hipStreamNonBlocking), "stream");
+  FPPR_SERVE_TRY(hipEventCreateWithFlags(&S->up_ev, hipEventDisableTiming), "event");
+  FPPR_SERVE_TRY(hipEventRecord(S->up_ev, S->up_s), "event record");
   FPPR_SERVE_TRY(hipStreamCreateWithFlags(&S->agg_s, hipStreamNonBlocking), "stream");
   for (int i = 0; i < kRing; ++i) {
     FPPR_SERVE_TRY(hipHostMalloc(&S->h_tab[i], o.max_requests * sizeof(WalkDesc), hipHostMallocDefault),

@@ -531,7 +531,7 @@ class Server:
     from poll() while the query runs."""
 
     def __init__(self, graph: Graph, mode="continuous", max_requests=64, memory_bytes=16 << 30,
-                 host_bytes=256 << 20, slice_walks=1 << 22, blocks_per_cu=0):
+                 host_bytes=256 << 20, slice_walks=1 << 26, blocks_per_cu=0):
         o = fppr_server_opts(FPPR_SERVE_FIFO if mode == "fifo" else FPPR_SERVE_CONTINUOUS, max_requests,
                              memory_bytes, host_bytes, slice_walks, blocks_per_cu)
         h = ctypes.c_void_p()
