@@ -42,7 +42,7 @@ namespace fppr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint32_t kInlineRestarts = 8;  // restarts handled per iteration
+constexpr uint32_t kInlineRestarts = 4;  // restarts handled per iteration (4 measured fastest of 2..16)
 
 enum : uint32_t {
   kIdle = 0,
