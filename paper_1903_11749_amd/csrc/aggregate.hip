@@ -201,6 +201,40 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       const uint32_t idx = e * 64 + lane;
       v[e] = idx < R ? a.endpoints[row * R + idx] : kPad;
     }
+    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
+    // Every walk of the source ended at the same node (always the case for a
+    // source without out-edges, whose walks restart at it until they stop):
+    // one distinct endpoint with count R, no sorting.
+    {
+      const uint32_t t0 = static_cast<uint32_t>(__shfl(static_cast<int>(v[0]), 0, 64));
+      bool same = true;
+#pragma unroll
+      for (uint32_t e = 0; e < E; ++e) same = same && (e * 64 + lane >= R || v[e] == t0);
+      if (__ballot(!same) == 0) {
+        const uint32_t nd = t0 != kPad ? 1u : 0u;
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+          const uint32_t idx = e * 64 + lane;
+          if (a.counts && idx < R) {
+            const bool head = idx < nd;
+            a.counts[(row * R + idx) * 2] = head ? t0 : 0u;
+            a.counts[(row * R + idx) * 2 + 1] = head ? R : 0u;
+          }
+        }
+        if (lane == 0) {
+          if (a.n_distinct) a.n_distinct[row] = nd;
+          if (a.digest) a.digest[row] = nd ? digest_term(src, t0, R) : 0ull;
+        }
+        if (a.topk) {
+          for (uint32_t q = lane; q < a.k; q += 64) {
+            const bool head = q < nd;
+            a.topk[(row * a.k + q) * 2] = head ? t0 : kNoNode;
+            a.topk[(row * a.k + q) * 2 + 1] = head ? R : 0u;
+          }
+        }
+        continue;
+      }
+    }
     wave_bitonic<E>(v);
 
     // run heads: first element of each group of equal endpoints
@@ -222,7 +256,6 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       before[e] = nd;
       nd += static_cast<uint32_t>(__popcll(hm[e]));
     }
-    const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
     uint64_t dig = 0;
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
