@@ -42,6 +42,7 @@ namespace fppr {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk (rows spanned + 1)
 constexpr uint32_t kInlineRestarts = 4;  // restarts handled per iteration (4 measured fastest of 2..16)
 
 enum : uint32_t {
@@ -112,6 +113,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   __shared__ uint64_t sh_line[kThreads / 64][64];
   __shared__ uint64_t sh_x[kThreads / 64][64];
   __shared__ uint32_t sh_res[kThreads / 64][64];
+  __shared__ uint32_t sh_src[kThreads / 64][kSrcBuf];  // the current chunk's source ids
   const uint32_t lane = __lane_id();
   const uint32_t wv = threadIdx.x / 64;
   Lane L{};
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   const Block* blocks = nullptr;
   const uint32_t* sources = nullptr;
   uint32_t* endpoints = nullptr;
-  uint64_t first = 0, walk0 = 0, R_magic = 0;
+  uint64_t first = 0, walk0 = 0, R_magic = 0, src_q0 = 0;
   uint32_t R = 1, n = 0, T = 0, key0 = 0, key1 = 0, tree_min = 0, K_log2 = 0;
 
   for (;;) {
@@ -188,6 +190,21 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         pend = kNoChunk;
         cur = c;
         if (c + kWalkChunk < end) end = c + kWalkChunk;
+        if (sources) {
+          // the chunk's source rows [q_lo, q_hi] to LDS in one coalesced load,
+          // so that refills read source ids without waiting on memory
+          auto row_of = [&](uint64_t id) {
+            const uint64_t wi = walk0 + (id - first);
+            uint64_t q = __umul64hi(wi, R_magic);
+            if (wi - q * R >= R) q += 1;
+            return q;
+          };
+          const uint64_t q_lo = row_of(cur), q_hi = row_of(end - 1);
+          const uint32_t rows = static_cast<uint32_t>(q_hi - q_lo + 1);  // <= kSrcBuf
+          for (uint32_t j = lane; j < rows; j += 64) sh_src[wv][j] = sources[q_lo + j];
+          src_q0 = q_lo;
+          wave_sync();
+        }
       }
       const uint64_t avail = end - cur;
       const uint32_t nidle = static_cast<uint32_t>(__popcll(idle));
@@ -202,7 +219,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
             q += 1;
             rem -= R;
           }
-          L.s = sources ? sources[q] : static_cast<uint32_t>(q);
+          L.s = sources ? sh_src[wv][q - src_q0] : static_cast<uint32_t>(q);
           L.i = static_cast<uint32_t>(rem);
           if (kLaneKeys) {
             L.k0 = key0;
