@@ -52,6 +52,7 @@ struct fppr_batch {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kLanes - 1] = {};
   std::vector<int> graph_lane, item_lane;  // lane of each graph's rebuild / item's counting
+  std::vector<bool> split;                 // all-nodes item: coin-only kernel for nodes without out-edges
 };
 
 namespace {
@@ -158,6 +159,10 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
   if ((e = fork_lanes(b, s)) != hipSuccess) return hip_fail(e, "fork streams");
   for (size_t k = 0; k < b->items.size(); ++k) {
     const fppr_batch_item& it = b->items[k];
+    if (b->split[k]) {
+      if ((e = launch_dangling(it.graph, &it.params, b->endpoints[k], stats, lane(b->item_lane[k]))) != hipSuccess)
+        return hip_fail(e, "dangling walks");
+    }
     AggLaunch a = make_agg(&it.params, b->endpoints[k], it.sources, item_sources(it), &it.out);
     a.table = b->agg_table;
     if (a.topk || a.counts || a.digest) {
@@ -216,13 +221,23 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
   std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
     return item_sources(items[x]) * items[x].params.R > item_sources(items[y]) * items[y].params.R;
   });
+  // An item over all nodes of its graph walks only from the nodes with
+  // out-edges in the walk launch (endpoints placed by source id); the walks
+  // from the other nodes only restart at their source and run in a coin-only
+  // kernel before the item's counting. Draws and results are unchanged.
+  b->split.assign(count, false);
+  for (uint32_t k = 0; k < count; ++k) b->split[k] = !items[k].sources && split_dangling(items[k].graph);
   uint64_t first = 0;
   for (uint32_t k : order) {
     const fppr_batch_item& it = items[k];
-    const uint64_t walks = item_sources(it) * it.params.R;
+    const uint64_t walks = (b->split[k] ? it.graph->n_live : item_sources(it)) * it.params.R;
     if (walks == 0) continue;
-    b->host_table.push_back(
-        make_desc(it.graph, &it.params, it.sources, item_sources(it), b->endpoints[k], first, 0, walks));
+    WalkDesc D = b->split[k] ? make_desc(it.graph, &it.params, it.graph->live, it.graph->n_live, b->endpoints[k],
+                                         first, 0, walks)
+                             : make_desc(it.graph, &it.params, it.sources, item_sources(it), b->endpoints[k],
+                                         first, 0, walks);
+    if (b->split[k]) D.flags = kDescEpBySource;
+    b->host_table.push_back(D);
     first += (walks + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
   }
   b->total = first;

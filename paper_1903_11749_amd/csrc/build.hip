@@ -264,6 +264,23 @@ __global__ void __launch_bounds__(kThreads) k_scan_apply(const uint32_t* __restr
     if (base + k < n) out[base + k] = ex + v[k];
 }
 
+// 1 for nodes with out-edges
+__global__ void k_live_flags(const uint64_t* __restrict__ off, uint32_t n, uint32_t* flag) {
+  for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < n;
+       v += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    flag[v] = off[v + 1] > off[v] ? 1u : 0u;
+}
+
+// nodes with out-edges in id order to `live`, the others to `dang`
+__global__ void k_split_nodes(const uint32_t* __restrict__ flag, const uint64_t* __restrict__ scan, uint32_t n,
+                              uint32_t* live, uint32_t* dang) {
+  for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < n;
+       v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    if (flag[v]) live[scan[v]] = static_cast<uint32_t>(v);
+    else dang[v - scan[v]] = static_cast<uint32_t>(v);
+  }
+}
+
 uint32_t grid_for(uint64_t items) {
   uint64_t b = (items + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
@@ -293,6 +310,16 @@ hipError_t launch_validate(const fppr_graph* g, hipStream_t s) {
   if (g->m)
     hipLaunchKernelGGL(k_validate_edges, dim3(grid_for(g->m)), dim3(kThreads), 0, s, g->col, g->w,
                        g->m, g->n, g->d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_nodes(fppr_graph* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_live_flags, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->n, g->flag);
+  hipError_t e = launch_scan_u32(g->flag, g->scan, g->n, g->scan_blocks,
+                                 reinterpret_cast<uint64_t*>(g->d_err + 10), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_split_nodes, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->flag, g->scan, g->n,
+                     g->live, g->dang);
   return hipGetLastError();
 }
 

@@ -63,6 +63,8 @@ void free_graph(fppr_graph* g) {
   dfree(g->pool);
   dfree(g->rec_st);
   dfree(g->small_nodes);
+  dfree(g->live);
+  dfree(g->dang);
   if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
   delete g;
 }
@@ -89,6 +91,7 @@ struct Ctl {
   uint64_t blocks;
   uint64_t small;
   uint32_t n_tree;
+  uint64_t live;
 };
 
 hipError_t read_ctl(const fppr_graph* g, hipStream_t s, Ctl* c) {
@@ -102,6 +105,7 @@ hipError_t read_ctl(const fppr_graph* g, hipStream_t s, Ctl* c) {
   std::memcpy(&c->blocks, raw + 2, 8);
   std::memcpy(&c->small, raw + 6, 8);
   c->n_tree = raw[9];
+  std::memcpy(&c->live, raw + 10, 8);
   return hipSuccess;
 }
 
@@ -296,8 +300,13 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     free_graph(g);
     return invalid(msg);
   }
+  FPPR_TRY(dmalloc(&g->live, n, acc), "hipMalloc(live nodes)");
+  FPPR_TRY(dmalloc(&g->dang, n, acc), "hipMalloc(dangling nodes)");
+  FPPR_TRY(launch_split_nodes(g, s), "split nodes");
   FPPR_TRY(launch_region_sizes(g, s), "region sizes");
   FPPR_TRY(read_ctl(g, s, &c), "read region sizes");
+  g->n_live = c.live;
+  g->n_dang = n - c.live;
   g->n_blocks = c.blocks;
   FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
   FPPR_TRY(launch_leaves(g, s), "leaf blocks");
@@ -538,11 +547,19 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
                                                                      r0 * p->R * 4ull);
     if (r0 > 0 && (e = launch_zero_u64(reinterpret_cast<uint64_t*>(ctl), 1, s)) != hipSuccess)
       return hip_fail(e, "zero walk counter");  // the invalid-source flag accumulates
-    const WalkDesc D = make_desc(g, p, sources, n_sources, ep_base, 0, r0 * p->R, nb * p->R);
+    // All nodes in one launch: the walk kernel takes the nodes with out-edges
+    // and a coin-only kernel the others (their walks only restart at the
+    // source and always end there); draws and results are those of one
+    // launch over every node.
+    const bool split = !sources && !blocked && split_dangling(g);
+    WalkDesc D = split ? make_desc(g, p, g->live, g->n_live, ep_base, 0, 0, g->n_live * p->R)
+                       : make_desc(g, p, sources, n_sources, ep_base, 0, r0 * p->R, nb * p->R);
+    if (split) D.flags = kDescEpBySource;
     if ((e = launch_set_desc(D, desc, s)) != hipSuccess) return hip_fail(e, "walk descriptor");
     const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
-    if ((e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
+    if (total && (e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
       return hip_fail(e, "walk kernel");
+    if (split && (e = launch_dangling(g, p, ep_base, stats, s)) != hipSuccess) return hip_fail(e, "dangling walks");
     if (prof && !blocked && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
     AggLaunch a = make_agg(p, out->endpoints ? out->endpoints + r0 * p->R : ws_ep, sources ? sources + r0 : nullptr,
                            nb, out);

@@ -51,6 +51,11 @@ struct fppr_graph {
   uint32_t K_log2 = 0;
   uint64_t n_small = 0;
   uint64_t* pool = nullptr;          // [n_small * K]
+  // nodes with out-edges and without, each in id order (degrees never change
+  // after create, so these are built once)
+  uint32_t* live = nullptr;          // [n_live]
+  uint32_t* dang = nullptr;          // [n_dang]
+  uint64_t n_live = 0, n_dang = 0;
   uint64_t pool_cap = 0;             // entries allocated
   uint4* rec_st = nullptr;           // [n] stitched records
   uint32_t* small_nodes = nullptr;   // [n] rank -> node
@@ -74,6 +79,9 @@ void drop_pool(fppr_graph* g);
 hipError_t launch_validate(const fppr_graph* g, hipStream_t s);
 // region sizes + scan -> g->region, total blocks at d_err[2..3]
 hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s);
+// nodes with / without out-edges -> g->live, g->dang; the count of the former
+// at d_err[10..11]
+hipError_t launch_split_nodes(fppr_graph* g, hipStream_t s);
 // prefixes and destinations into leaf blocks, node records
 hipError_t launch_leaves(fppr_graph* g, hipStream_t s);
 hipError_t launch_trees(fppr_graph* g, hipStream_t s);
@@ -102,8 +110,12 @@ struct WalkDesc {
   uint64_t count;
   uint64_t walk0;
   uint64_t R_magic;          // floor((2^64 - 1) / R)
-  uint32_t R, n, key0, key1, T, tree_min, K_log2, pad;
+  uint32_t R, n, key0, key1, T, tree_min, K_log2;
+  uint32_t flags;            // kDescEpBySource
 };
+// the endpoint of walk i of source s goes to endpoints[s * R + i] (a run over
+// a list of some of the nodes that fills an all-nodes endpoint buffer)
+constexpr uint32_t kDescEpBySource = 1;
 // lane_keys: the per-lane-key form of the kernel (for tables whose
 // descriptors all read one graph; see same_graph_table)
 hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
@@ -112,6 +124,16 @@ hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, un
 // read the same graph arrays
 bool same_graph_table(const WalkDesc* h, uint32_t ndesc);
 hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s);
+// Walks from the nodes without out-edges of g, R each, under p's seed and
+// alpha: every move is a restart at the source (Sec. 2.1), so a walk is its
+// sequence of coins and always ends at its source; endpoint of walk i of
+// node s -> endpoints[s * R + i]. Statistics as the walk kernel counts them.
+hipError_t launch_dangling(const fppr_graph* g, const fppr_params* p, uint32_t* endpoints, fppr_stats* stats,
+                           hipStream_t s);
+// all-nodes runs split off the walks from nodes without out-edges when those
+// are a quarter of the nodes or more (below that the extra source list and
+// launch cost more than they save)
+inline bool split_dangling(const fppr_graph* g) { return g->n_dang > 0 && g->n_dang * 4 >= g->n; }
 // descriptor of walks [walk0, walk0 + count) of a run of `p` on graph g
 WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* sources,
                    uint64_t n_sources, uint32_t* endpoints, uint64_t first, uint64_t walk0,

@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   const uint32_t* sources = nullptr;
   uint32_t* endpoints = nullptr;
   uint64_t first = 0, walk0 = 0, R_magic = 0, src_q0 = 0;
-  uint32_t R = 1, n = 0, T = 0, key0 = 0, key1 = 0, tree_min = 0, K_log2 = 0;
+  uint32_t R = 1, n = 0, T = 0, key0 = 0, key1 = 0, tree_min = 0, K_log2 = 0, dflags = 0;
 
   for (;;) {
     // ---- refill idle lanes from the wave's chunk of walk ids ----
@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           key1 = D.key1;
           tree_min = D.tree_min;
           K_log2 = D.K_log2;
+          dflags = D.flags;
           end = first + D.count;  // limit of the descriptor, clipped below
         } else {
           end = t.descs[d].first + t.descs[d].count;
@@ -226,13 +227,13 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
             L.k1 = key1;
             L.T = T;
           }
-          L.ep = endpoints + w;
+          L.ep = (dflags & kDescEpBySource) ? endpoints + static_cast<uint64_t>(L.s) * R + rem : endpoints + w;
           L.tail = L.s;
           L.m = 0;
           L.len = 0;
           L.ph = kSrcRec;
           if (L.s >= n) {  // invalid source: no walk, recorded for the caller
-            *L.ep = kNoNode;
+            if (!(dflags & kDescEpBySource)) *L.ep = kNoNode;
             atomicOr(t.ctl + 1, 1ull);
             if (kStats) atomicAdd(reinterpret_cast<unsigned long long*>(&t.stats->walks), ~0ull);
             L.ph = kIdle;
@@ -461,6 +462,66 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   }
 }
 
+// Walks from nodes without out-edges: only coins. Each thread takes walks
+// t, t + N, t + 2N, ... of the run and advances one move per loop iteration,
+// so a wave's lanes stay busy until their whole share is done (no lane waits
+// for another lane's long walk).
+template <bool kStats>
+__global__ void __launch_bounds__(kThreads) k_dangling(const uint32_t* __restrict__ dang, uint64_t total,
+                                                       uint32_t R, uint64_t R_magic, uint32_t T, uint32_t key0,
+                                                       uint32_t key1, uint32_t* __restrict__ endpoints,
+                                                       fppr_stats* stats) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  uint32_t s = 0, i = 0, m = 0;
+  uint64_t st_walks = 0, st_moves = 0, st_capped = 0;
+  auto take = [&]() {
+    if (w >= total) return false;
+    uint64_t q = __umul64hi(w, R_magic);
+    uint64_t rem = w - q * R;
+    if (rem >= R) {
+      q += 1;
+      rem -= R;
+    }
+    s = dang[q];
+    i = static_cast<uint32_t>(rem);
+    m = 0;
+    return true;
+  };
+  bool active = take();
+  while (__ballot(active) != 0) {
+    if (active) {
+      const U4 x = philox10(i, m, s, 0u, key0, key1);
+      m += 1;
+      const bool coin = x.x2 < T;
+      if (coin || m == kMoveCap) {
+        endpoints[static_cast<uint64_t>(s) * R + i] = s;
+        if (kStats) {
+          st_walks += 1;
+          st_moves += m;
+          st_capped += coin ? 0u : 1u;
+        }
+        w += stride;
+        active = take();
+      }
+    }
+  }
+  if (kStats) {
+    // fppr_stats order: walks, moves, steps, capped, dangling, plain, stitched, log
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(stats);
+    const uint64_t vw = wave_sum_u64(st_walks), vm = wave_sum_u64(st_moves), vc = wave_sum_u64(st_capped);
+    if (__lane_id() == 0) {
+      if (vw) atomicAdd(out + 0, static_cast<unsigned long long>(vw));
+      if (vm) {
+        atomicAdd(out + 1, static_cast<unsigned long long>(vm));
+        atomicAdd(out + 2, static_cast<unsigned long long>(vm));
+        atomicAdd(out + 4, static_cast<unsigned long long>(vm));
+      }
+      if (vc) atomicAdd(out + 3, static_cast<unsigned long long>(vc));
+    }
+  }
+}
+
 __global__ void k_fill_u64(uint64_t* p, uint64_t count, uint64_t value) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < count;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -497,6 +558,32 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s) {
   uint64_t b = (count + 255) / 256;
   if (b > 4096) b = 4096;
   hipLaunchKernelGGL(k_fill_u64, dim3(static_cast<uint32_t>(b)), dim3(256), 0, s, p, count, 0ull);
+  return hipGetLastError();
+}
+
+hipError_t launch_dangling(const fppr_graph* g, const fppr_params* p, uint32_t* endpoints, fppr_stats* stats,
+                           hipStream_t s) {
+  const uint64_t total = g->n_dang * p->R;
+  if (total == 0) return hipSuccess;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  e = stats ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dangling<true>, kThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_dangling<false>, kThreads, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  uint64_t blocks = static_cast<uint64_t>(cus) * per_cu;
+  const uint64_t need = (total + kThreads - 1) / kThreads;
+  if (blocks > need) blocks = need;
+  const uint32_t T = fppr_alpha_threshold(p->alpha);
+  const uint32_t k0 = static_cast<uint32_t>(p->seed), k1 = static_cast<uint32_t>(p->seed >> 32);
+  if (stats)
+    hipLaunchKernelGGL(k_dangling<true>, dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, g->dang, total,
+                       p->R, ~0ull / p->R, T, k0, k1, endpoints, stats);
+  else
+    hipLaunchKernelGGL(k_dangling<false>, dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, g->dang, total,
+                       p->R, ~0ull / p->R, T, k0, k1, endpoints, stats);
   return hipGetLastError();
 }
 

@@ -90,3 +90,28 @@ def test_blocked_invalid_source_and_tiny_budget(fp, graph):
         fp.run(G, 0.15, 64, 9, sources=src, topk=8, counts=False, stats=False, max_workspace=need // 6)
     with pytest.raises(fp.FpprError):
         fp.fppr_plan_block(G, p, src.size, 100)
+
+
+def test_split_run_equals_blocked_and_oracle(fp):
+    """A graph where about half the nodes have no out-edges: the all-nodes run
+    sends their walks to the coin-only kernel; it equals the blocked run (which
+    keeps every walk in the walk kernel) and the oracle, counts and statistics
+    included."""
+    import torch
+
+    say("case: all-nodes run with the coin-only kernel vs blocked run vs oracle")
+    g = synth.rmat(13, 8, .57, .19, .19, 100, seed=2050, zipf_s=1.3)
+    assert (g.degrees() == 0).mean() > 0.25
+    G = fp.Graph(g)
+    kw = dict(topk=8, counts=True, digests=True, stats=True)
+    full = fp.run(G, 0.15, 96, 13, **kw)
+    p = fp.make_params(0.15, 96, 13, 8, False, True, True, True)
+    part = fp.run(G, 0.15, 96, 13, max_workspace=fp.fppr_plan(G, p, g.n) // 3, **kw)
+    same(full, part)
+    ref = O.run(O.Graph.from_csr(g), 0.15, 96, 13, topk=8)
+    torch.cuda.synchronize()
+    assert np.array_equal(full.counts.cpu().numpy().view(np.uint32), ref.counts)
+    assert np.array_equal(full.topk.cpu().numpy().view(np.uint32), ref.topk)
+    st = full.stats_dict()
+    for key in ("walks", "moves", "steps", "capped", "dangling_moves", "plain_moves"):
+        assert st[key] == ref.stats[key], key
