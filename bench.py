@@ -11,8 +11,11 @@ Step (all on one HIP stream, CSR already resident in HBM):
 
 Prints one JSON line. `value` is walk-steps per second of the whole step
 (steps = edges traversed, restarts and every step of a stitched move
-included). The roofline object describes the walk kernel, timed with HIP
-events the library records on the stream it launches on.
+included). The roofline object describes the walk kernel k_walk, timed with
+HIP events the library records on the stream it launches on; in all-nodes
+runs on graphs where a quarter or more of the nodes have no out-edges, the
+walks from those nodes run in a coin-only kernel (k_dangling) after it,
+reported beside the roofline.
 """
 from __future__ import annotations
 
@@ -60,8 +63,9 @@ def walk_source_hash() -> str:
 
 
 def counted_traffic():
-    """HBM bytes per walk launch from the committed counter summary, or None
-    when the walk kernel's sources changed since the counters were taken."""
+    """HBM bytes of one k_walk launch from the committed counter summary, or
+    None when the walk kernel's sources changed since the counters were
+    taken."""
     path = os.path.join(ROOT, PMC_SUMMARY)
     if not os.path.exists(path):
         return None
@@ -460,15 +464,18 @@ def main():
 
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    walk_ms, agg_ms, steps_total, st_last = [], [], 0, None
+    walk_ms, agg_ms, kern_ms, coin_ms, steps_total, st_last = [], [], [], [], 0, None
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e0.record(stream)
     for i in range(args.steps):
         step()
         wm, am = prof.read()  # waits for this step's walk + aggregation events
+        km, cm = prof.read_walk()
         walk_ms.append(wm)
         agg_ms.append(am)
+        kern_ms.append(km)
+        coin_ms.append(cm)
         st_last = out.stats_dict()
         steps_total += st_last["steps"]
         log(f"step {i + 1}/{args.steps}: walk {wm:.1f} ms, aggregate {am:.1f} ms")
@@ -480,16 +487,35 @@ def main():
     value = steps_total / (ms_total / 1e3)
     sources_per_s = n_src * args.steps / (ms_total / 1e3)
 
-    walk_avg = float(np.mean(walk_ms))
-    ab = alg_bytes(st_last)
-    achieved = ab / (walk_avg / 1e3) / 1e9
+    # Work of the coin-only kernel, counted apart from the walk kernel's: the
+    # same walks (keys depend on source, walk and move only) from an untimed
+    # run over the nodes without out-edges as an explicit source list.
+    kern_avg, coin_avg = float(np.mean(kern_ms)), float(np.mean(coin_ms))
+    st_coin = {"walks": 0, "moves": 0}
+    if coin_avg > 0:
+        dang = np.flatnonzero(g.degrees() == 0).astype(np.uint32)
+        o = fppr.run(G, alpha, R, seed, sources=dang, topk=0, stitch=bool(st_cfg), counts=False,
+                     digests=False, stats=True, stream=stream)
+        st_coin = o.stats_dict()
+        del o
+        assert st_coin["plain_moves"] == 0 and st_coin["stitched_moves"] == 0
+    st_walk = dict(st_last)
+    for key in ("walks", "moves", "steps", "dangling_moves"):
+        st_walk[key] -= st_coin.get(key, 0)
+    ab = alg_bytes(st_walk)
+    achieved = ab / (kern_avg / 1e3) / 1e9
     traffic = counted_traffic() if args.workload in ("scale24", "serve") else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
-                "kernel": "k_walk", "kernel_ms": round(walk_avg, 3),
-                "alg_bytes_per_launch": ab,
-                "walk_steps_per_s_kernel": round(st_last["steps"] / (walk_avg / 1e3), 1),
-                "moves_per_s_kernel": round(st_last["moves"] / (walk_avg / 1e3), 1)}
+                "kernel": "k_walk", "kernel_ms": round(kern_avg, 3), "alg_bytes_per_launch": ab,
+                "traffic_GBps": round(traffic / (kern_avg / 1e3) / 1e9, 1) if traffic else None,
+                "walk_steps_per_s_kernel": round(st_walk["steps"] / (kern_avg / 1e3), 1),
+                "moves_per_s_kernel": round(st_walk["moves"] / (kern_avg / 1e3), 1)}
+    coin_only = None
+    if coin_avg > 0:
+        coin_only = {"kernel": "k_dangling", "ms": round(coin_avg, 3), "walks": st_coin["walks"],
+                     "moves": st_coin["moves"], "moves_per_s": round(st_coin["moves"] / (coin_avg / 1e3), 1),
+                     "bound": "alu (one Philox4x32-10 block per move)"}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "walk-steps/s", "n_gpus": 1,
@@ -502,8 +528,10 @@ def main():
         "sources_per_s": round(sources_per_s, 1),
         "walk_stats_per_step": st_last,
         "aggregate_ms": round(float(np.mean(agg_ms)), 3),
+        "walk_phase_ms": round(float(np.mean(walk_ms)), 3),
         "wall_s": round(wall, 3),
         "roofline": roofline,
+        "coin_only": coin_only,
     }
 
     # ---- oracle: sampled parity + CPU baseline (rank 0, N = 1) ----

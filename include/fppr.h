@@ -209,6 +209,13 @@ FPPR_API fppr_status fppr_profile_destroy(fppr_profile* p);
 /* Waits for the events of the last run that used `p` and returns the walk
  * and aggregation kernel durations in milliseconds (host outputs). */
 FPPR_API fppr_status fppr_profile_read(fppr_profile* p, double* walk_ms, double* aggregate_ms);
+/* Splits the walk time of the last single-launch run that used `p`: the walk
+ * kernel alone, and the coin-only kernel that an all-nodes run launches for
+ * the nodes without out-edges (0 when it was not launched; see fppr_run).
+ * Blocked runs report their whole walk-and-count time as walk kernel time;
+ * batch runs report 0 coin-only time (their coin-only kernels run on the
+ * counting streams and are timed with the aggregation). */
+FPPR_API fppr_status fppr_profile_read_walk(fppr_profile* p, double* walk_kernel_ms, double* coin_only_ms);
 
 /* Outputs (all device pointers, caller-owned; NULL = not wanted):
  *  topk       [n_src][k][2] uint32: (t, count) by count descending then t

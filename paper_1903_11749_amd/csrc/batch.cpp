@@ -154,6 +154,7 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
                   b->opts.blocks_per_cu, s,
                   same_graph_table(b->host_table.data(), static_cast<uint32_t>(b->host_table.size())));
   if (e != hipSuccess) return hip_fail(e, "walk kernel");
+  if (prof && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
   if ((e = fork_lanes(b, s)) != hipSuccess) return hip_fail(e, "fork streams");

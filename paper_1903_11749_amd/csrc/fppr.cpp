@@ -559,6 +559,7 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
     const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
     if (total && (e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
       return hip_fail(e, "walk kernel");
+    if (prof && !blocked && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
     if (split && (e = launch_dangling(g, p, ep_base, stats, s)) != hipSuccess) return hip_fail(e, "dangling walks");
     if (prof && !blocked && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
     AggLaunch a = make_agg(p, out->endpoints ? out->endpoints + r0 * p->R : ws_ep, sources ? sources + r0 : nullptr,
@@ -575,6 +576,7 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
     }
   }
   if (prof && blocked) {  // blocked runs: the walk time covers every block's walks and counting
+    if ((e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipEventRecord(prof->ev[2], s)) != hipSuccess) return hip_fail(e, "event");
   }
@@ -613,6 +615,18 @@ FPPR_API fppr_status fppr_profile_read(fppr_profile* p, double* walk_ms, double*
   if ((e = hipEventElapsedTime(&b, p->ev[2], p->ev[3])) != hipSuccess) return hip_fail(e, "elapsed");
   if (walk_ms) *walk_ms = a;
   if (aggregate_ms) *aggregate_ms = b;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_profile_read_walk(fppr_profile* p, double* walk_kernel_ms, double* coin_only_ms) {
+  if (!p) return invalid("profile is NULL");
+  hipError_t e = hipEventSynchronize(p->ev[3]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  float a = 0.f, b = 0.f;
+  if ((e = hipEventElapsedTime(&a, p->ev[0], p->ev[4])) != hipSuccess) return hip_fail(e, "elapsed");
+  if ((e = hipEventElapsedTime(&b, p->ev[4], p->ev[1])) != hipSuccess) return hip_fail(e, "elapsed");
+  if (walk_kernel_ms) *walk_kernel_ms = a;
+  if (coin_only_ms) *coin_only_ms = b;
   return FPPR_OK;
 }
 

@@ -63,7 +63,8 @@ struct fppr_graph {
 };
 
 struct fppr_profile {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // start, walks done, aggregation start, aggregation done, walk kernel done
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace fppr {

@@ -462,63 +462,78 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   }
 }
 
-// Walks from nodes without out-edges: only coins. Each thread takes walks
-// t, t + N, t + 2N, ... of the run and advances one move per loop iteration,
-// so a wave's lanes stay busy until their whole share is done (no lane waits
-// for another lane's long walk).
+// Walks from nodes without out-edges. Such a walk restarts at its source on
+// every move, so it ends there whatever its coins: the endpoints are written
+// as whole rows, each wave taking row after row with its lanes on
+// consecutive walk slots. The coins only decide the statistics (moves and
+// capped walks); when those are wanted, each thread then draws the coins of
+// a contiguous range of walks, one move per loop iteration, so a wave's
+// lanes stay busy until their whole range is done.
 template <bool kStats>
-__global__ void __launch_bounds__(kThreads) k_dangling(const uint32_t* __restrict__ dang, uint64_t total,
+__global__ void __launch_bounds__(kThreads) k_dangling(const uint32_t* __restrict__ dang, uint64_t n_dang,
                                                        uint32_t R, uint64_t R_magic, uint32_t T, uint32_t key0,
                                                        uint32_t key1, uint32_t* __restrict__ endpoints,
                                                        fppr_stats* stats) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-  uint32_t s = 0, i = 0, m = 0;
-  uint64_t st_walks = 0, st_moves = 0, st_capped = 0;
-  auto take = [&]() {
-    if (w >= total) return false;
-    uint64_t q = __umul64hi(w, R_magic);
-    uint64_t rem = w - q * R;
+  const uint32_t lane = __lane_id();
+  const uint64_t waves = static_cast<uint64_t>(gridDim.x) * (kThreads / 64);
+  for (uint64_t q = static_cast<uint64_t>(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; q < n_dang;
+       q += waves) {
+    const uint32_t s = dang[q];
+    uint32_t* row = endpoints + static_cast<uint64_t>(s) * R;
+    for (uint32_t i = lane; i < R; i += 64) row[i] = s;
+  }
+  if (!kStats) return;
+
+  const uint64_t total = n_dang * R;
+  const uint64_t threads = static_cast<uint64_t>(gridDim.x) * kThreads;
+  const uint64_t per = (total + threads - 1) / threads;
+  const uint64_t w0 = (static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x) * per;
+  uint64_t left = w0 < total ? (total - w0 < per ? total - w0 : per) : 0;
+  const uint64_t walks = left;
+  uint64_t q = 0;
+  uint32_t i = 0, s = 0, s_next = 0, m = 0;
+  if (left) {
+    q = __umul64hi(w0, R_magic);
+    uint64_t rem = w0 - q * R;
     if (rem >= R) {
       q += 1;
       rem -= R;
     }
-    s = dang[q];
     i = static_cast<uint32_t>(rem);
-    m = 0;
-    return true;
-  };
-  bool active = take();
-  while (__ballot(active) != 0) {
-    if (active) {
+    s = dang[q];
+    if (left > R - i) s_next = dang[q + 1];  // the range continues into the next row
+  }
+  uint64_t moves = 0, capped = 0;
+  while (__ballot(left != 0) != 0) {
+    if (left) {
       const U4 x = philox10(i, m, s, 0u, key0, key1);
       m += 1;
       const bool coin = x.x2 < T;
       if (coin || m == kMoveCap) {
-        endpoints[static_cast<uint64_t>(s) * R + i] = s;
-        if (kStats) {
-          st_walks += 1;
-          st_moves += m;
-          st_capped += coin ? 0u : 1u;
+        moves += m;
+        capped += coin ? 0u : 1u;
+        m = 0;
+        left -= 1;
+        if (++i == R) {  // next row: its source was loaded a row ago
+          i = 0;
+          q += 1;
+          s = s_next;
+          if (left > R) s_next = dang[q + 1];
         }
-        w += stride;
-        active = take();
       }
     }
   }
-  if (kStats) {
-    // fppr_stats order: walks, moves, steps, capped, dangling, plain, stitched, log
-    unsigned long long* out = reinterpret_cast<unsigned long long*>(stats);
-    const uint64_t vw = wave_sum_u64(st_walks), vm = wave_sum_u64(st_moves), vc = wave_sum_u64(st_capped);
-    if (__lane_id() == 0) {
-      if (vw) atomicAdd(out + 0, static_cast<unsigned long long>(vw));
-      if (vm) {
-        atomicAdd(out + 1, static_cast<unsigned long long>(vm));
-        atomicAdd(out + 2, static_cast<unsigned long long>(vm));
-        atomicAdd(out + 4, static_cast<unsigned long long>(vm));
-      }
-      if (vc) atomicAdd(out + 3, static_cast<unsigned long long>(vc));
+  // fppr_stats order: walks, moves, steps, capped, dangling, plain, stitched, log
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(stats);
+  const uint64_t vw = wave_sum_u64(walks), vm = wave_sum_u64(moves), vc = wave_sum_u64(capped);
+  if (lane == 0) {
+    if (vw) atomicAdd(out + 0, static_cast<unsigned long long>(vw));
+    if (vm) {
+      atomicAdd(out + 1, static_cast<unsigned long long>(vm));
+      atomicAdd(out + 2, static_cast<unsigned long long>(vm));
+      atomicAdd(out + 4, static_cast<unsigned long long>(vm));
     }
+    if (vc) atomicAdd(out + 3, static_cast<unsigned long long>(vc));
   }
 }
 
@@ -563,8 +578,7 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t count, hipStream_t s) {
 
 hipError_t launch_dangling(const fppr_graph* g, const fppr_params* p, uint32_t* endpoints, fppr_stats* stats,
                            hipStream_t s) {
-  const uint64_t total = g->n_dang * p->R;
-  if (total == 0) return hipSuccess;
+  if (g->n_dang == 0) return hipSuccess;
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -574,16 +588,17 @@ hipError_t launch_dangling(const fppr_graph* g, const fppr_params* p, uint32_t* 
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   uint64_t blocks = static_cast<uint64_t>(cus) * per_cu;
+  const uint64_t total = g->n_dang * p->R;
   const uint64_t need = (total + kThreads - 1) / kThreads;
   if (blocks > need) blocks = need;
   const uint32_t T = fppr_alpha_threshold(p->alpha);
   const uint32_t k0 = static_cast<uint32_t>(p->seed), k1 = static_cast<uint32_t>(p->seed >> 32);
   if (stats)
-    hipLaunchKernelGGL(k_dangling<true>, dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, g->dang, total,
-                       p->R, ~0ull / p->R, T, k0, k1, endpoints, stats);
+    hipLaunchKernelGGL(k_dangling<true>, dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, g->dang,
+                       g->n_dang, p->R, ~0ull / p->R, T, k0, k1, endpoints, stats);
   else
-    hipLaunchKernelGGL(k_dangling<false>, dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, g->dang, total,
-                       p->R, ~0ull / p->R, T, k0, k1, endpoints, stats);
+    hipLaunchKernelGGL(k_dangling<false>, dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, g->dang,
+                       g->n_dang, p->R, ~0ull / p->R, T, k0, k1, endpoints, stats);
   return hipGetLastError();
 }
 

@@ -153,6 +153,8 @@ _SIGS = [
     ("fppr_profile_destroy", ctypes.c_int, [P]),
     ("fppr_profile_read", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
+    ("fppr_profile_read_walk", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
     ("fppr_batch_plan", ctypes.c_int, [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
     ("fppr_batch_create", ctypes.c_int, [P, ctypes.c_uint32, ctypes.POINTER(fppr_batch_opts), P,
                                          ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
@@ -411,6 +413,13 @@ class Profile:
         a = ctypes.c_double()
         b = ctypes.c_double()
         _check(lib().fppr_profile_read(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def read_walk(self):
+        """(walk kernel ms, coin-only kernel ms) of the last single-launch run."""
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(lib().fppr_profile_read_walk(self.handle, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
     def __del__(self):

@@ -115,3 +115,31 @@ def test_split_run_equals_blocked_and_oracle(fp):
     st = full.stats_dict()
     for key in ("walks", "moves", "steps", "capped", "dangling_moves", "plain_moves"):
         assert st[key] == ref.stats[key], key
+
+
+def test_profile_splits_walk_and_coin_only_time(fp):
+    """The stage timer reports the walk kernel and the coin-only kernel apart;
+    their sum is the walk time, and runs without the coin-only kernel report
+    0 for it."""
+    import torch
+
+    say("case: stage timer of a split all-nodes run and of a source-list run")
+    g = synth.rmat(13, 8, .57, .19, .19, 100, seed=2050, zipf_s=1.3)
+    G = fp.Graph(g)
+    p = fp.make_params(0.15, 96, 13, 8, False, False, True, False)
+    for src in (None, np.arange(0, g.n, 2, dtype=np.uint32)):
+        n_src = g.n if src is None else src.size
+        ws = torch.empty((fp.fppr_plan(G, p, n_src) + 7) // 8, dtype=torch.int64, device="cuda")
+        out = fp.alloc_outputs(n_src, 96, 8, counts=False, digests=True, stats=False)
+        prof = fp.Profile()
+        out.profile = prof
+        s = None if src is None else torch.from_numpy(src.view(np.int32)).cuda()
+        fp.fppr_run(G, p, s, n_src, ws, out, None)
+        walk, _ = prof.read()
+        kern, coin = prof.read_walk()
+        assert kern > 0 and coin >= 0
+        assert abs(kern + coin - walk) < 1e-3 + 1e-3 * walk
+        if src is None:
+            assert coin > 0
+        else:
+            assert coin < 0.05

@@ -51,6 +51,7 @@ def test_null_handles(fp):
     assert L.fppr_plan(None, None, 1, ctypes.byref(ws)) == fp.FPPR_INVALID_ARGUMENT
     assert L.fppr_run_check(None, None) == fp.FPPR_INVALID_ARGUMENT
     assert L.fppr_profile_read(None, None, None) == fp.FPPR_INVALID_ARGUMENT
+    assert L.fppr_profile_read_walk(None, None, None) == fp.FPPR_INVALID_ARGUMENT
 
 
 def test_batch_refuses_bad_items(fp):
