@@ -87,10 +87,12 @@ typedef struct {
 
 typedef struct {
   /* Rows with more than hub_threshold out-edges (the large nodes of Sec. 4.1)
-   * carry a 16-ary prefix tree, the integer counterpart of the alias tree
+   * carry a prefix tree, the integer counterpart of the alias tree
    * (Algorithm 3, Lemma 1): the row is cut into blocks of 8 edges whose
    * running totals form the next level, 16 keys to a 128-byte node,
-   * recursively, and a pick descends one node per level. It returns exactly
+   * recursively; the top level (at most 14 keys) sits in the node's own
+   * 128-byte line, so a pick reads the node line, one node per level below
+   * the top, and one block of 8 edges. It returns exactly
    * the edge a flat search returns, so the threshold never changes results.
    * 0 selects 8 (the fastest on the graphs measured); values below 8 act as
    * 8; UINT32_MAX disables trees (rows of more than 8 edges are then
@@ -101,7 +103,7 @@ typedef struct {
 /* Creates the device graph: validates the CSR (device-side; INVALID_ARGUMENT
  * on n == 0, n > 2^32-2, m >= 2^36, a non-monotone offset array, off[0] != 0,
  * off[n] != m, col >= n, w == 0, a row of 2^27 or more edges), computes the
- * per-row inclusive uint64 weight prefixes, the 16-byte node records and the
+ * per-row inclusive uint64 weight prefixes, the 128-byte node lines and the
  * prefix trees. Synchronous: returns after the graph is ready. The library
  * allocates its own device arrays (freed by fppr_graph_destroy).
  * opts may be NULL (defaults). */

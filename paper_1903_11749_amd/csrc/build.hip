@@ -1,6 +1,6 @@
 // Graph ingest: CSR validation, per-row inclusive uint64 weight prefixes laid
-// out with the destination ids in 128-byte leaf blocks, 16-byte node records
-// and the rows' 16-ary prefix trees.
+// out with the destination ids in 128-byte leaf blocks, 128-byte node lines
+// and the rows' prefix trees (top level in the node line, 16-ary below).
 //
 // Routing probability r(s,t) = w(s,t) / sum_v w(s,v) (Sec. 2.1) is realised
 // on exact integers: the prefix P of a row is strictly increasing (w >= 1),
@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr uint32_t kShortRow = 64;  // rows up to this length: one thread each
+static_assert(kShortRow / kLeafEdges <= kTopKeys, "a short row's tree is its top level alone");
 
 __global__ void k_validate_offsets(const uint64_t* __restrict__ off, uint32_t n, uint64_t m,
                                    uint32_t* err) {
@@ -53,11 +54,14 @@ __global__ void k_region_sizes(const uint64_t* __restrict__ off, uint32_t n, uin
   }
 }
 
-__device__ __forceinline__ void write_record(uint4* rec, uint64_t u, uint64_t W, uint64_t region,
+// Node line of u without its tree keys (the tree kernels fill those in).
+__device__ __forceinline__ void write_record(Block* rec, uint64_t u, uint64_t W, uint64_t region,
                                              uint64_t d) {
   const uint64_t od = (region << kRegionShift) | d;
-  rec[u] = make_uint4(static_cast<uint32_t>(W), static_cast<uint32_t>(W >> 32),
-                      static_cast<uint32_t>(od), static_cast<uint32_t>(od >> 32));
+  ulonglong2* dst = reinterpret_cast<ulonglong2*>(rec + u);
+  dst[0] = make_ulonglong2(W, od);
+#pragma unroll
+  for (uint32_t k = 1; k < kNodeKeys / 2; ++k) dst[k] = make_ulonglong2(~0ull, ~0ull);
 }
 
 // Short rows: one thread accumulates its row into its leaf blocks and writes
@@ -65,7 +69,7 @@ __device__ __forceinline__ void write_record(uint4* rec, uint64_t u, uint64_t W,
 __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
                                const uint32_t* __restrict__ w, const uint64_t* __restrict__ region,
                                uint32_t n, uint32_t tree_min, uint64_t cap, Block* __restrict__ blk,
-                               uint4* __restrict__ rec, uint32_t* rows, uint32_t* n_rows,
+                               Block* __restrict__ rec, uint32_t* rows, uint32_t* n_rows,
                                uint32_t* err) {
   for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
        u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
@@ -89,17 +93,22 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
       continue;
     }
     Block* leaves = blk + r0 + tree_nodes(d, tree_min);
+    // a row this short that has a tree has only its top level (at most 8
+    // keys, the leaf blocks' last prefixes): it goes into the node line here
+    write_record(rec, u, 0, r0, d);
+    const bool tree = d > tree_min;
     uint64_t acc = 0;
     for (uint64_t j = 0; j < d; ++j) {
       acc += w[a + j];
       leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = acc;
       leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = col[a + j];
+      if (tree && ((j % kLeafEdges) == kLeafEdges - 1 || j == d - 1)) rec[u].key[kTopKey0 + j / kLeafEdges] = acc;
     }
     for (uint64_t j = d; j < leaf_blocks(d) * kLeafEdges; ++j) {
       leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = ~0ull;
       leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = 0u;
     }
-    write_record(rec, u, acc, r0, d);
+    rec[u].key[0] = acc;
   }
 }
 
@@ -109,7 +118,7 @@ __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __rest
                                                           const uint32_t* __restrict__ w,
                                                           const uint64_t* __restrict__ region,
                                                           uint32_t tree_min, Block* __restrict__ blk,
-                                                          uint4* __restrict__ rec,
+                                                          Block* __restrict__ rec,
                                                           const uint32_t* rows,
                                                           const uint32_t* n_rows) {
   __shared__ uint64_t lds[kThreads / 64];
@@ -150,33 +159,29 @@ __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __rest
   }
 }
 
-// Node `b` of level `l` of the tree of a row: 16 keys read from its leaves.
-__device__ __forceinline__ void tree_node(const Block* __restrict__ leaves, uint64_t d, uint32_t l,
-                                          uint64_t b, Block* __restrict__ dst) {
+// Key k of level l of the tree of a row (~0 past the level's end), read from
+// its leaves.
+__device__ __forceinline__ uint64_t level_key(const Block* __restrict__ leaves, uint64_t d, uint32_t l,
+                                              uint64_t k) {
   const uint32_t sh = 3 + 4 * (l - 1);  // edges covered by one key of level l: 8 * 16^(l-1)
-  const uint64_t nkeys = (d + (1ull << sh) - 1) >> sh;
-#pragma unroll
-  for (uint32_t t = 0; t < kNodeKeys; ++t) {
-    const uint64_t k = b * kNodeKeys + t;
-    uint64_t v = ~0ull;
-    if (k < nkeys) {
-      uint64_t last = (k + 1) << sh;
-      if (last > d) last = d;
-      v = leaves[(last - 1) / kLeafEdges].lf.p[(last - 1) % kLeafEdges];
-    }
-    dst->key[t] = v;
-  }
+  if (k >= ((d + (1ull << sh) - 1) >> sh)) return ~0ull;
+  uint64_t last = (k + 1) << sh;
+  if (last > d) last = d;
+  return leaves[(last - 1) / kLeafEdges].lf.p[(last - 1) % kLeafEdges];
 }
 
 // Rows with a tree: short trees by one thread, large ones queued for a block.
+// The top level goes to the row's node line, the levels below to its region.
+// Rows of at most kShortRow edges got their top level from k_leaves_short.
 __global__ void k_tree_short(const uint64_t* __restrict__ off, const uint64_t* __restrict__ region,
-                             uint32_t n, uint32_t tree_min, Block* __restrict__ blk,
+                             uint32_t n, uint32_t tree_min, Block* __restrict__ blk, Block* __restrict__ rec,
                              uint32_t* rows, uint32_t* n_rows, uint32_t* n_tree_rows) {
   for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
        u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint64_t d = off[u + 1] - off[u];
     if (d <= tree_min || d > kMaxDeg) continue;
     atomicAdd(n_tree_rows, 1u);
+    if (d <= kShortRow) continue;
     const uint64_t nodes = tree_nodes(d, tree_min);
     if (nodes > 16) {
       rows[atomicAdd(n_rows, 1u)] = static_cast<uint32_t>(u);
@@ -184,9 +189,12 @@ __global__ void k_tree_short(const uint64_t* __restrict__ off, const uint64_t* _
     }
     Block* dst = blk + region[u];
     const Block* leaves = dst + nodes;
-    for (uint32_t l = tree_levels(d); l >= 1; --l) {
+    const uint32_t L = tree_levels(d);
+    for (uint32_t k = 0; k < kTopKeys; ++k) rec[u].key[kTopKey0 + k] = level_key(leaves, d, L, k);
+    for (uint32_t l = L - 1; l >= 1; --l) {
       const uint64_t nl = tree_level_nodes(d, l);
-      for (uint64_t b = 0; b < nl; ++b) tree_node(leaves, d, l, b, dst + b);
+      for (uint64_t b = 0; b < nl; ++b)
+        for (uint32_t t = 0; t < kNodeKeys; ++t) dst[b].key[t] = level_key(leaves, d, l, b * kNodeKeys + t);
       dst += nl;
     }
   }
@@ -195,7 +203,7 @@ __global__ void k_tree_short(const uint64_t* __restrict__ off, const uint64_t* _
 __global__ void __launch_bounds__(kThreads) k_tree_long(const uint64_t* __restrict__ off,
                                                         const uint64_t* __restrict__ region,
                                                         uint32_t tree_min, Block* __restrict__ blk,
-                                                        const uint32_t* rows,
+                                                        Block* __restrict__ rec, const uint32_t* rows,
                                                         const uint32_t* n_rows) {
   const uint32_t nr = *n_rows;
   for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
@@ -204,9 +212,12 @@ __global__ void __launch_bounds__(kThreads) k_tree_long(const uint64_t* __restri
     const uint64_t nodes = tree_nodes(d, tree_min);
     Block* dst = blk + region[u];
     const Block* leaves = dst + nodes;
-    for (uint32_t l = tree_levels(d); l >= 1; --l) {
+    const uint32_t L = tree_levels(d);
+    if (threadIdx.x < kTopKeys) rec[u].key[kTopKey0 + threadIdx.x] = level_key(leaves, d, L, threadIdx.x);
+    for (uint32_t l = L - 1; l >= 1; --l) {
       const uint64_t nl = tree_level_nodes(d, l);
-      for (uint64_t b = threadIdx.x; b < nl; b += kThreads) tree_node(leaves, d, l, b, dst + b);
+      for (uint64_t k = threadIdx.x; k < nl * kNodeKeys; k += kThreads)
+        dst[k / kNodeKeys].key[k % kNodeKeys] = level_key(leaves, d, l, k);
       dst += nl;
     }
   }
@@ -345,9 +356,9 @@ hipError_t launch_trees(fppr_graph* g, hipStream_t s) {
   uint32_t* n_long = g->d_err + 8;
   uint32_t* n_tree = g->d_err + 9;
   hipLaunchKernelGGL(k_tree_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->region,
-                     g->n, g->tree_min, g->blocks, g->rows, n_long, n_tree);
+                     g->n, g->tree_min, g->blocks, g->rec, g->rows, n_long, n_tree);
   hipLaunchKernelGGL(k_tree_long, dim3(1024), dim3(kThreads), 0, s, g->off, g->region,
-                     g->tree_min, g->blocks, g->rows, n_long);
+                     g->tree_min, g->blocks, g->rec, g->rows, n_long);
   return hipGetLastError();
 }
 

@@ -8,10 +8,13 @@
 namespace fppr {
 
 // ---------------------------------------------------------------------------
-// Node record: 16 bytes, one per node, read with one 128-bit load.
-//   word 0 (64 bit): total weight W of the row (plain record), or the first
-//                    pool entry of the node (stitched record of a small node)
-//   word 1 (64 bit): (first block of the row's region << 28) | flags
+// Node line: 128 bytes per node (one memory line, read by one dependent
+// load), laid out as a Block:
+//   key[0]: total weight W of the row (plain table), or the address of the
+//           node's first pool entry (stitched table, small nodes)
+//   key[1]: (first block of the row's region << 28) | flags
+//   key[2..15]: the top level of the row's prefix tree (up to 14 keys, ~0
+//           past its end and in rows without a tree)
 // flags: bits 0..26 out-degree, bit 27 = small node served by the pool.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRegionShift = 28;
@@ -24,22 +27,25 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
 // Row regions. Every row owns a run of 128-byte blocks (one memory line):
-//   [prefix-tree nodes, top level first][leaf blocks]
+//   [prefix-tree nodes below the top level, top first][leaf blocks]
 // Leaf block b holds edges 8b .. 8b+7 of the row: their inclusive weight
 // prefixes P (8 x u64) and destination ids (8 x u32); slots past the row's
 // end hold P = ~0. A pick that knows its leaf block reads one line.
 // Prefix tree (integer form of the alias tree, Sec. 4.1 and Algorithm 3: the
 // row is cut into groups whose total weights form the next level,
-// recursively, and a pick walks from the root down to one group): rows with
+// recursively, and a pick walks from the top down to one group): rows with
 // more than the tree threshold of edges carry it. Level 1 has one key per
-// leaf block, level l one key per 16 nodes of level l-1; key k of level l is
-// P[min((k+1) * 8 * 16^(l-1), d) - 1]. A node is 16 keys (128 bytes; unused
-// keys ~0); the top level L is the first with at most 16 keys. Taking the
-// first key > X at every level and then the first prefix > X in the leaf
-// returns exactly the edge a flat search over P returns.
+// leaf block, level l one key per 16 keys of level l-1; key k of level l is
+// P[min((k+1) * 8 * 16^(l-1), d) - 1]. The top level L is the first with at
+// most 14 keys and sits in the node line; every level below it is stored as
+// nodes of 16 keys (128 bytes; unused keys ~0). Taking the first key > X at
+// every level and then the first prefix > X in the leaf returns exactly the
+// edge a flat search over P returns.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kLeafEdges = 8;
 constexpr uint32_t kNodeKeys = 16;
+constexpr uint32_t kTopKeys = 14;  // tree keys in a node line
+constexpr uint32_t kTopKey0 = 2;   // their first word
 
 struct LeafBlock {
   uint64_t p[kLeafEdges];  // inclusive prefixes (~0 past the row's end)
@@ -47,7 +53,7 @@ struct LeafBlock {
   uint32_t pad[kLeafEdges];
 };
 union alignas(128) Block {
-  uint64_t key[kNodeKeys];  // tree node
+  uint64_t key[kNodeKeys];  // tree node or node line
   LeafBlock lf;             // leaf block
 };
 static_assert(sizeof(Block) == 128, "one memory line per block");
@@ -55,13 +61,14 @@ static_assert(sizeof(Block) == 128, "one memory line per block");
 __host__ __device__ __forceinline__ uint64_t leaf_blocks(uint64_t d) {
   return (d + kLeafEdges - 1) / kLeafEdges;
 }
-// levels of the tree of a row with d edges (d > 8)
+// levels of the tree of a row with d edges (d > 8), the top level included:
+// level 1 has ceil(d / 8) keys, each level 16 times fewer (rounded up)
 __host__ __device__ __forceinline__ uint32_t tree_levels(uint64_t d) {
   uint32_t L = 1;
-  uint64_t span = kLeafEdges * kNodeKeys;  // edges covered by one level-L node
-  while (d > span) {
+  uint64_t keys = leaf_blocks(d);
+  while (keys > kTopKeys) {
     ++L;
-    span *= kNodeKeys;
+    keys = (keys + kNodeKeys - 1) / kNodeKeys;
   }
   return L;
 }
@@ -70,12 +77,13 @@ __host__ __device__ __forceinline__ uint64_t tree_level_nodes(uint64_t d, uint32
   const uint32_t sh = 3 + 4 * l;
   return (d + (1ull << sh) - 1) >> sh;
 }
-// tree nodes of a row (0 when it has no tree)
+// tree nodes a row keeps in its region: every level below the top (0 when
+// it has no tree, or its tree is the top level alone)
 __host__ __device__ __forceinline__ uint64_t tree_nodes(uint64_t d, uint32_t tree_min) {
   if (d <= tree_min) return 0;
   const uint32_t L = tree_levels(d);
   uint64_t t = 0;
-  for (uint32_t l = 1; l <= L; ++l) t += tree_level_nodes(d, l);
+  for (uint32_t l = 1; l < L; ++l) t += tree_level_nodes(d, l);
   return t;
 }
 __host__ __device__ __forceinline__ uint64_t region_blocks(uint64_t d, uint32_t tree_min) {
@@ -115,28 +123,29 @@ __device__ __forceinline__ uint64_t scaled_draw(uint32_t x0, uint32_t x1, uint64
 }
 
 struct GraphView {
-  const uint4* __restrict__ rec;     // plain records
+  const Block* __restrict__ rec;     // node lines (plain table)
   const Block* __restrict__ blocks;  // row regions
   uint32_t tree_min;                 // rows with deg > tree_min (>= 8) have a tree
 };
 
-__device__ __forceinline__ uint64_t rec_w(uint4 r) {
-  return (static_cast<uint64_t>(r.y) << 32) | r.x;
-}
-__device__ __forceinline__ uint64_t rec_od(uint4 r) {
-  return (static_cast<uint64_t>(r.w) << 32) | r.z;
+// number of the top-level keys of node line `ln` that are <= X
+__device__ __forceinline__ uint32_t top_count(const Block& ln, uint64_t X) {
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kTopKeys; ++k) c += (ln.key[kTopKey0 + k] <= X) ? 1u : 0u;
+  return c;
 }
 
 // Destination of the first edge whose prefix exceeds X (P[deg-1] = W > X),
-// with ordinary dependent loads: tree descent or a binary search over the
-// leaf blocks' last prefixes, then one leaf block.
-__device__ __forceinline__ uint32_t pick_blocking(const GraphView& g, uint64_t region, uint32_t deg,
-                                                  uint64_t X) {
+// with ordinary dependent loads: the top level from the node line, then the
+// tree levels below it, or a binary search over the leaf blocks' last
+// prefixes in rows without a tree; then one leaf block.
+__device__ __forceinline__ uint32_t pick_blocking(const GraphView& g, const Block& ln, uint64_t region,
+                                                  uint32_t deg, uint64_t X) {
   uint64_t leaf;
   if (deg > g.tree_min) {
-    const uint32_t L = tree_levels(deg);
-    uint64_t base = 0, b = 0;
-    for (uint32_t l = L; l >= 1; --l) {
+    uint64_t base = 0, b = top_count(ln, X);
+    for (uint32_t l = tree_levels(deg) - 1; l >= 1; --l) {
       const Block& nd = g.blocks[region + base + b];
       uint32_t cnt = 0;
 #pragma unroll

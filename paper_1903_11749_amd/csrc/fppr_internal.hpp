@@ -32,7 +32,7 @@ struct fppr_graph {
   const uint32_t* w = nullptr;
   bool owns_csr = false;
   // derived arrays
-  uint4* rec = nullptr;             // [n] node records
+  fppr::Block* rec = nullptr;       // [n] node lines
   fppr::Block* blocks = nullptr;    // [n_blocks] row regions: tree nodes, leaf blocks
   uint64_t n_blocks = 0;
   uint64_t* region = nullptr;       // [n] first block of each row's region
@@ -57,7 +57,7 @@ struct fppr_graph {
   uint32_t* dang = nullptr;          // [n_dang]
   uint64_t n_live = 0, n_dang = 0;
   uint64_t pool_cap = 0;             // entries allocated
-  uint4* rec_st = nullptr;           // [n] stitched records
+  fppr::Block* rec_st = nullptr;    // [n] stitched node lines
   uint32_t* small_nodes = nullptr;   // [n] rank -> node
   uint64_t device_bytes = 0;
 };
@@ -103,7 +103,7 @@ hipError_t launch_pool(fppr_graph* g, hipStream_t s);
 // endpoint goes to endpoints[w]. first is a multiple of kWalkChunk.
 constexpr uint64_t kWalkChunk = 256;
 struct WalkDesc {
-  const uint4* rec;          // plain records, or the stitched table
+  const Block* rec;          // plain node lines, or the stitched table
   const Block* blocks;       // row regions
   const uint32_t* sources;   // source ids by row, or null for row = node id
   uint32_t* endpoints;

@@ -33,31 +33,32 @@ __global__ void k_small_flags(const uint64_t* __restrict__ off, uint32_t n, uint
   }
 }
 
-// small_nodes[rank] = u and the stitched record table: small nodes point at
-// their pool block (absolute address), every other node keeps its plain
-// record.
+// small_nodes[rank] = u and the stitched node-line table: small nodes point
+// at their pool block (absolute address), every other node keeps its plain
+// line. Eight lanes copy one 128-byte line, 16 bytes each.
 __global__ void k_small_compact(const uint32_t* __restrict__ flag,
-                                const uint64_t* __restrict__ rank, const uint4* __restrict__ rec,
+                                const uint64_t* __restrict__ rank, const Block* __restrict__ rec,
                                 uint32_t n, uint32_t K_log2, uint64_t cap, const uint64_t* pool,
-                                uint32_t* __restrict__ small_nodes, uint4* __restrict__ rec_st,
+                                uint32_t* __restrict__ small_nodes, Block* __restrict__ rec_st,
                                 uint32_t* err) {
-  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
-       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    uint4 r = rec[u];
-    if (flag[u]) {
+  const uint64_t total = static_cast<uint64_t>(n) * 8;
+  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t u = t >> 3;
+    const uint32_t part = static_cast<uint32_t>(t & 7);
+    ulonglong2 v = reinterpret_cast<const ulonglong2*>(rec + u)[part];
+    if (part == 0 && flag[u]) {
       const uint64_t k = rank[u];
       if (k >= cap) {
         atomicOr(err, kErrCapacity);
       } else {
         small_nodes[k] = static_cast<uint32_t>(u);
-        // the stitched record carries the address of the node's first entry
-        const uint64_t base = reinterpret_cast<uint64_t>(pool + (k << K_log2));
-        const uint64_t od = rec_od(r) | kPoolFlag;
-        r = make_uint4(static_cast<uint32_t>(base), static_cast<uint32_t>(base >> 32),
-                       static_cast<uint32_t>(od), static_cast<uint32_t>(od >> 32));
+        // the stitched line carries the address of the node's first entry
+        v.x = reinterpret_cast<uint64_t>(pool + (k << K_log2));
+        v.y |= kPoolFlag;
       }
     }
-    rec_st[u] = r;
+    reinterpret_cast<ulonglong2*>(rec_st + u)[part] = v;
   }
 }
 
@@ -73,13 +74,13 @@ __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* 
     const uint32_t v = small_nodes[idx >> K_log2];
     uint32_t cur = v, steps = 0, mark = 0;
     for (uint32_t t = 0; t < L; ++t) {
-      const uint4 r = g.rec[cur];
-      const uint64_t od = rec_od(r);
+      const Block& ln = g.rec[cur];
+      const uint64_t od = ln.key[1];
       const uint32_t deg = static_cast<uint32_t>(od & kDegMask);
       if (deg == 0) break;  // arrived at a node without out-edges: stays active
       const U4 x = philox10(j, t, v, 1u, key0, key1);
-      const uint64_t X = scaled_draw(x.x0, x.x1, rec_w(r));
-      cur = pick_blocking(g, od >> kRegionShift, deg, X);
+      const uint64_t X = scaled_draw(x.x0, x.x1, ln.key[0]);
+      cur = pick_blocking(g, ln, od >> kRegionShift, deg, X);
       steps += 1;
       if (x.x2 < T) {
         mark = 1;
@@ -101,7 +102,8 @@ hipError_t launch_small_flags(fppr_graph* g, uint32_t S, hipStream_t s) {
 }
 
 hipError_t launch_small_compact(fppr_graph* g, uint32_t /*S*/, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_compact, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->flag, g->scan,
+  hipLaunchKernelGGL(k_small_compact, dim3(grid_for(static_cast<uint64_t>(g->n) * 8)), dim3(kThreads), 0, s,
+                     g->flag, g->scan,
                      g->rec, g->n, g->K_log2, g->n_small, g->pool, g->small_nodes, g->rec_st,
                      g->d_err);
   return hipGetLastError();

@@ -21,13 +21,15 @@
 // waves switch descriptors without waiting.
 //
 // Each lane runs its walk as a small state machine that needs exactly one
-// dependent load per loop iteration (node record, one 128-byte tree node, one
-// 128-byte leaf block of prefixes and destinations, or one pool entry). Tree
-// nodes and leaf blocks are read by lane pairs, 64 bytes per lane: on gfx950
-// random 128-byte lines stream at full rate only when each lane takes at most
-// half a line (a lane reading a whole line of its own runs 3.7x slower). The
-// head's record stays in registers, so the restart from a node without
-// out-edges (Sec. 2.1) costs no load at all.
+// dependent load per loop iteration (a 128-byte node line, one 128-byte tree
+// node, one 128-byte leaf block of prefixes and destinations, or one pool
+// entry). Lines are read by lane pairs, 64 bytes per lane: on gfx950 random
+// 128-byte lines stream at full rate only when each lane takes at most half a
+// line (a lane reading a whole line of its own runs 3.7x slower). A node
+// line brings the top level of the row's prefix tree with it; the pair hands
+// its keys to the owner through LDS, so a pick at a row with a tree starts one
+// level down. The head's weight and flags stay in registers, so the restart
+// from a node without out-edges (Sec. 2.1) costs no load at all.
 //
 // One move (integer only):
 //   x = Philox4x32-10(key = seed, counter = (i, m, s, 0))
@@ -47,8 +49,8 @@ constexpr uint32_t kInlineRestarts = 4;  // restarts handled per iteration (4 me
 
 enum : uint32_t {
   kIdle = 0,
-  kSrcRec = 1,  // load the head's record (kept in registers)
-  kRec = 2,     // load the tail's record
+  kSrcRec = 1,  // load the head's node line (weight and flags kept in registers)
+  kRec = 2,     // load the tail's node line
   kTree = 3,    // load one prefix-tree node (128 bytes)
   kBsearch = 4, // load one leaf block's last prefix (rows without a tree, > 8 edges)
   kLeaf = 5,    // load one leaf block: 8 prefixes and their destinations
@@ -114,6 +116,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   __shared__ uint64_t sh_x[kThreads / 64][64];
   __shared__ uint32_t sh_res[kThreads / 64][64];
   __shared__ uint32_t sh_src[kThreads / 64][kSrcBuf];  // the current chunk's source ids
+  __shared__ uint4 sh_top[kThreads / 64][64][kTopKeys / 2];  // top tree keys of each lane's node line
   const uint32_t lane = __lane_id();
   const uint32_t wv = threadIdx.x / 64;
   Lane L{};
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   uint32_t d = ~0u, pend_d = 0;
   bool exhausted = false;
   uint64_t walks = 0;  // walks started by this wave
-  const uint4* rec = nullptr;
+  const Block* rec = nullptr;
   const Block* blocks = nullptr;
   const uint32_t* sources = nullptr;
   uint32_t* endpoints = nullptr;
@@ -247,30 +250,30 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
     if (__ballot(L.ph != kIdle) == 0) break;
 
     // ---- this iteration's loads ----
-    // Records, pool entries and probes are one small load per lane. Tree nodes
-    // and leaf blocks are whole 128-byte lines loaded by lane pairs.
+    // Pool entries and probes are one small load per lane. Node lines, tree
+    // nodes and leaf blocks are whole 128-byte lines loaded by lane pairs.
     const uint32_t ph = L.ph;
+    const bool rec_line = (ph == kSrcRec || ph == kRec);
     uint64_t v0 = 0, v1 = 0;
-    if (ph == kSrcRec || ph == kRec) {
-      const uint4 r = rec[L.tail];
-      v0 = rec_w(r);
-      v1 = rec_od(r);
-    } else if (ph == kBsearch) {
+    if (ph == kBsearch) {
       v0 = blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)].lf.p[kLeafEdges - 1];
     } else if (ph == kPool) {
       v0 = *reinterpret_cast<const uint64_t*>(L.X);
     }
-    const bool want_line = (ph == kTree || ph == kLeaf);
+    const bool want_line = rec_line || ph == kTree || ph == kLeaf;
     const uint64_t line_mask = __ballot(want_line);
     const uint64_t leaf_mask = __ballot(ph == kLeaf);
+    const uint64_t rec_mask = __ballot(rec_line);
     uint32_t line_res = 0;  // tree: keys <= X in the node; leaf: destination
     if (line_mask) {
       // Owners publish their line and draw in the wave's LDS table. Lane pairs
       // load lines: in round r the pair p reads the line of lane 32 r + p, the
-      // even lane its first 64 bytes (tree keys 0..7, or the leaf's 8
-      // prefixes), the odd lane the rest (keys 8..15, or the 8 destinations).
-      sh_line[wv][lane] =
-          want_line ? reinterpret_cast<uint64_t>(blocks + L.off + L.hi + L.lo) : 0;
+      // even lane its first 64 bytes (tree keys 0..7, the leaf's 8 prefixes,
+      // or the node line's weight, flags and top keys 0..5), the odd lane the
+      // rest (keys 8..15, the 8 destinations, or top keys 6..13).
+      sh_line[wv][lane] = !want_line ? 0
+                          : rec_line ? reinterpret_cast<uint64_t>(rec + L.tail)
+                                     : reinterpret_cast<uint64_t>(blocks + L.off + L.hi + L.lo);
       sh_x[wv][lane] = L.X;
       wave_sync();
       const uint32_t half = lane & 1u, pair = lane >> 1;
@@ -290,6 +293,22 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
       for (uint32_t r = 0; r < 2; ++r) {
         if (((line_mask >> (32 * r)) & 0xFFFFFFFFull) == 0) continue;
         const uint32_t owner = 32 * r + pair;
+        if ((rec_mask >> owner) & 1ull) {  // node line: weight and flags, top keys to the owner
+          uint4* top = sh_top[wv][owner];
+          if (half == 0) {
+            sh_x[wv][owner] = (static_cast<uint64_t>(q[r][0].y) << 32) | q[r][0].x;
+            sh_line[wv][owner] = (static_cast<uint64_t>(q[r][0].w) << 32) | q[r][0].z;
+            top[0] = q[r][1];
+            top[1] = q[r][2];
+            top[2] = q[r][3];
+          } else {
+            top[3] = q[r][0];
+            top[4] = q[r][1];
+            top[5] = q[r][2];
+            top[6] = q[r][3];
+          }
+          continue;
+        }
         const uint64_t xo = sh_x[wv][owner];
         const bool leaf = (leaf_mask >> owner) & 1ull;
         uint32_t cnt = 0;
@@ -314,6 +333,10 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
       }
       wave_sync();
       line_res = sh_res[wv][lane];
+      if (rec_line) {
+        v0 = sh_x[wv][lane];
+        v1 = sh_line[wv][lane];
+      }
       wave_sync();
     }
 
@@ -366,14 +389,15 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         done = true;
         capped = !coin;
       } else if (L.tail == L.s) {
-        begin = true;  // back at the head: its record is in registers
+        begin = true;  // back at the head: its weight and flags are in registers
       } else {
         L.ph = kRec;
       }
     }
 
-    // ---- start a move at the tail with record (bw, bod) ----
+    // ---- start a move at the tail with weight bw and flags bod ----
     if (begin) {
+      bool fresh = rec_line;  // the node line was loaded this iteration: its top keys are in LDS
       for (uint32_t restarts = 0;; ++restarts) {
         const U4 x = kLaneKeys ? philox10(L.i, L.m, L.s, 0u, L.k0, L.k1)
                                : philox10(L.i, L.m, L.s, 0u, key0, key1);
@@ -390,15 +414,20 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           }
           bw = L.sW;
           bod = L.s_od;
+          fresh = false;
           if (restarts + 1 >= kInlineRestarts) {
             L.ph = kCont;
             break;
           }
           continue;
         }
-        if (bod & kPoolFlag) {  // small node: its record holds the pool block address
+        if (bod & kPoolFlag) {  // small node: its line holds the pool block address
           L.X = bw + (((static_cast<uint64_t>(x.x0) << K_log2) >> 32) << 3);
           L.ph = kPool;
+          break;
+        }
+        if (dg > tree_min && !fresh) {  // the head's top keys: load its line again (same draw)
+          L.ph = kRec;
           break;
         }
         L.X = scaled_draw(x.x0, x.x1, bw);
@@ -412,8 +441,24 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         L.lo = 0;
         L.hi = 0;
         if (dg > tree_min) {
-          L.lvl = tree_levels(dg);  // lo: node within the level, hi: first node of the level
-          L.ph = kTree;
+          // top level from the node line; lo: node within the next level (or
+          // the leaf block), hi: first node of that level
+          uint32_t c = 0;
+#pragma unroll
+          for (uint32_t k = 0; k < kTopKeys / 2; ++k) {
+            const uint4 v = sh_top[wv][lane][k];
+            const uint64_t k0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
+            const uint64_t k1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
+            c += (k0 <= L.X ? 1u : 0u) + (k1 <= L.X ? 1u : 0u);
+          }
+          L.lo = c;
+          const uint32_t lv = tree_levels(dg);
+          if (lv == 1) {
+            L.ph = kLeaf;
+          } else {
+            L.lvl = lv - 1;
+            L.ph = kTree;
+          }
         } else if (dg > kLeafEdges) {
           L.hi = static_cast<uint32_t>(leaf_blocks(dg)) - 1;  // candidate leaf blocks [lo, hi]
           L.ph = kBsearch;
