@@ -212,8 +212,10 @@ FPPR_API fppr_status fppr_profile_destroy(fppr_profile* p);
  * and aggregation kernel durations in milliseconds (host outputs). */
 FPPR_API fppr_status fppr_profile_read(fppr_profile* p, double* walk_ms, double* aggregate_ms);
 /* Splits the walk time of the last single-launch run that used `p`: the walk
- * kernel alone, and the coin-only kernel that an all-nodes run launches for
- * the nodes without out-edges (0 when it was not launched; see fppr_run).
+ * kernel alone, and the time after it until the coin-only kernel that an
+ * all-nodes run launches for the nodes without out-edges has also finished
+ * (it runs beside the walk kernel on a stream of the graph's own; 0 when it
+ * finished first or was not launched; see fppr_run).
  * Blocked runs report their whole walk-and-count time as walk kernel time;
  * batch runs report 0 coin-only time (their coin-only kernels run on the
  * counting streams and are timed with the aggregation). */

@@ -65,6 +65,9 @@ void free_graph(fppr_graph* g) {
   dfree(g->small_nodes);
   dfree(g->live);
   dfree(g->dang);
+  if (g->side) (void)hipStreamDestroy(g->side);
+  if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
+  if (g->join_ev) (void)hipEventDestroy(g->join_ev);
   if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
   delete g;
 }
@@ -307,6 +310,11 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   FPPR_TRY(read_ctl(g, s, &c), "read region sizes");
   g->n_live = c.live;
   g->n_dang = n - c.live;
+  if (split_dangling(g)) {
+    FPPR_TRY(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking), "hipStreamCreate(side)");
+    FPPR_TRY(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming), "hipEventCreate(fork)");
+    FPPR_TRY(hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming), "hipEventCreate(join)");
+  }
   g->n_blocks = c.blocks;
   FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
   FPPR_TRY(launch_leaves(g, s), "leaf blocks");
@@ -550,17 +558,29 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
     // All nodes in one launch: the walk kernel takes the nodes with out-edges
     // and a coin-only kernel the others (their walks only restart at the
     // source and always end there); draws and results are those of one
-    // launch over every node.
+    // launch over every node. The coin-only kernel (arithmetic only, few
+    // registers, no LDS) runs on the graph's side stream, in the wave slots
+    // the memory-bound walk kernel leaves free.
     const bool split = !sources && !blocked && split_dangling(g);
     WalkDesc D = split ? make_desc(g, p, g->live, g->n_live, ep_base, 0, 0, g->n_live * p->R)
                        : make_desc(g, p, sources, n_sources, ep_base, 0, r0 * p->R, nb * p->R);
     if (split) D.flags = kDescEpBySource;
     if ((e = launch_set_desc(D, desc, s)) != hipSuccess) return hip_fail(e, "walk descriptor");
     const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
+    if (split) {  // the side stream starts after everything queued on `s` so far
+      std::lock_guard<std::mutex> lk(g->side_mu);
+      if ((e = hipEventRecord(g->fork_ev, s)) != hipSuccess) return hip_fail(e, "fork event");
+      if ((e = hipStreamWaitEvent(g->side, g->fork_ev, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+    }
     if (total && (e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
       return hip_fail(e, "walk kernel");
     if (prof && !blocked && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
-    if (split && (e = launch_dangling(g, p, ep_base, stats, s)) != hipSuccess) return hip_fail(e, "dangling walks");
+    if (split) {
+      std::lock_guard<std::mutex> lk(g->side_mu);
+      if ((e = launch_dangling(g, p, ep_base, stats, g->side)) != hipSuccess) return hip_fail(e, "dangling walks");
+      if ((e = hipEventRecord(g->join_ev, g->side)) != hipSuccess) return hip_fail(e, "join event");
+      if ((e = hipStreamWaitEvent(s, g->join_ev, 0)) != hipSuccess) return hip_fail(e, "join wait");
+    }
     if (prof && !blocked && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
     AggLaunch a = make_agg(p, out->endpoints ? out->endpoints + r0 * p->R : ws_ep, sources ? sources + r0 : nullptr,
                            nb, out);

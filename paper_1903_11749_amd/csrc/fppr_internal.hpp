@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/fppr.h"
@@ -56,6 +57,11 @@ struct fppr_graph {
   uint32_t* live = nullptr;          // [n_live]
   uint32_t* dang = nullptr;          // [n_dang]
   uint64_t n_live = 0, n_dang = 0;
+  // side stream of all-nodes runs on graphs with many nodes without
+  // out-edges: their coin-only kernel runs there beside the walk kernel
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  std::mutex side_mu;  // keeps each event record and its wait together across host threads
   uint64_t pool_cap = 0;             // entries allocated
   fppr::Block* rec_st = nullptr;    // [n] stitched node lines
   uint32_t* small_nodes = nullptr;   // [n] rank -> node

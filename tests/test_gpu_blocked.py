@@ -118,9 +118,9 @@ def test_split_run_equals_blocked_and_oracle(fp):
 
 
 def test_profile_splits_walk_and_coin_only_time(fp):
-    """The stage timer reports the walk kernel and the coin-only kernel apart;
-    their sum is the walk time, and runs without the coin-only kernel report
-    0 for it."""
+    """The stage timer reports the walk kernel and the time the coin-only
+    kernel (beside it on the graph's side stream) adds after it; their sum is
+    the walk time, and runs without the coin-only kernel report 0 for it."""
     import torch
 
     say("case: stage timer of a split all-nodes run and of a source-list run")
@@ -139,7 +139,5 @@ def test_profile_splits_walk_and_coin_only_time(fp):
         kern, coin = prof.read_walk()
         assert kern > 0 and coin >= 0
         assert abs(kern + coin - walk) < 1e-3 + 1e-3 * walk
-        if src is None:
-            assert coin > 0
-        else:
+        if src is not None:
             assert coin < 0.05
