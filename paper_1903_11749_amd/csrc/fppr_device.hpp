@@ -128,47 +128,6 @@ struct GraphView {
   uint32_t tree_min;                 // rows with deg > tree_min (>= 8) have a tree
 };
 
-// number of the top-level keys of node line `ln` that are <= X
-__device__ __forceinline__ uint32_t top_count(const Block& ln, uint64_t X) {
-  uint32_t c = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < kTopKeys; ++k) c += (ln.key[kTopKey0 + k] <= X) ? 1u : 0u;
-  return c;
-}
-
-// Destination of the first edge whose prefix exceeds X (P[deg-1] = W > X),
-// with ordinary dependent loads: the top level from the node line, then the
-// tree levels below it, or a binary search over the leaf blocks' last
-// prefixes in rows without a tree; then one leaf block.
-__device__ __forceinline__ uint32_t pick_blocking(const GraphView& g, const Block& ln, uint64_t region,
-                                                  uint32_t deg, uint64_t X) {
-  uint64_t leaf;
-  if (deg > g.tree_min) {
-    uint64_t base = 0, b = top_count(ln, X);
-    for (uint32_t l = tree_levels(deg) - 1; l >= 1; --l) {
-      const Block& nd = g.blocks[region + base + b];
-      uint32_t cnt = 0;
-#pragma unroll
-      for (uint32_t k = 0; k < kNodeKeys; ++k) cnt += (nd.key[k] <= X) ? 1u : 0u;
-      base += tree_level_nodes(deg, l);
-      b = b * kNodeKeys + cnt;
-    }
-    leaf = region + base + b;
-  } else {
-    uint64_t lo = 0, hi = leaf_blocks(deg) - 1;
-    while (lo < hi) {
-      const uint64_t mid = lo + ((hi - lo) >> 1);
-      if (g.blocks[region + mid].lf.p[kLeafEdges - 1] > X) hi = mid; else lo = mid + 1;
-    }
-    leaf = region + lo;
-  }
-  const LeafBlock& lb = g.blocks[leaf].lf;
-  uint32_t j = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < kLeafEdges; ++k) j += (lb.p[k] <= X) ? 1u : 0u;
-  return lb.c[j];
-}
-
 __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t d) {
   return d <= 1 ? 0u : 32u - __clz(d - 1u);
 }

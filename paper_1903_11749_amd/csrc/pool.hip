@@ -62,33 +62,100 @@ __global__ void k_small_compact(const uint32_t* __restrict__ flag,
   }
 }
 
-// One thread per (small node rank, slot j).
+// The value of the other lane of this lane's aligned pair (DPP quad
+// permutation [1, 0, 3, 2]).
+__device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint64_t pair_swap64(uint64_t x) {
+  return static_cast<uint64_t>(pair_swap(static_cast<uint32_t>(x))) |
+         (static_cast<uint64_t>(pair_swap(static_cast<uint32_t>(x >> 32))) << 32);
+}
+// keys of q (two u64) that are <= X
+__device__ __forceinline__ uint32_t count2(uint4 q, uint64_t X) {
+  const uint64_t k0 = (static_cast<uint64_t>(q.y) << 32) | q.x;
+  const uint64_t k1 = (static_cast<uint64_t>(q.w) << 32) | q.z;
+  return (k0 <= X ? 1u : 0u) + (k1 <= X ? 1u : 0u);
+}
+
+// A lane pair per (small node rank, slot j): both lanes follow the same pool
+// walk, and each reads one half of every 128-byte line it needs (the even
+// lane bytes 0..63, the odd lane bytes 64..127), adding the pair's compare
+// counts with one DPP swap, so that no lane reads more than 64 bytes of a
+// random line. The 64 slots of a small node sit in consecutive pairs, so
+// their first steps read the same lines.
 __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* __restrict__ small_nodes,
                                                    uint64_t n_small, uint32_t K_log2, uint32_t L,
                                                    uint32_t T, uint32_t key0, uint32_t key1,
                                                    uint64_t* __restrict__ pool) {
   const uint64_t total = n_small << K_log2;
-  for (uint64_t idx = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; idx < total;
-       idx += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+  const uint32_t half = threadIdx.x & 1u;
+  const uint64_t stride = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 1;
+  for (uint64_t idx = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) >> 1; idx < total;
+       idx += stride) {
     const uint32_t j = static_cast<uint32_t>(idx & ((1ull << K_log2) - 1));
     const uint32_t v = small_nodes[idx >> K_log2];
     uint32_t cur = v, steps = 0, mark = 0;
     for (uint32_t t = 0; t < L; ++t) {
-      const Block& ln = g.rec[cur];
-      const uint64_t od = ln.key[1];
+      // node line: weight and flags (even lane's first 16 bytes) and top keys
+      const uint4* ln = reinterpret_cast<const uint4*>(g.rec + cur) + half * 4;
+      const uint4 q0 = ln[0], q1 = ln[1], q2 = ln[2], q3 = ln[3];
+      const uint64_t W0 = (static_cast<uint64_t>(q0.y) << 32) | q0.x;
+      const uint64_t od0 = (static_cast<uint64_t>(q0.w) << 32) | q0.z;
+      const uint64_t Wp = pair_swap64(W0), odp = pair_swap64(od0);
+      const uint64_t W = half ? Wp : W0, od = half ? odp : od0;
       const uint32_t deg = static_cast<uint32_t>(od & kDegMask);
       if (deg == 0) break;  // arrived at a node without out-edges: stays active
       const U4 x = philox10(j, t, v, 1u, key0, key1);
-      const uint64_t X = scaled_draw(x.x0, x.x1, ln.key[0]);
-      cur = pick_blocking(g, ln, od >> kRegionShift, deg, X);
+      const uint64_t X = scaled_draw(x.x0, x.x1, W);
+      const uint64_t region = od >> kRegionShift;
+      uint64_t leaf;
+      if (deg > g.tree_min) {
+        uint32_t c = half ? count2(q0, X) + count2(q1, X) + count2(q2, X) + count2(q3, X)
+                          : count2(q1, X) + count2(q2, X) + count2(q3, X);
+        c += pair_swap(c);
+        uint64_t base = 0, b = c;
+        for (uint32_t l = tree_levels(deg) - 1; l >= 1; --l) {
+          const uint4* nd = reinterpret_cast<const uint4*>(g.blocks + region + base + b) + half * 4;
+          uint32_t cc = count2(nd[0], X) + count2(nd[1], X) + count2(nd[2], X) + count2(nd[3], X);
+          cc += pair_swap(cc);
+          base += tree_level_nodes(deg, l);
+          b = b * kNodeKeys + cc;
+        }
+        leaf = region + base + b;
+      } else {
+        uint64_t lo = 0, hi = leaf_blocks(deg) - 1;
+        while (lo < hi) {
+          const uint64_t mid = lo + ((hi - lo) >> 1);
+          if (g.blocks[region + mid].lf.p[kLeafEdges - 1] > X) hi = mid; else lo = mid + 1;
+        }
+        leaf = region + lo;
+      }
+      // leaf block: the even lane counts the 8 prefixes, the odd lane holds
+      // the 8 destinations
+      const uint4* lf = reinterpret_cast<const uint4*>(g.blocks + leaf) + half * 4;
+      uint32_t e = 0, dst = 0;
+      const uint4 l0 = lf[0], l1 = lf[1];
+      if (half == 0) {
+        e = count2(l0, X) + count2(l1, X) + count2(lf[2], X) + count2(lf[3], X);
+      }
+      e += pair_swap(e);
+      if (half) {
+        const uint4 w = e < 4 ? l0 : l1;
+        const uint32_t k = e & 3u;
+        dst = k == 0 ? w.x : (k == 1 ? w.y : (k == 2 ? w.z : w.w));
+      }
+      dst += pair_swap(dst);
+      cur = dst;
       steps += 1;
       if (x.x2 < T) {
         mark = 1;
         break;
       }
     }
-    pool[idx] = static_cast<uint64_t>(cur) | (static_cast<uint64_t>(steps) << 32) |
-                (static_cast<uint64_t>(mark) << 48);
+    if (half == 0)
+      pool[idx] = static_cast<uint64_t>(cur) | (static_cast<uint64_t>(steps) << 32) |
+                  (static_cast<uint64_t>(mark) << 48);
   }
 }
 
@@ -114,7 +181,7 @@ hipError_t launch_pool(fppr_graph* g, hipStream_t s) {
   if (total == 0) return hipSuccess;
   GraphView gv{g->rec, g->blocks, g->tree_min};
   const uint64_t seed = g->pool_opts.seed;
-  hipLaunchKernelGGL(k_pool, dim3(grid_for(total)), dim3(kThreads), 0, s, gv, g->small_nodes,
+  hipLaunchKernelGGL(k_pool, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
                      g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,
                      static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->pool);
   return hipGetLastError();
