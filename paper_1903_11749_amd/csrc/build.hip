@@ -1,6 +1,7 @@
 // Graph ingest: CSR validation, per-row inclusive uint64 weight prefixes laid
 // out with the destination ids in 128-byte leaf blocks, 128-byte node lines
-// and the rows' prefix trees (top level in the node line, 16-ary below).
+// and the rows' prefix trees (top level in the node line, 16-ary below),
+// all in one pass over the edges.
 //
 // Routing probability r(s,t) = w(s,t) / sum_v w(s,v) (Sec. 2.1) is realised
 // on exact integers: the prefix P of a row is strictly increasing (w >= 1),
@@ -65,12 +66,14 @@ __device__ __forceinline__ void write_record(Block* rec, uint64_t u, uint64_t W,
 }
 
 // Short rows: one thread accumulates its row into its leaf blocks and writes
-// its record. Long rows are queued for a block each.
+// its node line. Long rows are queued for a block each. Rows with a tree are
+// counted (one atomic per wave).
 __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
                                const uint32_t* __restrict__ w, const uint64_t* __restrict__ region,
                                uint32_t n, uint32_t tree_min, uint64_t cap, Block* __restrict__ blk,
                                Block* __restrict__ rec, uint32_t* rows, uint32_t* n_rows,
-                               uint32_t* err) {
+                               uint32_t* n_tree_rows, uint32_t* err) {
+  uint64_t trees = 0;
   for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
        u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint64_t a = off[u];
@@ -80,6 +83,7 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
       atomicOr(err, kErrDegree);
       continue;
     }
+    trees += d > tree_min ? 1u : 0u;
     if (r0 + region_blocks(d, tree_min) > cap) {
       atomicOr(err, kErrCapacity);
       continue;
@@ -110,9 +114,36 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
     }
     rec[u].key[0] = acc;
   }
+  trees = wave_sum_u64(trees);
+  if (__lane_id() == 0 && trees) atomicAdd(n_tree_rows, static_cast<uint32_t>(trees));
 }
 
-// Long rows: one block per row, scanning tiles of kThreads*4 weights.
+// Puts prefix P = P[j] of a row with a tree (d edges, L levels, T region tree
+// nodes) into every level whose key ends at edge j: key k of level l is
+// P[min((k+1) * 8 * 16^(l-1), d) - 1]. The top level goes to the node line
+// (whose unused keys are already ~0); at the row's last edge the rest of
+// each region level's last node is padded with ~0.
+__device__ __forceinline__ void place_tree_key(Block* __restrict__ region_base, Block* __restrict__ line,
+                                               uint64_t d, uint32_t L, uint64_t T, uint64_t j, uint64_t P) {
+  const bool last = j == d - 1;
+  uint64_t span = kLeafEdges, cum = 0;
+  for (uint32_t l = 1; l <= L; ++l, span *= kNodeKeys) {
+    if (!last && ((j + 1) & (span - 1)) != 0) return;  // not a key boundary here, nor above
+    const uint64_t k = j / span;
+    if (l == L) {
+      line->key[kTopKey0 + k] = P;
+    } else {
+      cum += tree_level_nodes(d, l);
+      Block* nd = region_base + (T - cum) + k / kNodeKeys;  // levels stored top first
+      nd->key[k % kNodeKeys] = P;
+      if (last)
+        for (uint64_t t = k % kNodeKeys + 1; t < kNodeKeys; ++t) nd->key[t] = ~0ull;
+    }
+  }
+}
+
+// Long rows: one block per row, scanning tiles of kThreads*4 weights; every
+// prefix also goes into the tree levels whose keys end at it.
 __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __restrict__ off,
                                                           const uint32_t* __restrict__ col,
                                                           const uint32_t* __restrict__ w,
@@ -128,7 +159,13 @@ __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __rest
     const uint64_t a = off[u];
     const uint64_t d = off[u + 1] - a;
     const uint64_t r0 = region[u];
-    Block* leaves = blk + r0 + tree_nodes(d, tree_min);
+    const uint64_t T = tree_nodes(d, tree_min);
+    const bool tree = d > tree_min;
+    const uint32_t L = tree ? tree_levels(d) : 0;
+    Block* leaves = blk + r0 + T;
+    // the node line before any of its tree keys (the scans' barriers order
+    // this write before theirs); its weight comes with the last edge
+    if (threadIdx.x == 0) write_record(rec, u, 0, r0, d);
     uint64_t carry = 0;
     for (uint64_t t0 = 0; t0 < d; t0 += kThreads * 4) {
       const uint64_t j0 = t0 + threadIdx.x * 4ull;
@@ -146,79 +183,17 @@ __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __rest
       for (int k = 0; k < 4; ++k) {
         const uint64_t j = j0 + k;
         if (j < d) {
-          leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = carry + excl + v[k];
+          const uint64_t P = carry + excl + v[k];
+          leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = P;
           leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = col[a + j];
-          if (j == d - 1) write_record(rec, u, carry + excl + v[k], r0, d);
+          if (tree) place_tree_key(blk + r0, rec + u, d, L, T, j, P);
+          if (j == d - 1) rec[u].key[0] = P;
         } else if (j < leaf_blocks(d) * kLeafEdges) {
           leaves[j / kLeafEdges].lf.p[j % kLeafEdges] = ~0ull;
           leaves[j / kLeafEdges].lf.c[j % kLeafEdges] = 0u;
         }
       }
       carry += total;
-    }
-  }
-}
-
-// Key k of level l of the tree of a row (~0 past the level's end), read from
-// its leaves.
-__device__ __forceinline__ uint64_t level_key(const Block* __restrict__ leaves, uint64_t d, uint32_t l,
-                                              uint64_t k) {
-  const uint32_t sh = 3 + 4 * (l - 1);  // edges covered by one key of level l: 8 * 16^(l-1)
-  if (k >= ((d + (1ull << sh) - 1) >> sh)) return ~0ull;
-  uint64_t last = (k + 1) << sh;
-  if (last > d) last = d;
-  return leaves[(last - 1) / kLeafEdges].lf.p[(last - 1) % kLeafEdges];
-}
-
-// Rows with a tree: short trees by one thread, large ones queued for a block.
-// The top level goes to the row's node line, the levels below to its region.
-// Rows of at most kShortRow edges got their top level from k_leaves_short.
-__global__ void k_tree_short(const uint64_t* __restrict__ off, const uint64_t* __restrict__ region,
-                             uint32_t n, uint32_t tree_min, Block* __restrict__ blk, Block* __restrict__ rec,
-                             uint32_t* rows, uint32_t* n_rows, uint32_t* n_tree_rows) {
-  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
-       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t d = off[u + 1] - off[u];
-    if (d <= tree_min || d > kMaxDeg) continue;
-    atomicAdd(n_tree_rows, 1u);
-    if (d <= kShortRow) continue;
-    const uint64_t nodes = tree_nodes(d, tree_min);
-    if (nodes > 16) {
-      rows[atomicAdd(n_rows, 1u)] = static_cast<uint32_t>(u);
-      continue;
-    }
-    Block* dst = blk + region[u];
-    const Block* leaves = dst + nodes;
-    const uint32_t L = tree_levels(d);
-    for (uint32_t k = 0; k < kTopKeys; ++k) rec[u].key[kTopKey0 + k] = level_key(leaves, d, L, k);
-    for (uint32_t l = L - 1; l >= 1; --l) {
-      const uint64_t nl = tree_level_nodes(d, l);
-      for (uint64_t b = 0; b < nl; ++b)
-        for (uint32_t t = 0; t < kNodeKeys; ++t) dst[b].key[t] = level_key(leaves, d, l, b * kNodeKeys + t);
-      dst += nl;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kThreads) k_tree_long(const uint64_t* __restrict__ off,
-                                                        const uint64_t* __restrict__ region,
-                                                        uint32_t tree_min, Block* __restrict__ blk,
-                                                        Block* __restrict__ rec, const uint32_t* rows,
-                                                        const uint32_t* n_rows) {
-  const uint32_t nr = *n_rows;
-  for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
-    const uint32_t u = rows[r];
-    const uint64_t d = off[u + 1] - off[u];
-    const uint64_t nodes = tree_nodes(d, tree_min);
-    Block* dst = blk + region[u];
-    const Block* leaves = dst + nodes;
-    const uint32_t L = tree_levels(d);
-    if (threadIdx.x < kTopKeys) rec[u].key[kTopKey0 + threadIdx.x] = level_key(leaves, d, L, threadIdx.x);
-    for (uint32_t l = L - 1; l >= 1; --l) {
-      const uint64_t nl = tree_level_nodes(d, l);
-      for (uint64_t k = threadIdx.x; k < nl * kNodeKeys; k += kThreads)
-        dst[k / kNodeKeys].key[k % kNodeKeys] = level_key(leaves, d, l, k);
-      dst += nl;
     }
   }
 }
@@ -345,20 +320,9 @@ hipError_t launch_leaves(fppr_graph* g, hipStream_t s) {
   uint32_t* n_long = g->d_err + 1;
   hipLaunchKernelGGL(k_leaves_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->col,
                      g->w, g->region, g->n, g->tree_min, g->n_blocks, g->blocks, g->rec, g->rows,
-                     n_long, g->d_err);
+                     n_long, g->d_err + 9, g->d_err);
   hipLaunchKernelGGL(k_leaves_long, dim3(2048), dim3(kThreads), 0, s, g->off, g->col, g->w,
                      g->region, g->tree_min, g->blocks, g->rec, g->rows, n_long);
-  return hipGetLastError();
-}
-
-hipError_t launch_trees(fppr_graph* g, hipStream_t s) {
-  if (g->m == 0 || g->tree_min == 0xFFFFFFFFu) return hipSuccess;
-  uint32_t* n_long = g->d_err + 8;
-  uint32_t* n_tree = g->d_err + 9;
-  hipLaunchKernelGGL(k_tree_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->region,
-                     g->n, g->tree_min, g->blocks, g->rec, g->rows, n_long, n_tree);
-  hipLaunchKernelGGL(k_tree_long, dim3(1024), dim3(kThreads), 0, s, g->off, g->region,
-                     g->tree_min, g->blocks, g->rec, g->rows, n_long);
   return hipGetLastError();
 }
 
