@@ -67,7 +67,8 @@ __device__ __forceinline__ void write_record(Block* rec, uint64_t u, uint64_t W,
 
 // Short rows: one thread accumulates its row into its leaf blocks and writes
 // its node line. Long rows are queued for a block each. Rows with a tree are
-// counted (one atomic per wave).
+// counted when n_tree_rows is given (one atomic per wave; the count depends
+// only on the degrees and the threshold, so rebuilds skip it).
 __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
                                const uint32_t* __restrict__ w, const uint64_t* __restrict__ region,
                                uint32_t n, uint32_t tree_min, uint64_t cap, Block* __restrict__ blk,
@@ -114,8 +115,10 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
     }
     rec[u].key[0] = acc;
   }
-  trees = wave_sum_u64(trees);
-  if (__lane_id() == 0 && trees) atomicAdd(n_tree_rows, static_cast<uint32_t>(trees));
+  if (n_tree_rows) {
+    trees = wave_sum_u64(trees);
+    if (__lane_id() == 0 && trees) atomicAdd(n_tree_rows, static_cast<uint32_t>(trees));
+  }
 }
 
 // Puts prefix P = P[j] of a row with a tree (d edges, L levels, T region tree
@@ -316,11 +319,11 @@ hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s) {
                          reinterpret_cast<uint64_t*>(g->d_err + 2), s);
 }
 
-hipError_t launch_leaves(fppr_graph* g, hipStream_t s) {
+hipError_t launch_leaves(fppr_graph* g, hipStream_t s, bool count_trees) {
   uint32_t* n_long = g->d_err + 1;
   hipLaunchKernelGGL(k_leaves_short, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->col,
                      g->w, g->region, g->n, g->tree_min, g->n_blocks, g->blocks, g->rec, g->rows,
-                     n_long, g->d_err + 9, g->d_err);
+                     n_long, count_trees ? g->d_err + 9 : nullptr, g->d_err);
   hipLaunchKernelGGL(k_leaves_long, dim3(2048), dim3(kThreads), 0, s, g->off, g->col, g->w,
                      g->region, g->tree_min, g->blocks, g->rec, g->rows, n_long);
   return hipGetLastError();

@@ -122,7 +122,7 @@ hipError_t zero_ctl(fppr_graph* g, hipStream_t s) {
 hipError_t derive(fppr_graph* g, hipStream_t s) {
   hipError_t e;
   if ((e = launch_region_sizes(g, s)) != hipSuccess) return e;
-  return launch_leaves(g, s);
+  return launch_leaves(g, s, false);  // the tree-row count is unchanged
 }
 
 uint32_t log2_exact(uint32_t v) {
@@ -316,7 +316,7 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   }
   g->n_blocks = c.blocks;
   FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
-  FPPR_TRY(launch_leaves(g, s), "leaf blocks");
+  FPPR_TRY(launch_leaves(g, s, true), "leaf blocks");
   FPPR_TRY(read_ctl(g, s, &c), "read build status");
   if (c.err) {
     std::string msg = "graph build failed:" + err_bits(c.err);
@@ -441,7 +441,7 @@ FPPR_API fppr_status fppr_graph_set_hub_threshold(fppr_graph* g, uint32_t hub_th
     if ((e = dmalloc(&g->blocks, c.blocks, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(blocks)");
     g->n_blocks = c.blocks;
   }
-  if ((e = launch_leaves(g, s)) != hipSuccess) return hip_fail(e, "leaf blocks");
+  if ((e = launch_leaves(g, s, true)) != hipSuccess) return hip_fail(e, "leaf blocks");
   if ((e = read_ctl(g, s, &c)) != hipSuccess) return hip_fail(e, "read build status");
   if (c.err) return invalid("graph build failed:" + err_bits(c.err));
   g->n_tree = c.n_tree;

@@ -90,7 +90,7 @@ hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s);
 // at d_err[10..11]
 hipError_t launch_split_nodes(fppr_graph* g, hipStream_t s);
 // prefixes and destinations into leaf blocks, node records
-hipError_t launch_leaves(fppr_graph* g, hipStream_t s);
+hipError_t launch_leaves(fppr_graph* g, hipStream_t s, bool count_trees);
 // exclusive scan of u32 input to u64 output; writes the total to *total_dev
 hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* blocks,
                            uint64_t* total_dev, hipStream_t s);
