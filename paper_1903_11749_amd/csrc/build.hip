@@ -80,12 +80,23 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
     const uint64_t a = off[u];
     const uint64_t d = off[u + 1] - a;
     const uint64_t r0 = region[u];
+    const bool fits = d <= kMaxDeg && r0 + region_blocks(d, tree_min) <= cap;
+    // long rows to the queue: one atomic per wave, each lane at its rank
+    const bool long_row = fits && d > kShortRow;
+    const uint64_t lm = __ballot(long_row);
+    if (lm) {
+      const int leader = __builtin_ctzll(lm);
+      uint32_t base = 0;
+      if (static_cast<int>(__lane_id()) == leader) base = atomicAdd(n_rows, static_cast<uint32_t>(__popcll(lm)));
+      base = static_cast<uint32_t>(__shfl(static_cast<int>(base), leader, 64));
+      if (long_row) rows[base + mask_rank(lm)] = static_cast<uint32_t>(u);
+    }
     if (d > kMaxDeg) {
       atomicOr(err, kErrDegree);
       continue;
     }
     trees += d > tree_min ? 1u : 0u;
-    if (r0 + region_blocks(d, tree_min) > cap) {
+    if (!fits) {
       atomicOr(err, kErrCapacity);
       continue;
     }
@@ -93,10 +104,7 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
       write_record(rec, u, 0, r0, 0);
       continue;
     }
-    if (d > kShortRow) {
-      rows[atomicAdd(n_rows, 1u)] = static_cast<uint32_t>(u);
-      continue;
-    }
+    if (long_row) continue;
     Block* leaves = blk + r0 + tree_nodes(d, tree_min);
     // a row this short that has a tree has only its top level (at most 8
     // keys, the leaf blocks' last prefixes): it goes into the node line here
