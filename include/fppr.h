@@ -85,19 +85,34 @@ typedef struct {
                                   fppr_graph_destroy */
 } fppr_csr;
 
+/* Graph layouts (fppr_graph_opts.layout). Both give identical results. The
+ * narrow layout reads fewer lines per weighted pick but compares twice the
+ * keys per line: it pays when the graph's lines mostly miss the caches. */
+#define FPPR_LAYOUT_AUTO 0u   /* narrow when it fits (max out-degree x max weight
+                                 < 2^32) and the graph's lines take 1 GiB or
+                                 more ((n + m / 8) x 128 bytes), else wide */
+#define FPPR_LAYOUT_WIDE 1u   /* always wide */
+#define FPPR_LAYOUT_NARROW 2u /* narrow; INVALID_ARGUMENT when it does not fit */
+
 typedef struct {
   /* Rows with more than hub_threshold out-edges (the large nodes of Sec. 4.1)
    * carry a prefix tree, the integer counterpart of the alias tree
-   * (Algorithm 3, Lemma 1): the row is cut into blocks of 8 edges whose
-   * running totals form the next level, 16 keys to a 128-byte node,
-   * recursively; the top level (at most 14 keys) sits in the node's own
-   * 128-byte line, so a pick reads the node line, one node per level below
-   * the top, and one block of 8 edges. It returns exactly
-   * the edge a flat search returns, so the threshold never changes results.
-   * 0 selects 8 (the fastest on the graphs measured); values below 8 act as
-   * 8; UINT32_MAX disables trees (rows of more than 8 edges are then
-   * binary-searched over their 8-edge blocks). */
+   * (Algorithm 3, Lemma 1): the row is cut into blocks of E edges whose
+   * running totals form the next level, F keys to a 128-byte node,
+   * recursively; the top level sits in the node's own 128-byte line, so a
+   * pick reads the node line, one node per level below the top, and one
+   * block of E edges. Wide layout (64-bit prefixes): E = 8, F = 16, up to 14
+   * top keys. Narrow layout (32-bit prefixes, for graphs whose row totals
+   * fit in 32 bits): E = 16, F = 32, up to 28 top keys. A pick returns
+   * exactly the edge a flat search returns, so neither the threshold nor the
+   * layout changes results. 0 selects 8 (the fastest on the graphs
+   * measured); values below 8 act as 8; UINT32_MAX disables trees (rows of
+   * more than E edges are then binary-searched over their blocks). */
   uint32_t hub_threshold;
+  /* FPPR_LAYOUT_AUTO, _WIDE or _NARROW. A narrow graph keeps its layout:
+   * a rebuild whose weights push a row total past 2^32 - 1 fails its check
+   * (fppr_graph_check) and the graph must be created again. */
+  uint32_t layout;
 } fppr_graph_opts;
 
 /* Creates the device graph: validates the CSR (device-side; INVALID_ARGUMENT
@@ -132,6 +147,9 @@ FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream);
  * (0 without a pool), device_bytes = bytes the library allocated. */
 FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t* m,
                                      uint32_t* n_hubs, uint64_t* n_small, uint64_t* device_bytes);
+/* The layout chosen at creation (host output): FPPR_LAYOUT_WIDE or
+ * FPPR_LAYOUT_NARROW. */
+FPPR_API fppr_status fppr_graph_layout(const fppr_graph* g, uint32_t* layout);
 
 typedef struct {
   uint32_t S;     /* small nodes: 1 <= out-degree <= S (S >= 1) */

@@ -150,9 +150,9 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
   e = launch_zero_u64(reinterpret_cast<uint64_t*>(b->ctl), kCtlBytes / 8, s);
   if (e != hipSuccess) return hip_fail(e, "zero control words");
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
-  e = launch_walk(b->table, static_cast<uint32_t>(b->host_table.size()), b->total, b->ctl, stats,
-                  b->opts.blocks_per_cu, s,
-                  same_graph_table(b->host_table.data(), static_cast<uint32_t>(b->host_table.size())));
+  const uint32_t nt = static_cast<uint32_t>(b->host_table.size());
+  e = launch_walk(b->table, nt, b->total, b->ctl, stats, b->opts.blocks_per_cu, s,
+                  table_layout(b->host_table.data(), nt), same_graph_table(b->host_table.data(), nt));
   if (e != hipSuccess) return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
@@ -237,7 +237,7 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
                                          first, 0, walks)
                              : make_desc(it.graph, &it.params, it.sources, item_sources(it), b->endpoints[k],
                                          first, 0, walks);
-    if (b->split[k]) D.flags = kDescEpBySource;
+    if (b->split[k]) D.flags |= kDescEpBySource;
     b->host_table.push_back(D);
     first += (walks + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
   }

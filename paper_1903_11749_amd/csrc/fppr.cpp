@@ -79,6 +79,7 @@ std::string err_bits(uint32_t e) {
   if (e & kErrWeight) s += " weight == 0;";
   if (e & kErrDegree) s += " a row has 2^27 or more edges;";
   if (e & kErrCapacity) s += " pool table overflow (graph changed shape);";
+  if (e & kErrNarrow) s += " a row's total weight exceeds 2^32 - 1 in a graph created with 32-bit prefixes (recreate it);";
   return s;
 }
 
@@ -95,6 +96,7 @@ struct Ctl {
   uint64_t small;
   uint32_t n_tree;
   uint64_t live;
+  uint32_t max_deg, max_w;
 };
 
 hipError_t read_ctl(const fppr_graph* g, hipStream_t s, Ctl* c) {
@@ -109,6 +111,8 @@ hipError_t read_ctl(const fppr_graph* g, hipStream_t s, Ctl* c) {
   std::memcpy(&c->small, raw + 6, 8);
   c->n_tree = raw[9];
   std::memcpy(&c->live, raw + 10, 8);
+  c->max_deg = raw[12];
+  c->max_w = raw[13];
   return hipSuccess;
 }
 
@@ -173,6 +177,7 @@ WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* so
   D.T = fppr_alpha_threshold(p->alpha);
   D.tree_min = g->tree_min;
   D.K_log2 = stitch ? g->K_log2 : 0;
+  D.flags = g->narrow ? kDescNarrow : 0u;
   return D;
 }
 
@@ -242,6 +247,9 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   uint32_t H = kLeafEdges;
   if (opts && opts->hub_threshold) H = opts->hub_threshold;
   if (H < kLeafEdges) H = kLeafEdges;
+  const uint32_t layout = opts ? opts->layout : FPPR_LAYOUT_AUTO;
+  if (layout != FPPR_LAYOUT_AUTO && layout != FPPR_LAYOUT_WIDE && layout != FPPR_LAYOUT_NARROW)
+    return invalid("layout must be AUTO, WIDE or NARROW");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   fppr_graph* g = new fppr_graph();
@@ -294,7 +302,7 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   FPPR_TRY(dmalloc(&g->d_err, 16, acc), "hipMalloc(ctl)");
 
   FPPR_TRY(zero_ctl(g, s), "zero control words");
-  FPPR_TRY(launch_validate(g, s), "validate");
+  FPPR_TRY(launch_validate(g, s, true), "validate");
   Ctl c{};
   FPPR_TRY(read_ctl(g, s, &c), "read validation");
   if (c.err) {
@@ -302,6 +310,16 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     free_graph(g);
     return invalid(msg);
   }
+  // narrow layout: every row total surely fits in 32 bits, and (by default)
+  // the graph's lines are well beyond the caches, where fewer lines per pick
+  // outweigh the extra compares per line
+  const bool fits = static_cast<uint64_t>(c.max_deg) * c.max_w <= 0xFFFFFFFFull;
+  if (layout == FPPR_LAYOUT_NARROW && !fits) {
+    free_graph(g);
+    return invalid("layout NARROW needs max out-degree x max weight < 2^32");
+  }
+  const uint64_t line_bytes = (n + m / 8) * sizeof(Block);
+  g->narrow = layout == FPPR_LAYOUT_NARROW || (layout == FPPR_LAYOUT_AUTO && fits && line_bytes >= (1ull << 30));
   FPPR_TRY(dmalloc(&g->live, n, acc), "hipMalloc(live nodes)");
   FPPR_TRY(dmalloc(&g->dang, n, acc), "hipMalloc(dangling nodes)");
   FPPR_TRY(launch_split_nodes(g, s), "split nodes");
@@ -344,6 +362,12 @@ FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t*
   if (n_hubs) *n_hubs = g->n_tree;
   if (n_small) *n_small = g->has_pool ? g->n_small : 0;
   if (device_bytes) *device_bytes = g->device_bytes;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_graph_layout(const fppr_graph* g, uint32_t* layout) {
+  if (!g || !layout) return invalid("graph or layout is NULL");
+  *layout = g->narrow ? FPPR_LAYOUT_NARROW : FPPR_LAYOUT_WIDE;
   return FPPR_OK;
 }
 
@@ -415,7 +439,7 @@ FPPR_API fppr_status fppr_graph_rebuild(fppr_graph* g, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if ((e = zero_ctl(g, s)) != hipSuccess) return hip_fail(e, "zero control words");
-  if ((e = launch_validate(g, s)) != hipSuccess) return hip_fail(e, "validate");
+  if ((e = launch_validate(g, s, false)) != hipSuccess) return hip_fail(e, "validate");
   if ((e = derive(g, s)) != hipSuccess) return hip_fail(e, "derive");
   if (g->has_pool) return pool_kernels(g, s);
   return FPPR_OK;
@@ -561,7 +585,7 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
     const bool split = !sources && !blocked && split_dangling(g);
     WalkDesc D = split ? make_desc(g, p, g->live, g->n_live, ep_base, 0, 0, g->n_live * p->R)
                        : make_desc(g, p, sources, n_sources, ep_base, 0, r0 * p->R, nb * p->R);
-    if (split) D.flags = kDescEpBySource;
+    if (split) D.flags |= kDescEpBySource;
     if ((e = launch_set_desc(D, desc, s)) != hipSuccess) return hip_fail(e, "walk descriptor");
     const uint64_t total = (D.count + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
     if (split) {  // the side stream starts after everything queued on `s` so far
@@ -569,7 +593,8 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
       if ((e = hipEventRecord(g->fork_ev, s)) != hipSuccess) return hip_fail(e, "fork event");
       if ((e = hipStreamWaitEvent(g->side, g->fork_ev, 0)) != hipSuccess) return hip_fail(e, "fork wait");
     }
-    if (total && (e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
+    if (total && (e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s, table_layout(&D, 1))) !=
+                     hipSuccess)
       return hip_fail(e, "walk kernel");
     if (prof && !blocked && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
     if (split) {

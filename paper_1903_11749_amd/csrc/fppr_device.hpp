@@ -13,8 +13,9 @@ namespace fppr {
 //   key[0]: total weight W of the row (plain table), or the address of the
 //           node's first pool entry (stitched table, small nodes)
 //   key[1]: (first block of the row's region << 28) | flags
-//   key[2..15]: the top level of the row's prefix tree (up to 14 keys, ~0
-//           past its end and in rows without a tree)
+//   bytes 16..127: the top level of the row's prefix tree (~0 past its end
+//           and in rows without a tree): up to 14 u64 keys (wide layout) or
+//           up to 28 u32 keys (narrow layout)
 // flags: bits 0..26 out-degree, bit 27 = small node served by the pool.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRegionShift = 28;
@@ -28,24 +29,37 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 // ---------------------------------------------------------------------------
 // Row regions. Every row owns a run of 128-byte blocks (one memory line):
 //   [prefix-tree nodes below the top level, top first][leaf blocks]
-// Leaf block b holds edges 8b .. 8b+7 of the row: their inclusive weight
-// prefixes P (8 x u64) and destination ids (8 x u32); slots past the row's
-// end hold P = ~0. A pick that knows its leaf block reads one line.
+// A graph has one of two layouts, fixed when it is created:
+//   wide:   leaf block b holds edges 8b .. 8b+7 of the row: their inclusive
+//           weight prefixes P (8 x u64) and destination ids (8 x u32); a
+//           tree node holds 16 u64 keys; the node line up to 14 top keys.
+//   narrow: every row's total weight fits in 32 bits (checked at creation
+//           as max out-degree x max weight < 2^32, and by every rebuild), so
+//           prefixes are u32: leaf block b holds edges 16b .. 16b+15 (16 x
+//           u32 prefixes, then 16 x u32 ids); a tree node holds 32 u32 keys;
+//           the node line up to 28 top keys. Twice the fan-out per line.
+// Slots past the row's end hold P = ~0. A pick that knows its leaf block
+// reads one line.
 // Prefix tree (integer form of the alias tree, Sec. 4.1 and Algorithm 3: the
 // row is cut into groups whose total weights form the next level,
 // recursively, and a pick walks from the top down to one group): rows with
 // more than the tree threshold of edges carry it. Level 1 has one key per
-// leaf block, level l one key per 16 keys of level l-1; key k of level l is
-// P[min((k+1) * 8 * 16^(l-1), d) - 1]. The top level L is the first with at
-// most 14 keys and sits in the node line; every level below it is stored as
-// nodes of 16 keys (128 bytes; unused keys ~0). Taking the first key > X at
-// every level and then the first prefix > X in the leaf returns exactly the
-// edge a flat search over P returns.
+// leaf block, level l one key per F keys of level l-1 (F = 16 or 32 keys a
+// node); key k of level l is P[min((k+1) * E * F^(l-1), d) - 1] (E = 8 or 16
+// edges a leaf). The top level L is the first with at most 14 (28) keys and
+// sits in the node line; every level below it is stored as nodes of F keys
+// (128 bytes; unused keys ~0). Taking the first key > X at every level and
+// then the first prefix > X in the leaf returns exactly the edge a flat
+// search over P returns.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kLeafEdges = 8;
+constexpr uint32_t kLeafEdges = 8;        // wide layout
 constexpr uint32_t kNodeKeys = 16;
-constexpr uint32_t kTopKeys = 14;  // tree keys in a node line
-constexpr uint32_t kTopKey0 = 2;   // their first word
+constexpr uint32_t kTopKeys = 14;
+constexpr uint32_t kTopKey0 = 2;          // first u64 word of the top keys
+constexpr uint32_t kNarrowLeafEdges = 16; // narrow layout
+constexpr uint32_t kNarrowNodeKeys = 32;
+constexpr uint32_t kNarrowTopKeys = 28;
+constexpr uint32_t kNarrowTopKey0 = 4;    // first u32 word of the top keys
 
 struct LeafBlock {
   uint64_t p[kLeafEdges];  // inclusive prefixes (~0 past the row's end)
@@ -53,41 +67,48 @@ struct LeafBlock {
   uint32_t pad[kLeafEdges];
 };
 union alignas(128) Block {
-  uint64_t key[kNodeKeys];  // tree node or node line
-  LeafBlock lf;             // leaf block
+  uint64_t key[kNodeKeys];  // wide tree node or node line
+  LeafBlock lf;             // wide leaf block
+  uint32_t w32[32];         // narrow: tree node keys, or leaf prefixes [0, 16) and ids [16, 32)
 };
 static_assert(sizeof(Block) == 128, "one memory line per block");
 
-__host__ __device__ __forceinline__ uint64_t leaf_blocks(uint64_t d) {
-  return (d + kLeafEdges - 1) / kLeafEdges;
+// log2 of the edges per leaf block, log2 of the keys per tree node, and the
+// top keys a node line holds, by layout
+__host__ __device__ __forceinline__ uint32_t leaf_shift(bool nar) { return nar ? 4u : 3u; }
+__host__ __device__ __forceinline__ uint32_t node_shift(bool nar) { return nar ? 5u : 4u; }
+__host__ __device__ __forceinline__ uint32_t top_keys(bool nar) { return nar ? kNarrowTopKeys : kTopKeys; }
+
+__host__ __device__ __forceinline__ uint64_t leaf_blocks(uint64_t d, bool nar) {
+  return (d + (1ull << leaf_shift(nar)) - 1) >> leaf_shift(nar);
 }
-// levels of the tree of a row with d edges (d > 8), the top level included:
-// level 1 has ceil(d / 8) keys, each level 16 times fewer (rounded up)
-__host__ __device__ __forceinline__ uint32_t tree_levels(uint64_t d) {
+// levels of the tree of a row with d edges, the top level included: level 1
+// has one key per leaf block, each level F times fewer (rounded up)
+__host__ __device__ __forceinline__ uint32_t tree_levels(uint64_t d, bool nar) {
   uint32_t L = 1;
-  uint64_t keys = leaf_blocks(d);
-  while (keys > kTopKeys) {
+  uint64_t keys = leaf_blocks(d, nar);
+  while (keys > top_keys(nar)) {
     ++L;
-    keys = (keys + kNodeKeys - 1) / kNodeKeys;
+    keys = (keys + (1ull << node_shift(nar)) - 1) >> node_shift(nar);
   }
   return L;
 }
-// nodes of level l >= 1: ceil(d / (8 * 16^l))
-__host__ __device__ __forceinline__ uint64_t tree_level_nodes(uint64_t d, uint32_t l) {
-  const uint32_t sh = 3 + 4 * l;
+// nodes of level l >= 1: ceil(d / (E * F^l))
+__host__ __device__ __forceinline__ uint64_t tree_level_nodes(uint64_t d, uint32_t l, bool nar) {
+  const uint32_t sh = leaf_shift(nar) + node_shift(nar) * l;
   return (d + (1ull << sh) - 1) >> sh;
 }
 // tree nodes a row keeps in its region: every level below the top (0 when
 // it has no tree, or its tree is the top level alone)
-__host__ __device__ __forceinline__ uint64_t tree_nodes(uint64_t d, uint32_t tree_min) {
+__host__ __device__ __forceinline__ uint64_t tree_nodes(uint64_t d, uint32_t tree_min, bool nar) {
   if (d <= tree_min) return 0;
-  const uint32_t L = tree_levels(d);
+  const uint32_t L = tree_levels(d, nar);
   uint64_t t = 0;
-  for (uint32_t l = 1; l < L; ++l) t += tree_level_nodes(d, l);
+  for (uint32_t l = 1; l < L; ++l) t += tree_level_nodes(d, l, nar);
   return t;
 }
-__host__ __device__ __forceinline__ uint64_t region_blocks(uint64_t d, uint32_t tree_min) {
-  return d ? tree_nodes(d, tree_min) + leaf_blocks(d) : 0;
+__host__ __device__ __forceinline__ uint64_t region_blocks(uint64_t d, uint32_t tree_min, bool nar) {
+  return d ? tree_nodes(d, tree_min, nar) + leaf_blocks(d, nar) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -126,6 +147,7 @@ struct GraphView {
   const Block* __restrict__ rec;     // node lines (plain table)
   const Block* __restrict__ blocks;  // row regions
   uint32_t tree_min;                 // rows with deg > tree_min (>= 8) have a tree
+  uint32_t narrow;                   // 1: narrow layout (u32 prefixes)
 };
 
 __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t d) {

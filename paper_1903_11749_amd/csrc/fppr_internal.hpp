@@ -19,6 +19,7 @@ enum : uint32_t {
   kErrWeight = 4u,
   kErrDegree = 16u,
   kErrCapacity = 32u,
+  kErrNarrow = 64u,  // a row total above 2^32 - 1 in a graph with the narrow layout
 };
 
 }  // namespace fppr
@@ -38,6 +39,7 @@ struct fppr_graph {
   uint64_t n_blocks = 0;
   uint64_t* region = nullptr;       // [n] first block of each row's region
   uint32_t tree_min = 8;            // rows with more edges carry a prefix tree
+  bool narrow = false;              // narrow layout: u32 prefixes (fixed at creation)
   uint32_t n_tree = 0;              // rows with a tree
   // scratch (kept for rebuilds)
   uint32_t* flag = nullptr;         // [n]   per-node u32 input of scans
@@ -83,7 +85,7 @@ fppr_status check_outputs(const fppr_params* p, const fppr_out* out);
 void drop_pool(fppr_graph* g);
 
 // build.hip
-hipError_t launch_validate(const fppr_graph* g, hipStream_t s);
+hipError_t launch_validate(const fppr_graph* g, hipStream_t s, bool maxima);  // maxima: max degree and weight (layout choice)
 // region sizes + scan -> g->region, total blocks at d_err[2..3]
 hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s);
 // nodes with / without out-edges -> g->live, g->dang; the count of the former
@@ -122,10 +124,16 @@ struct WalkDesc {
 // the endpoint of walk i of source s goes to endpoints[s * R + i] (a run over
 // a list of some of the nodes that fills an all-nodes endpoint buffer)
 constexpr uint32_t kDescEpBySource = 1;
+// the graph has the narrow layout (u32 prefixes, 16-edge leaves, 32-key nodes)
+constexpr uint32_t kDescNarrow = 2;
 // lane_keys: the per-lane-key form of the kernel (for tables whose
 // descriptors all read one graph; see same_graph_table)
+// layout: table_layout of the table's host copy
 hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
-                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, bool lane_keys = false);
+                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, int layout,
+                       bool lane_keys = false);
+// 0 when every descriptor's graph is wide, 1 when every one is narrow, 2 mixed
+int table_layout(const WalkDesc* h, uint32_t ndesc);
 // true when a table (host copy) has more than one descriptor and all of them
 // read the same graph arrays
 bool same_graph_table(const WalkDesc* h, uint32_t ndesc);

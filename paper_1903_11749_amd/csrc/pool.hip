@@ -71,8 +71,14 @@ __device__ __forceinline__ uint64_t pair_swap64(uint64_t x) {
   return static_cast<uint64_t>(pair_swap(static_cast<uint32_t>(x))) |
          (static_cast<uint64_t>(pair_swap(static_cast<uint32_t>(x >> 32))) << 32);
 }
-// keys of q (two u64) that are <= X
-__device__ __forceinline__ uint32_t count2(uint4 q, uint64_t X) {
+// keys of q that are <= X: two u64 keys (wide layout) or four u32 keys
+// (narrow layout, where X < 2^32)
+template <bool kNar>
+__device__ __forceinline__ uint32_t count_q(uint4 q, uint64_t X) {
+  if (kNar) {
+    const uint32_t x = static_cast<uint32_t>(X);
+    return (q.x <= x ? 1u : 0u) + (q.y <= x ? 1u : 0u) + (q.z <= x ? 1u : 0u) + (q.w <= x ? 1u : 0u);
+  }
   const uint64_t k0 = (static_cast<uint64_t>(q.y) << 32) | q.x;
   const uint64_t k1 = (static_cast<uint64_t>(q.w) << 32) | q.z;
   return (k0 <= X ? 1u : 0u) + (k1 <= X ? 1u : 0u);
@@ -83,7 +89,8 @@ __device__ __forceinline__ uint32_t count2(uint4 q, uint64_t X) {
 // lane bytes 0..63, the odd lane bytes 64..127), adding the pair's compare
 // counts with one DPP swap, so that no lane reads more than 64 bytes of a
 // random line. The 64 slots of a small node sit in consecutive pairs, so
-// their first steps read the same lines.
+// their first steps read the same lines. kNar: the graph's layout.
+template <bool kNar>
 __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* __restrict__ small_nodes,
                                                    uint64_t n_small, uint32_t K_log2, uint32_t L,
                                                    uint32_t T, uint32_t key0, uint32_t key1,
@@ -111,37 +118,42 @@ __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* 
       const uint64_t region = od >> kRegionShift;
       uint64_t leaf;
       if (deg > g.tree_min) {
-        uint32_t c = half ? count2(q0, X) + count2(q1, X) + count2(q2, X) + count2(q3, X)
-                          : count2(q1, X) + count2(q2, X) + count2(q3, X);
+        uint32_t c = half ? count_q<kNar>(q0, X) + count_q<kNar>(q1, X) + count_q<kNar>(q2, X) +
+                                count_q<kNar>(q3, X)
+                          : count_q<kNar>(q1, X) + count_q<kNar>(q2, X) + count_q<kNar>(q3, X);
         c += pair_swap(c);
         uint64_t base = 0, b = c;
-        for (uint32_t l = tree_levels(deg) - 1; l >= 1; --l) {
+        for (uint32_t l = tree_levels(deg, kNar) - 1; l >= 1; --l) {
           const uint4* nd = reinterpret_cast<const uint4*>(g.blocks + region + base + b) + half * 4;
-          uint32_t cc = count2(nd[0], X) + count2(nd[1], X) + count2(nd[2], X) + count2(nd[3], X);
+          uint32_t cc = count_q<kNar>(nd[0], X) + count_q<kNar>(nd[1], X) + count_q<kNar>(nd[2], X) +
+                        count_q<kNar>(nd[3], X);
           cc += pair_swap(cc);
-          base += tree_level_nodes(deg, l);
-          b = b * kNodeKeys + cc;
+          base += tree_level_nodes(deg, l, kNar);
+          b = (b << node_shift(kNar)) + cc;
         }
         leaf = region + base + b;
       } else {
-        uint64_t lo = 0, hi = leaf_blocks(deg) - 1;
+        uint64_t lo = 0, hi = leaf_blocks(deg, kNar) - 1;
         while (lo < hi) {
           const uint64_t mid = lo + ((hi - lo) >> 1);
-          if (g.blocks[region + mid].lf.p[kLeafEdges - 1] > X) hi = mid; else lo = mid + 1;
+          const uint64_t last = kNar ? g.blocks[region + mid].w32[kNarrowLeafEdges - 1]
+                                     : g.blocks[region + mid].lf.p[kLeafEdges - 1];
+          if (last > X) hi = mid; else lo = mid + 1;
         }
         leaf = region + lo;
       }
-      // leaf block: the even lane counts the 8 prefixes, the odd lane holds
-      // the 8 destinations
+      // leaf block: the even lane counts the prefixes (8 or 16), the odd
+      // lane holds the destinations
       const uint4* lf = reinterpret_cast<const uint4*>(g.blocks + leaf) + half * 4;
       uint32_t e = 0, dst = 0;
-      const uint4 l0 = lf[0], l1 = lf[1];
+      const uint4 l0 = lf[0], l1 = lf[1], l2 = lf[2], l3 = lf[3];
       if (half == 0) {
-        e = count2(l0, X) + count2(l1, X) + count2(lf[2], X) + count2(lf[3], X);
+        e = count_q<kNar>(l0, X) + count_q<kNar>(l1, X) + count_q<kNar>(l2, X) + count_q<kNar>(l3, X);
       }
       e += pair_swap(e);
       if (half) {
-        const uint4 w = e < 4 ? l0 : l1;
+        const uint32_t qi = e >> 2;
+        const uint4 w = qi == 0 ? l0 : (qi == 1 ? l1 : (qi == 2 ? l2 : l3));
         const uint32_t k = e & 3u;
         dst = k == 0 ? w.x : (k == 1 ? w.y : (k == 2 ? w.z : w.w));
       }
@@ -179,11 +191,16 @@ hipError_t launch_small_compact(fppr_graph* g, uint32_t /*S*/, hipStream_t s) {
 hipError_t launch_pool(fppr_graph* g, hipStream_t s) {
   const uint64_t total = g->n_small << g->K_log2;
   if (total == 0) return hipSuccess;
-  GraphView gv{g->rec, g->blocks, g->tree_min};
+  GraphView gv{g->rec, g->blocks, g->tree_min, g->narrow ? 1u : 0u};
   const uint64_t seed = g->pool_opts.seed;
-  hipLaunchKernelGGL(k_pool, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
-                     g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,
-                     static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->pool);
+  if (g->narrow)
+    hipLaunchKernelGGL(k_pool<true>, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
+                       g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,
+                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->pool);
+  else
+    hipLaunchKernelGGL(k_pool<false>, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
+                       g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,
+                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->pool);
   return hipGetLastError();
 }
 

@@ -105,12 +105,26 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t x) {
 }
 
 __device__ __forceinline__ uint32_t sread(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// keys of q that are <= X: two u64 keys (wide layout) or four u32 keys
+// (narrow layout, where X < 2^32); `nar` is wave-uniform
+__device__ __forceinline__ uint32_t count_q(uint4 q, uint64_t X, bool nar) {
+  if (nar) {
+    const uint32_t x = static_cast<uint32_t>(X);
+    return (q.x <= x ? 1u : 0u) + (q.y <= x ? 1u : 0u) + (q.z <= x ? 1u : 0u) + (q.w <= x ? 1u : 0u);
+  }
+  const uint64_t k0 = (static_cast<uint64_t>(q.y) << 32) | q.x;
+  const uint64_t k1 = (static_cast<uint64_t>(q.w) << 32) | q.z;
+  return (k0 <= X ? 1u : 0u) + (k1 <= X ? 1u : 0u);
+}
 __device__ __forceinline__ uint64_t sread64(uint64_t x) {
   return static_cast<uint64_t>(sread(static_cast<uint32_t>(x))) |
          (static_cast<uint64_t>(sread(static_cast<uint32_t>(x >> 32))) << 32);
 }
 
-template <bool kStats, bool kLaneKeys>
+// kLayout: 0 = every descriptor's graph is wide, 1 = every one is narrow,
+// 2 = mixed (read per descriptor).
+template <bool kStats, bool kLaneKeys, int kLayout>
 __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   __shared__ uint64_t sh_line[kThreads / 64][64];
   __shared__ uint64_t sh_x[kThreads / 64][64];
@@ -253,10 +267,13 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
     // Pool entries and probes are one small load per lane. Node lines, tree
     // nodes and leaf blocks are whole 128-byte lines loaded by lane pairs.
     const uint32_t ph = L.ph;
+    // the graph's layout (wave-uniform; a constant unless the table mixes layouts)
+    const bool nar = kLayout == 2 ? (dflags & kDescNarrow) != 0 : kLayout == 1;
     const bool rec_line = (ph == kSrcRec || ph == kRec);
     uint64_t v0 = 0, v1 = 0;
     if (ph == kBsearch) {
-      v0 = blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)].lf.p[kLeafEdges - 1];
+      const Block& lb = blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)];
+      v0 = nar ? lb.w32[kNarrowLeafEdges - 1] : lb.lf.p[kLeafEdges - 1];
     } else if (ph == kPool) {
       v0 = *reinterpret_cast<const uint64_t*>(L.X);
     }
@@ -314,18 +331,26 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         uint32_t cnt = 0;
         if (!leaf || half == 0) {
 #pragma unroll
-          for (uint32_t k = 0; k < 4; ++k) {
-            const uint64_t k0 = (static_cast<uint64_t>(q[r][k].y) << 32) | q[r][k].x;
-            const uint64_t k1 = (static_cast<uint64_t>(q[r][k].w) << 32) | q[r][k].z;
-            cnt += (k0 <= xo ? 1u : 0u) + (k1 <= xo ? 1u : 0u);
-          }
+          for (uint32_t k = 0; k < 4; ++k) cnt += count_q(q[r][k], xo, nar);
         }
         cnt += swap_pair(cnt);  // both lanes of the pair hold the total
-        if (leaf) {  // destination j = cnt: word j of the odd lane's 8 ids
-          if (half == 1) {
-            const uint4 w = (cnt < 4) ? q[r][0] : q[r][1];
-            const uint32_t jw = cnt & 3u;
-            sh_res[wv][owner] = jw == 0 ? w.x : (jw == 1 ? w.y : (jw == 2 ? w.z : w.w));
+        if (leaf) {  // destination j = cnt: word j of the odd lane's 8 (16) ids
+          if (half == 1) {  // selects of values (an indexed pick would put q in scratch)
+            const uint32_t jw = cnt & 3u, qi = cnt >> 2;
+            if (!nar) {
+              const uint4 w = qi == 0 ? q[r][0] : q[r][1];
+              sh_res[wv][owner] = jw == 0 ? w.x : (jw == 1 ? w.y : (jw == 2 ? w.z : w.w));
+            } else {
+              uint32_t wq[4];
+#pragma unroll
+              for (uint32_t t = 0; t < 4; ++t) {
+                const uint4 v = q[r][t];
+                wq[t] = jw == 0 ? v.x : (jw == 1 ? v.y : (jw == 2 ? v.z : v.w));
+              }
+              const uint32_t lo2 = (qi & 1u) ? wq[1] : wq[0];
+              const uint32_t hi2 = (qi & 1u) ? wq[3] : wq[2];
+              sh_res[wv][owner] = (qi & 2u) ? hi2 : lo2;
+            }
           }
         } else if (half == 0) {
           sh_res[wv][owner] = cnt;
@@ -352,8 +377,8 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
       bod = v1;
       begin = true;
     } else if (ph == kTree) {
-      L.hi += static_cast<uint32_t>(tree_level_nodes(L.deg, L.lvl));
-      L.lo = L.lo * kNodeKeys + line_res;
+      L.hi += static_cast<uint32_t>(tree_level_nodes(L.deg, L.lvl, nar));
+      L.lo = (L.lo << node_shift(nar)) + line_res;
       if (--L.lvl == 0) {  // leaves start right after the tree: block hi + lo
         L.lo += L.hi;
         L.hi = 0;
@@ -445,22 +470,17 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           // the leaf block), hi: first node of that level
           uint32_t c = 0;
 #pragma unroll
-          for (uint32_t k = 0; k < kTopKeys / 2; ++k) {
-            const uint4 v = sh_top[wv][lane][k];
-            const uint64_t k0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
-            const uint64_t k1 = (static_cast<uint64_t>(v.w) << 32) | v.z;
-            c += (k0 <= L.X ? 1u : 0u) + (k1 <= L.X ? 1u : 0u);
-          }
+          for (uint32_t k = 0; k < kTopKeys / 2; ++k) c += count_q(sh_top[wv][lane][k], L.X, nar);
           L.lo = c;
-          const uint32_t lv = tree_levels(dg);
+          const uint32_t lv = tree_levels(dg, nar);
           if (lv == 1) {
             L.ph = kLeaf;
           } else {
             L.lvl = lv - 1;
             L.ph = kTree;
           }
-        } else if (dg > kLeafEdges) {
-          L.hi = static_cast<uint32_t>(leaf_blocks(dg)) - 1;  // candidate leaf blocks [lo, hi]
+        } else if (dg > (1u << leaf_shift(nar))) {
+          L.hi = static_cast<uint32_t>(leaf_blocks(dg, nar)) - 1;  // candidate leaf blocks [lo, hi]
           L.ph = kBsearch;
         } else {
           L.ph = kLeaf;  // the one leaf block
@@ -592,14 +612,14 @@ __global__ void k_set_desc(WalkDesc d, WalkDesc* dst) {
   if (threadIdx.x == 0) *dst = d;
 }
 
-template <bool kStats, bool kLaneKeys>
+template <bool kStats, bool kLaneKeys, int kLayout>
 hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t s) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats, kLaneKeys>, kThreads, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats, kLaneKeys, kLayout>, kThreads, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   if (blocks_per_cu && static_cast<int>(blocks_per_cu) < per_cu) per_cu = static_cast<int>(blocks_per_cu);
@@ -607,7 +627,8 @@ hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t
   const uint64_t need = (t.total + kThreads - 1) / kThreads;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_walk<kStats, kLaneKeys>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0, s, t);
+  hipLaunchKernelGGL((k_walk<kStats, kLaneKeys, kLayout>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0,
+                     s, t);
   return hipGetLastError();
 }
 
@@ -661,12 +682,23 @@ hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s) {
 }
 
 hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
-                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, bool lane_keys) {
+                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, int layout, bool lane_keys) {
   if (total == 0 || ndesc == 0) return hipSuccess;
   WalkTable t{descs, ndesc, total, ctl, stats};
-  if (lane_keys)
-    return stats ? launch_walk_t<true, true>(t, blocks_per_cu, s) : launch_walk_t<false, true>(t, blocks_per_cu, s);
-  return stats ? launch_walk_t<true, false>(t, blocks_per_cu, s) : launch_walk_t<false, false>(t, blocks_per_cu, s);
+  const uint32_t b = blocks_per_cu;
+  if (lane_keys) {  // one graph, so one layout
+    if (layout == 1) return stats ? launch_walk_t<true, true, 1>(t, b, s) : launch_walk_t<false, true, 1>(t, b, s);
+    return stats ? launch_walk_t<true, true, 0>(t, b, s) : launch_walk_t<false, true, 0>(t, b, s);
+  }
+  if (layout == 0) return stats ? launch_walk_t<true, false, 0>(t, b, s) : launch_walk_t<false, false, 0>(t, b, s);
+  if (layout == 1) return stats ? launch_walk_t<true, false, 1>(t, b, s) : launch_walk_t<false, false, 1>(t, b, s);
+  return stats ? launch_walk_t<true, false, 2>(t, b, s) : launch_walk_t<false, false, 2>(t, b, s);
+}
+
+int table_layout(const WalkDesc* h, uint32_t ndesc) {
+  bool nar = false, wide = false;
+  for (uint32_t k = 0; k < ndesc; ++k) ((h[k].flags & kDescNarrow) ? nar : wide) = true;
+  return nar && wide ? 2 : (nar ? 1 : 0);
 }
 
 bool same_graph_table(const WalkDesc* h, uint32_t ndesc) {

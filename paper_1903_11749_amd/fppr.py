@@ -50,8 +50,13 @@ class fppr_csr(ctypes.Structure):
                 ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("mem", ctypes.c_int)]
 
 
+FPPR_LAYOUT_AUTO = 0
+FPPR_LAYOUT_WIDE = 1
+FPPR_LAYOUT_NARROW = 2
+
+
 class fppr_graph_opts(ctypes.Structure):
-    _fields_ = [("hub_threshold", ctypes.c_uint32)]
+    _fields_ = [("hub_threshold", ctypes.c_uint32), ("layout", ctypes.c_uint32)]
 
 
 class fppr_pool_opts(ctypes.Structure):
@@ -138,6 +143,7 @@ _SIGS = [
     ("fppr_graph_info", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_graph_layout", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_uint32)]),
     ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
     ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
     ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
@@ -225,7 +231,7 @@ class Graph:
     arrays: copied) or torch device tensors (borrowed: kept referenced here)."""
 
     def __init__(self, csr=None, hub_threshold: int = 0, stream=None, *, n=None,
-                 row_offsets=None, col=None, w=None):
+                 row_offsets=None, col=None, w=None, layout: int = FPPR_LAYOUT_AUTO):
         import torch
 
         if csr is not None:
@@ -251,7 +257,7 @@ class Graph:
             c.w = ww.ctypes.data if ww.size else None
             c.mem = FPPR_MEM_HOST
         self.m = int(c.m)
-        o = fppr_graph_opts(hub_threshold)
+        o = fppr_graph_opts(hub_threshold, layout)
         h = ctypes.c_void_p()
         _check(lib().fppr_graph_create(ctypes.byref(c), ctypes.byref(o), _stream_ptr(stream),
                                        ctypes.byref(h)))
@@ -272,6 +278,12 @@ class Graph:
         _check(lib().fppr_graph_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(hubs),
                                      ctypes.byref(small), ctypes.byref(by)))
         return dict(n=n.value, m=m.value, hubs=hubs.value, small=small.value, device_bytes=by.value)
+
+    def layout(self) -> int:
+        """FPPR_LAYOUT_WIDE or FPPR_LAYOUT_NARROW."""
+        v = ctypes.c_uint32()
+        _check(lib().fppr_graph_layout(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def build_pool(self, S: int, L: int, K: int, alpha: float, seed: int, stream=None):
         o = fppr_pool_opts(S, L, K, alpha, seed)

@@ -39,7 +39,7 @@ def u64(t):
 @pytest.fixture(scope="module")
 def items(fp):
     """Six items of uneven size: different graphs, alphas, walk budgets,
-    source subsets, plain and stitched."""
+    source subsets, plain and stitched, both layouts in one table."""
     specs = [
         (synth.chung_lu(3000, 30000, 2.1, 255, seed=2001), 0.1, 64, 11, 8, None, False),
         (synth.chung_lu(500, 4000, 2.5, 255, seed=2002), 0.2, 256, 12, 16, None, True),
@@ -51,8 +51,8 @@ def items(fp):
         (synth.chung_lu(64, 300, 2.1, 255, seed=2005), 0.1, 256, 15, 64, None, False),
     ]
     out = []
-    for g, alpha, R, seed, k, src, stitch in specs:
-        G = fp.Graph(g)
+    for i, (g, alpha, R, seed, k, src, stitch) in enumerate(specs):
+        G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW if i % 2 == 0 else fp.FPPR_LAYOUT_WIDE)
         if stitch:
             G.build_pool(S=16, L=3, K=32, alpha=alpha, seed=seed + 100)
         out.append(dict(csr=g, graph=G, alpha=alpha, R=R, seed=seed, topk=k, sources=src,

@@ -32,7 +32,7 @@ def fp():
 @pytest.fixture(scope="module")
 def world(fp):
     g = synth.chung_lu(30000, 400000, 2.2, 255, seed=2030)
-    G = fp.Graph(g)
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)  # the layout the large resident graph gets
     G.build_pool(S=32, L=3, K=64, alpha=0.15, seed=12)
     rng = np.random.default_rng(2031)
     queries = []

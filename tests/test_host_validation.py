@@ -35,6 +35,12 @@ def test_graph_create_refuses_bad_csr(fp):
     assert L.fppr_graph_create(ctypes.byref(c), None, None, ctypes.byref(out)) == fp.FPPR_INVALID_ARGUMENT
     assert "col" in last_error(fp)
     assert L.fppr_graph_create(None, None, None, ctypes.byref(out)) == fp.FPPR_INVALID_ARGUMENT
+    one = (ctypes.c_uint64 * 2)(0, 0)
+    c = fp.fppr_csr(1, 0, ctypes.cast(one, ctypes.c_void_p), None, None, fp.FPPR_MEM_HOST)
+    bad = fp.fppr_graph_opts(0, 5)
+    assert L.fppr_graph_create(ctypes.byref(c), ctypes.byref(bad), None, ctypes.byref(out)) == \
+        fp.FPPR_INVALID_ARGUMENT
+    assert "layout" in last_error(fp)
 
 
 def test_null_handles(fp):
@@ -47,6 +53,8 @@ def test_null_handles(fp):
     assert L.fppr_graph_set_hub_threshold(None, 8, None) == fp.FPPR_INVALID_ARGUMENT
     assert L.fppr_graph_build_pool(None, None, None) == fp.FPPR_INVALID_ARGUMENT
     assert L.fppr_graph_info(None, None, None, None, None, None) == fp.FPPR_INVALID_ARGUMENT
+    lay = ctypes.c_uint32()
+    assert L.fppr_graph_layout(None, ctypes.byref(lay)) == fp.FPPR_INVALID_ARGUMENT
     ws = ctypes.c_uint64()
     assert L.fppr_plan(None, None, 1, ctypes.byref(ws)) == fp.FPPR_INVALID_ARGUMENT
     assert L.fppr_run_check(None, None) == fp.FPPR_INVALID_ARGUMENT
