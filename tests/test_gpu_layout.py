@@ -113,3 +113,21 @@ def test_rebuild_past_the_narrow_bound_is_reported(fp):
         G.check()
     assert "32 bits" in str(ei.value) or "2^32" in str(ei.value)
     torch.cuda.synchronize()
+
+
+def test_narrow_threshold_changes_keep_results(fp):
+    """Changing the hub threshold of a narrow graph (rows re-laid out, pool
+    rebuilt) never changes results; they stay equal to a wide graph's."""
+    g = synth.chung_lu(6000, 90000, 2.05, 200, seed=2074)
+    say("case: narrow graph, hub threshold changes")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
+    Gw = fp.Graph(g, layout=fp.FPPR_LAYOUT_WIDE)
+    for X in (G, Gw):
+        X.build_pool(S=16, L=2, K=16, alpha=0.2, seed=9)
+    kw = dict(topk=10, stitch=True, counts=True, digests=True, stats=True)
+    ref = fp.run(Gw, 0.2, 48, 31, **kw)
+    for H in (8, 100, 3000, UINT32_MAX, 8):
+        G.set_hub_threshold(H)
+        G.rebuild()
+        G.check()
+        same(fp.run(G, 0.2, 48, 31, **kw), ref)
