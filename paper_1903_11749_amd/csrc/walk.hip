@@ -45,7 +45,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk (rows spanned + 1)
-constexpr uint32_t kInlineRestarts = 4;  // restarts handled per iteration (4 measured fastest of 2..16)
+constexpr uint32_t kInlineRestarts = 1;  // restarts per iteration: 1 (rare here, since all-nodes runs move
+                                         // the walks of nodes without out-edges to the coin-only kernel)
 
 enum : uint32_t {
   kIdle = 0,
