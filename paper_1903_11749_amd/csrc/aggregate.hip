@@ -148,6 +148,24 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
 // R <= 256: one wave per source, E = ceil(R/64) endpoints per lane (element
 // index idx = e * 64 + lane), sorted across the wave with shuffles.
 // ---------------------------------------------------------------------------
+// The value of lane (this lane ^ j), j a power of two below 64 (a constant
+// once the sort's loops are unrolled): DPP within rows of 16 lanes for
+// j = 1, 2, 4, 8, a swizzle within 32 lanes for j = 16, a permute for 32.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, uint32_t j) {
+  const int x = static_cast<int>(v);
+  switch (j) {
+    case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+    case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+    case 4: {  // half-row mirror (i -> 7 - i), then quad reverse (i -> i ^ 3): i -> i ^ 4
+      const int m = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
+      return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false));
+    }
+    case 8: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));  // row rotate by 8
+    case 16: return static_cast<uint32_t>(__builtin_amdgcn_ds_swizzle(x, 0x401F));  // xor 16 within 32 lanes
+    default: return static_cast<uint32_t>(__shfl_xor(x, static_cast<int>(j), 64));
+  }
+}
+
 template <int E>
 __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[E]) {
   const uint32_t lane = __lane_id();
@@ -173,7 +191,7 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[E]) {
 #pragma unroll
         for (uint32_t e = 0; e < E; ++e) {
           const uint32_t idx = e * 64 + lane;
-          const uint32_t other = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v[e]), static_cast<int>(j), 64));
+          const uint32_t other = xor_lane(v[e], j);
           const bool up = (idx & k) == 0;
           const bool lower = (lane & j) == 0;  // this lane holds the lower index
           const bool take_min = (lower == up);
