@@ -151,8 +151,7 @@ fppr_status enqueue(fppr_batch* b, fppr_stats* stats, fppr_profile* prof, hipStr
   if (e != hipSuccess) return hip_fail(e, "zero control words");
   if (prof && (e = hipEventRecord(prof->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
   const uint32_t nt = static_cast<uint32_t>(b->host_table.size());
-  e = launch_walk(b->table, nt, b->total, b->ctl, stats, b->opts.blocks_per_cu, s,
-                  table_layout(b->host_table.data(), nt), same_graph_table(b->host_table.data(), nt));
+  e = launch_walk(b->table, b->host_table.data(), nt, b->total, b->ctl, stats, b->opts.blocks_per_cu, s);
   if (e != hipSuccess) return hip_fail(e, "walk kernel");
   if (prof && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
   if (prof && (e = hipEventRecord(prof->ev[1], s)) != hipSuccess) return hip_fail(e, "event");

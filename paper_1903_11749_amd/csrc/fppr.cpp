@@ -593,8 +593,7 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
       if ((e = hipEventRecord(g->fork_ev, s)) != hipSuccess) return hip_fail(e, "fork event");
       if ((e = hipStreamWaitEvent(g->side, g->fork_ev, 0)) != hipSuccess) return hip_fail(e, "fork wait");
     }
-    if (total && (e = launch_walk(desc, 1, total, ctl, stats, p->blocks_per_cu, s, table_layout(&D, 1))) !=
-                     hipSuccess)
+    if (total && (e = launch_walk(desc, &D, 1, total, ctl, stats, p->blocks_per_cu, s)) != hipSuccess)
       return hip_fail(e, "walk kernel");
     if (prof && !blocked && (e = hipEventRecord(prof->ev[4], s)) != hipSuccess) return hip_fail(e, "event");
     if (split) {

@@ -128,10 +128,10 @@ constexpr uint32_t kDescEpBySource = 1;
 constexpr uint32_t kDescNarrow = 2;
 // lane_keys: the per-lane-key form of the kernel (for tables whose
 // descriptors all read one graph; see same_graph_table)
-// layout: table_layout of the table's host copy
-hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
-                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, int layout,
-                       bool lane_keys = false);
+// descs: the table on the device; host: the same table in host memory (it
+// selects the kernel's form: layouts, per-lane keys, inline restarts)
+hipError_t launch_walk(const WalkDesc* descs, const WalkDesc* host, uint32_t ndesc, uint64_t total,
+                       unsigned long long* ctl, fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s);
 // 0 when every descriptor's graph is wide, 1 when every one is narrow, 2 mixed
 int table_layout(const WalkDesc* h, uint32_t ndesc);
 // true when a table (host copy) has more than one descriptor and all of them

@@ -208,8 +208,8 @@ bool launch_slot(fppr_server* S, int slot, uint32_t nd, uint64_t total, hipStrea
     return fail(S, e, "upload walk table");
   if ((e = launch_zero_u64(reinterpret_cast<uint64_t*>(S->d_ctl[slot]), kCtlBytes / 8, ws)) != hipSuccess)
     return fail(S, e, "zero control words");
-  if ((e = launch_walk(S->d_tab[slot], nd, total, S->d_ctl[slot], S->d_stats, S->o.blocks_per_cu, ws,
-                       table_layout(S->h_tab[slot], nd), same_graph_table(S->h_tab[slot], nd))) != hipSuccess)
+  if ((e = launch_walk(S->d_tab[slot], S->h_tab[slot], nd, total, S->d_ctl[slot], S->d_stats, S->o.blocks_per_cu,
+                       ws)) != hipSuccess)
     return fail(S, e, "walk kernel");
   if ((e = hipEventRecord(S->ev[slot], ws)) != hipSuccess) return fail(S, e, "event record");
   S->ring_busy[slot] = true;

@@ -60,8 +60,7 @@ struct Trial {
       if ((e = launch_zero_u64(reinterpret_cast<uint64_t*>(buf->ctl), 2, s)) != hipSuccess)
         return hip_fail(e, "zero control words");
       if ((e = hipEventRecord(buf->ev[0], s)) != hipSuccess) return hip_fail(e, "event");
-      if ((e = launch_walk(buf->desc, 1, total, buf->ctl, nullptr, blocks_per_cu, s, table_layout(&D, 1))) !=
-          hipSuccess)
+      if ((e = launch_walk(buf->desc, &D, 1, total, buf->ctl, nullptr, blocks_per_cu, s)) != hipSuccess)
         return hip_fail(e, "walk kernel");
       if ((e = hipEventRecord(buf->ev[1], s)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipEventSynchronize(buf->ev[1])) != hipSuccess) return hip_fail(e, "event sync");

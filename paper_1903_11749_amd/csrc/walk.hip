@@ -45,8 +45,10 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk (rows spanned + 1)
-constexpr uint32_t kInlineRestarts = 1;  // restarts per iteration: 1 (rare here, since all-nodes runs move
-                                         // the walks of nodes without out-edges to the coin-only kernel)
+// Restarts at the head handled inline per loop iteration: 4 in general
+// (2..16 measured), 1 for tables of all-nodes runs whose nodes without
+// out-edges went to the coin-only kernel: restarts are rare there, and a
+// loop that cannot repeat costs less.
 
 enum : uint32_t {
   kIdle = 0,
@@ -124,8 +126,8 @@ __device__ __forceinline__ uint64_t sread64(uint64_t x) {
 }
 
 // kLayout: 0 = every descriptor's graph is wide, 1 = every one is narrow,
-// 2 = mixed (read per descriptor).
-template <bool kStats, bool kLaneKeys, int kLayout>
+// 2 = mixed (read per descriptor). kInlineRestarts: see above.
+template <bool kStats, bool kLaneKeys, int kLayout, uint32_t kInlineRestarts>
 __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   __shared__ uint64_t sh_line[kThreads / 64][64];
   __shared__ uint64_t sh_x[kThreads / 64][64];
@@ -613,14 +615,15 @@ __global__ void k_set_desc(WalkDesc d, WalkDesc* dst) {
   if (threadIdx.x == 0) *dst = d;
 }
 
-template <bool kStats, bool kLaneKeys, int kLayout>
+template <bool kStats, bool kLaneKeys, int kLayout, uint32_t kRestarts>
 hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t s) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats, kLaneKeys, kLayout>, kThreads, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk<kStats, kLaneKeys, kLayout, kRestarts>,
+                                                   kThreads, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   if (blocks_per_cu && static_cast<int>(blocks_per_cu) < per_cu) per_cu = static_cast<int>(blocks_per_cu);
@@ -628,8 +631,8 @@ hipError_t launch_walk_t(const WalkTable& t, uint32_t blocks_per_cu, hipStream_t
   const uint64_t need = (t.total + kThreads - 1) / kThreads;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_walk<kStats, kLaneKeys, kLayout>), dim3(static_cast<uint32_t>(blocks)), dim3(kThreads), 0,
-                     s, t);
+  hipLaunchKernelGGL((k_walk<kStats, kLaneKeys, kLayout, kRestarts>), dim3(static_cast<uint32_t>(blocks)),
+                     dim3(kThreads), 0, s, t);
   return hipGetLastError();
 }
 
@@ -682,24 +685,40 @@ hipError_t launch_set_desc(const WalkDesc& d, WalkDesc* dst, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_walk(const WalkDesc* descs, uint32_t ndesc, uint64_t total, unsigned long long* ctl,
-                       fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s, int layout, bool lane_keys) {
-  if (total == 0 || ndesc == 0) return hipSuccess;
-  WalkTable t{descs, ndesc, total, ctl, stats};
-  const uint32_t b = blocks_per_cu;
-  if (lane_keys) {  // one graph, so one layout
-    if (layout == 1) return stats ? launch_walk_t<true, true, 1>(t, b, s) : launch_walk_t<false, true, 1>(t, b, s);
-    return stats ? launch_walk_t<true, true, 0>(t, b, s) : launch_walk_t<false, true, 0>(t, b, s);
-  }
-  if (layout == 0) return stats ? launch_walk_t<true, false, 0>(t, b, s) : launch_walk_t<false, false, 0>(t, b, s);
-  if (layout == 1) return stats ? launch_walk_t<true, false, 1>(t, b, s) : launch_walk_t<false, false, 1>(t, b, s);
-  return stats ? launch_walk_t<true, false, 2>(t, b, s) : launch_walk_t<false, false, 2>(t, b, s);
-}
-
 int table_layout(const WalkDesc* h, uint32_t ndesc) {
   bool nar = false, wide = false;
   for (uint32_t k = 0; k < ndesc; ++k) ((h[k].flags & kDescNarrow) ? nar : wide) = true;
   return nar && wide ? 2 : (nar ? 1 : 0);
+}
+
+namespace {
+template <int kLayout, uint32_t kR>
+hipError_t launch_plain(const WalkTable& t, bool stats, uint32_t b, hipStream_t s) {
+  return stats ? launch_walk_t<true, false, kLayout, kR>(t, b, s) : launch_walk_t<false, false, kLayout, kR>(t, b, s);
+}
+}  // namespace
+
+hipError_t launch_walk(const WalkDesc* descs, const WalkDesc* host, uint32_t ndesc, uint64_t total,
+                       unsigned long long* ctl, fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s) {
+  if (total == 0 || ndesc == 0) return hipSuccess;
+  WalkTable t{descs, ndesc, total, ctl, stats};
+  const uint32_t b = blocks_per_cu;
+  const int layout = table_layout(host, ndesc);
+  if (same_graph_table(host, ndesc)) {  // one graph, so one layout; per-lane keys
+    if (layout == 1) return stats ? launch_walk_t<true, true, 1, 4>(t, b, s) : launch_walk_t<false, true, 1, 4>(t, b, s);
+    return stats ? launch_walk_t<true, true, 0, 4>(t, b, s) : launch_walk_t<false, true, 0, 4>(t, b, s);
+  }
+  bool split_only = true;  // every descriptor runs the nodes with out-edges of an all-nodes run
+  for (uint32_t k = 0; k < ndesc; ++k) split_only = split_only && (host[k].flags & kDescEpBySource);
+  const bool st = stats != nullptr;
+  if (split_only) {
+    if (layout == 0) return launch_plain<0, 1>(t, st, b, s);
+    if (layout == 1) return launch_plain<1, 1>(t, st, b, s);
+    return launch_plain<2, 1>(t, st, b, s);
+  }
+  if (layout == 0) return launch_plain<0, 4>(t, st, b, s);
+  if (layout == 1) return launch_plain<1, 4>(t, st, b, s);
+  return launch_plain<2, 4>(t, st, b, s);
 }
 
 bool same_graph_table(const WalkDesc* h, uint32_t ndesc) {
