@@ -85,12 +85,11 @@ typedef struct {
                                   fppr_graph_destroy */
 } fppr_csr;
 
-/* Graph layouts (fppr_graph_opts.layout). Both give identical results. The
- * narrow layout reads fewer lines per weighted pick but compares twice the
- * keys per line: it pays when the graph's lines mostly miss the caches. */
+/* Graph layouts (fppr_graph_opts.layout). Both give identical results; the
+ * narrow layout reads fewer lines per weighted pick (it was faster or equal
+ * on every workload measured). */
 #define FPPR_LAYOUT_AUTO 0u   /* narrow when it fits (max out-degree x max weight
-                                 < 2^32) and the graph's lines take 1 GiB or
-                                 more ((n + m / 8) x 128 bytes), else wide */
+                                 < 2^32), else wide */
 #define FPPR_LAYOUT_WIDE 1u   /* always wide */
 #define FPPR_LAYOUT_NARROW 2u /* narrow; INVALID_ARGUMENT when it does not fit */
 

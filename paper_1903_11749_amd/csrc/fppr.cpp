@@ -310,16 +310,13 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     free_graph(g);
     return invalid(msg);
   }
-  // narrow layout: every row total surely fits in 32 bits, and (by default)
-  // the graph's lines are well beyond the caches, where fewer lines per pick
-  // outweigh the extra compares per line
+  // narrow layout: every row total surely fits in 32 bits
   const bool fits = static_cast<uint64_t>(c.max_deg) * c.max_w <= 0xFFFFFFFFull;
   if (layout == FPPR_LAYOUT_NARROW && !fits) {
     free_graph(g);
     return invalid("layout NARROW needs max out-degree x max weight < 2^32");
   }
-  const uint64_t line_bytes = (n + m / 8) * sizeof(Block);
-  g->narrow = layout == FPPR_LAYOUT_NARROW || (layout == FPPR_LAYOUT_AUTO && fits && line_bytes >= (1ull << 30));
+  g->narrow = layout == FPPR_LAYOUT_NARROW || (layout == FPPR_LAYOUT_AUTO && fits);
   FPPR_TRY(dmalloc(&g->live, n, acc), "hipMalloc(live nodes)");
   FPPR_TRY(dmalloc(&g->dang, n, acc), "hipMalloc(dangling nodes)");
   FPPR_TRY(launch_split_nodes(g, s), "split nodes");

@@ -1,9 +1,8 @@
 """The two graph layouts (64-bit prefixes, and 32-bit prefixes for graphs whose
 row totals fit in 32 bits) give bit-identical results, against each other and
-against the oracle; the narrow layout is refused where it does not fit, and
-small graphs are wide by default; a rebuild that breaks a narrow graph's
-32-bit bound is reported. (The scale-24 parity test runs the narrow layout,
-chosen by default there.)"""
+against the oracle; the narrow layout is refused where it does not fit and
+chosen by default where it does; a rebuild that breaks a narrow graph's
+32-bit bound is reported."""
 import sys
 
 import numpy as np
@@ -104,7 +103,7 @@ def test_rebuild_past_the_narrow_bound_is_reported(fp):
     col = torch.from_numpy(g.col.view(np.int32)).cuda()
     w = torch.from_numpy(g.w.view(np.int32)).cuda()
     G = fp.Graph(n=g.n, row_offsets=ro, col=col, w=w, layout=fp.FPPR_LAYOUT_NARROW)
-    assert fp.Graph(g).layout() == fp.FPPR_LAYOUT_WIDE  # small graph: wide by default
+    assert fp.Graph(g).layout() == fp.FPPR_LAYOUT_NARROW  # narrow by default where it fits
     assert G.layout() == fp.FPPR_LAYOUT_NARROW
     big = np.full(g.m, 0x7FFFFFFF, dtype=np.uint32)
     w.copy_(torch.from_numpy(big.view(np.int32)).cuda())

@@ -73,23 +73,26 @@ def small():
     return synth.small_graph()
 
 
-def test_small_plain_all_sources(fp, small):
-    """Chung-Lu n=2000, alpha=0.2, R=100, seed 1, top-16, every source."""
-    say("case: small plain all sources")
-    G = fp.Graph(small)
+@pytest.mark.parametrize("layout", [0, 1, 2])
+def test_small_plain_all_sources(fp, small, layout):
+    """Chung-Lu n=2000, alpha=0.2, R=100, seed 1, top-16, every source; the
+    default layout, wide and narrow."""
+    say(f"case: small plain all sources, layout {layout}")
+    G = fp.Graph(small, layout=layout)
     out = fp.run(G, 0.2, 100, 1, topk=16)
     ref = O.run(O.Graph.from_csr(small), 0.2, 100, 1, topk=16)
     compare(out, ref, 100, 16)
     stats_equal(out, ref.stats)
 
 
+@pytest.mark.parametrize("layout", [1, 2])
 @pytest.mark.parametrize("H", [2, 8, 9, 64, 100, 4096, UINT32_MAX])
-def test_hub_threshold_is_results_invariant(fp, small, H):
-    """Rows above the threshold are searched through their 8-ary prefix tree,
-    the others by binary search: both pick the same edge as a flat search
-    (integer form of Lemma 1)."""
-    say(f"case: hub threshold H={H}")
-    G = fp.Graph(small, hub_threshold=H)
+def test_hub_threshold_is_results_invariant(fp, small, H, layout):
+    """Rows above the threshold are searched through their prefix tree, the
+    others by binary search: both pick the same edge as a flat search
+    (integer form of Lemma 1), in either layout."""
+    say(f"case: hub threshold H={H}, layout {layout}")
+    G = fp.Graph(small, hub_threshold=H, layout=layout)
     info = G.info()
     deg = small.degrees()
     want = 0 if H == UINT32_MAX else int(np.count_nonzero(deg > max(H, 8)))
@@ -100,12 +103,13 @@ def test_hub_threshold_is_results_invariant(fp, small, H):
     stats_equal(out, ref.stats)
 
 
+@pytest.mark.parametrize("layout", [1, 2])
 @pytest.mark.parametrize("S,L,K,H", [(8, 3, 16, 4096), (32, 3, 64, 64), (4, 1, 1, 2), (64, 5, 8, 16),
                                      (16, 2, 32, UINT32_MAX)])
-def test_small_stitched_and_pool(fp, small, S, L, K, H):
-    say(f"case: stitched S={S} L={L} K={K} H={H}")
+def test_small_stitched_and_pool(fp, small, S, L, K, H, layout):
+    say(f"case: stitched S={S} L={L} K={K} H={H}, layout {layout}")
     alpha = 0.2
-    G = fp.Graph(small, hub_threshold=H)
+    G = fp.Graph(small, hub_threshold=H, layout=layout)
     G.build_pool(S=S, L=L, K=K, alpha=alpha, seed=99)
     og = O.Graph.from_csr(small)
     pool = O.Pool(og, S=S, L=L, K=K, alpha=alpha, seed=99)
