@@ -147,7 +147,6 @@ struct GraphView {
   const Block* __restrict__ rec;     // node lines (plain table)
   const Block* __restrict__ blocks;  // row regions
   uint32_t tree_min;                 // rows with deg > tree_min (>= 8) have a tree
-  uint32_t narrow;                   // 1: narrow layout (u32 prefixes)
 };
 
 __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t d) {

@@ -191,7 +191,7 @@ hipError_t launch_small_compact(fppr_graph* g, uint32_t /*S*/, hipStream_t s) {
 hipError_t launch_pool(fppr_graph* g, hipStream_t s) {
   const uint64_t total = g->n_small << g->K_log2;
   if (total == 0) return hipSuccess;
-  GraphView gv{g->rec, g->blocks, g->tree_min, g->narrow ? 1u : 0u};
+  GraphView gv{g->rec, g->blocks, g->tree_min};
   const uint64_t seed = g->pool_opts.seed;
   if (g->narrow)
     hipLaunchKernelGGL(k_pool<true>, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
