@@ -67,11 +67,16 @@ def _row(row_offsets, col, w, u):
     return [int(x) for x in col[a:b]], [int(x) for x in w[a:b]]
 
 
-def _expand(row_offsets, col, w, v, d, fixed_k, first, step):
+def _expand(row_offsets, col, w, v, d, fixed_k, first, step, max_entries=None):
     """Algorithm 4 for one node, generic over the arithmetic: `first(w_e, W)`
     gives a first-step mass, `step(a, w_e, W)` the mass an edge carries out
     of a frontier entry of mass a. Returns (arrivals B by (t, j), final
-    frontier F by t, its length, frozen entries by (t, j))."""
+    frontier F by t, its length, frozen entries by (t, j)).
+
+    max_entries (optional): a level is expanded only if the table could not
+    exceed that many entries afterwards, bounding it by the current entries
+    plus two per out-edge of the frontier (one arrival and one frontier
+    entry each)."""
     nb, wt = _row(row_offsets, col, w, v)
     if not nb:
         raise ValueError("a big move needs a node with out-neighbours")
@@ -90,6 +95,10 @@ def _expand(row_offsets, col, w, v, d, fixed_k, first, step):
                 break
         elif not (len(Bt) + len(F) + len(Z) < d and prev < len(Bt)):
             break
+        if max_entries is not None:
+            out_edges = sum(int(row_offsets[u + 1]) - int(row_offsets[u]) for u in F)
+            if len(B) + len(F) + len(Z) + 2 * out_edges > max_entries:
+                break
         prev = len(Bt)
         nxt = {}
         for u, a in F.items():
@@ -108,14 +117,15 @@ def _expand(row_offsets, col, w, v, d, fixed_k, first, step):
     return B, F, j, Z
 
 
-def big_moves_exact(row_offsets, col, w, v, alpha, d, fixed_k=None):
+def big_moves_exact(row_offsets, col, w, v, alpha, d, fixed_k=None, max_entries=None):
     """Exact rational big moves of v: {(end, steps, mark): Fraction}. alpha
     is taken as a Fraction; fixed_k replaces the stop rule by exactly fixed_k
-    expansion levels (a pool's fixed walk length)."""
+    expansion levels (a pool's fixed walk length); max_entries adds the
+    size look-ahead of `_expand`."""
     al = Fraction(alpha)
     B, F, k, Z = _expand(row_offsets, col, w, v, d, fixed_k,
                          lambda we, W: Fraction(we, W),
-                         lambda a, we, W: a * (1 - al) * Fraction(we, W))
+                         lambda a, we, W: a * (1 - al) * Fraction(we, W), max_entries)
     out = {}
     for (t, j), a in B.items():
         out[(t, j, TERM)] = out.get((t, j, TERM), 0) + al * a
@@ -126,14 +136,14 @@ def big_moves_exact(row_offsets, col, w, v, alpha, d, fixed_k=None):
     return {key: p for key, p in out.items() if p != 0}
 
 
-def big_moves_fixed(row_offsets, col, w, v, T, d, fixed_k=None):
+def big_moves_fixed(row_offsets, col, w, v, T, d, fixed_k=None, max_entries=None):
     """62-bit fixed-point big moves of v for the coin threshold T (alpha =
     T / 2^32): {(end, steps, mark): integer weight}, weights in units of
     2^-62, zero weights dropped."""
     C = (1 << 32) - T
     B, F, k, Z = _expand(row_offsets, col, w, v, d, fixed_k,
                          lambda we, W: (we * ONE) // W,
-                         lambda a, we, W: (((a * C) >> 32) * we) // W)
+                         lambda a, we, W: (((a * C) >> 32) * we) // W, max_entries)
     out = {}
     for (t, j), a in B.items():
         key = (t, j, TERM)
@@ -149,14 +159,14 @@ def encode(t, steps, mark):
     return int(t) | (int(steps) << 32) | (int(mark) << 48)
 
 
-def table(row_offsets, col, w, small_nodes, T, d):
+def table(row_offsets, col, w, small_nodes, T, d, max_entries=None):
     """Big-move tables of every node in small_nodes (increasing ids): CSR
     offsets u64[len+1], entry encodings u64[], weights u64[] (each node's
     entries in increasing encoding order)."""
     offs = [0]
     ent, wts = [], []
     for v in small_nodes:
-        bm = big_moves_fixed(row_offsets, col, w, int(v), T, d)
+        bm = big_moves_fixed(row_offsets, col, w, int(v), T, d, max_entries=max_entries)
         for key in sorted(bm, key=lambda k: encode(*k)):
             ent.append(encode(*key))
             wts.append(bm[key])
@@ -184,11 +194,11 @@ def pick(entries, weights, D):
 MOVE_CAP = 65536
 
 
-def tables_by_node(row_offsets, col, w, S, T, d):
+def tables_by_node(row_offsets, col, w, S, T, d, max_entries=None):
     """{v: (entries, weights)} for every node with 1 <= out-degree <= S."""
     deg = np.diff(np.asarray(row_offsets, dtype=np.int64))
     small = np.flatnonzero((deg >= 1) & (deg <= S))
-    offs, ent, wts = table(row_offsets, col, w, small, T, d)
+    offs, ent, wts = table(row_offsets, col, w, small, T, d, max_entries)
     return {int(v): (ent[offs[r]:offs[r + 1]].tolist(), wts[offs[r]:offs[r + 1]].tolist())
             for r, v in enumerate(small)}
 

@@ -227,20 +227,45 @@ def test_table_and_pick():
 # --------------------------------------------------------------------------
 # the two things exact big moves are for
 # --------------------------------------------------------------------------
-def chain_with_big_moves(n, off, col, w, alpha, sources, small, d):
+def chain_with_big_moves(n, off, col, w, alpha, sources, small, d, cap=None):
     P, dang = transition(n, off, col, w)
     Q = ((1.0 - float(alpha)) * P).tolil()
     A = (float(alpha) * P).tolil()
     for v in small:
         Q.rows[v], Q.data[v], A.rows[v], A.data[v] = [], [], [], []
-        for (t, _, mark), p in BM.big_moves_exact(off, col, w, int(v), alpha, d).items():
+        for (t, _, mark), p in BM.big_moves_exact(off, col, w, int(v), alpha, d, max_entries=cap).items():
             M = A if mark == 1 else Q
             M[v, t] = M[v, t] + float(p)
     return _series(n, sources, Q.tocsr(), A.tocsr(), dang, float(alpha))
 
 
-@pytest.mark.parametrize("d", [4, 16, 64])
-def test_walks_on_big_moves_give_plain_ppr(d):
+@pytest.mark.parametrize("seed", range(4))
+def test_size_look_ahead(seed):
+    """With the size look-ahead every table holds at most max(cap, 2 deg(v))
+    entries, is still the exact distribution of every walk of its depth
+    (brute force), and never goes deeper than without the cap."""
+    off, col, w = random_graph(12, 40, 20 + seed, dangling=0.15)
+    alpha = Fraction(1, 4)
+    for v in range(12):
+        deg = int(off[v + 1]) - int(off[v])
+        if deg == 0:
+            continue
+        free = BM.big_moves_exact(off, col, w, v, alpha, 64)
+        for cap in (2, 6, 12, 30):
+            bm = BM.big_moves_exact(off, col, w, v, alpha, 64, max_entries=cap)
+            assert len(bm) <= max(cap, 2 * deg)
+            assert longest(bm) <= longest(free)
+            assert bm == brute(off, col, w, v, alpha, longest(bm))
+            fx = BM.big_moves_fixed(off, col, w, v, 1 << 30, 64, max_entries=cap)
+            assert set(fx) <= set(BM.big_moves_exact(off, col, w, v, Fraction(1, 4), 64, max_entries=cap))
+    # a node in front of a 10-edge row: a cap of 8 keeps it at one step
+    off, col, w = csr(12, [(0, 1)] + [(1, t) for t in range(2, 12)])
+    assert longest(BM.big_moves_exact(off, col, w, 0, alpha, 64, max_entries=8)) == 1
+    assert longest(BM.big_moves_exact(off, col, w, 0, alpha, 64, max_entries=22)) == 2
+
+
+@pytest.mark.parametrize("d,cap", [(4, None), (16, None), (64, None), (64, 24)])
+def test_walks_on_big_moves_give_plain_ppr(d, cap):
     """A walk that takes one big move at every small node and plain steps
     elsewhere ends with exactly the PPR distribution of plain walks
     (Lemma 2: a big move is the exact distribution of the walk's next k
@@ -253,7 +278,7 @@ def test_walks_on_big_moves_give_plain_ppr(d):
     alpha = Fraction(3, 20)
     src = np.arange(0, 300, 7)
     pi = ppr_exact(g.n, off, col, w, 0.15, src)
-    chain = chain_with_big_moves(g.n, off, col, w, alpha, src, small, d)
+    chain = chain_with_big_moves(g.n, off, col, w, alpha, src, small, d, cap)
     assert np.max(np.abs(chain - pi)) < 1e-12
     assert np.allclose(chain.sum(axis=1), 1.0, atol=1e-12)
 
