@@ -1,0 +1,102 @@
+"""Alias tables and alias trees (Sec. 2.2, Algorithm 1, Example 2; Sec. 4.1,
+Algorithm 3, Examples 3-4, Lemma 1): CPU oracle, test infrastructure only.
+
+Only the test suite may import this module; it shares nothing with the GPU
+library.
+
+Integer form. For a set S of n items with integer weights w (all >= 1) and
+total W, Algorithm 1's switch probability p(e) = n r(e) is kept as the
+integer P(e) = n w(e) in units of 1/W, so "1" is W and every update
+P(y) <- P(y) - (W - P(x)) is exact: the loop ends with every P in [0, W]
+and no item stranded by rounding. "Select any x in S^s and y in S^l" takes
+the first of each in insertion order (both are FIFO queues, seeded in item
+order; an item that drops below W joins the back of S^s); Example 2's
+printed result follows from that choice.
+
+A pick maps one 64-bit uniform D to X = floor(D n W / 2^64) in [0, n W):
+slot i = X div W (uniform over the n items) and U = X mod W (uniform over
+[0, W)); the result is item i if U < P(i), else its alias. Each item e then
+owns exactly n w(e) of the n W values of X, so the pick hits e with
+probability w(e) / W up to the 2^-64 granularity of D.
+
+Alias tree (Algorithm 3): a set larger than d is split into b = ceil(n / d)
+disjoint subsets; a subset's weight is the sum of its items' weights
+(integers, no normalisation needed); each subset gets its own alias table,
+and the set of subsets is treated the same way, recursively, until a level
+has at most d items. The paper splits at random; Lemma 1 holds for any
+partition, so the split is a parameter (contiguous blocks of d items in
+item order by default, the layout the prefix trees of the hot path use). A
+pick descends from the root with one 64-bit draw per level.
+"""
+from __future__ import annotations
+
+from collections import deque
+
+
+def alias_table(w):
+    """Algorithm 1 on integer weights: returns (P, alias, W) with P[i] in
+    [0, W] the switch threshold of item i in units of 1/W."""
+    w = [int(x) for x in w]
+    if not w or min(w) < 1:
+        raise ValueError("alias table needs at least one item, all weights >= 1")
+    n, W = len(w), sum(w)
+    P = [n * x for x in w]
+    alias = list(range(n))
+    small = deque(i for i in range(n) if P[i] < W)
+    large = deque(i for i in range(n) if P[i] > W)
+    while large:
+        x = small.popleft()
+        y = large[0]
+        alias[x] = y
+        P[y] -= W - P[x]
+        if P[y] <= W:
+            large.popleft()
+            if P[y] < W:
+                small.append(y)
+    return P, alias, W
+
+
+def alias_pick(P, alias, W, D):
+    """Item chosen by the 64-bit uniform D (see the module header)."""
+    n = len(P)
+    X = (int(D) * n * W) >> 64
+    i, U = divmod(X, W)
+    return i if U < P[i] else alias[i]
+
+
+def contiguous_split(n, d):
+    """Blocks of d consecutive items (the last one shorter)."""
+    return [list(range(a, min(a + d, n))) for a in range(0, n, d)]
+
+
+def alias_tree(w, d, split=contiguous_split):
+    """Algorithm 3: a list of levels from the leaves up. Level 0 holds the
+    items' subsets over the original items; each level is a list of groups
+    (members, P, alias, W) whose members index the level below (the items
+    for level 0). The last level has one group: the root."""
+    if d < 2:
+        raise ValueError("the degree threshold must be at least 2")
+    weights = [int(x) for x in w]
+    levels = []
+    while True:
+        n = len(weights)
+        groups = [list(range(n))] if n <= d else split(n, d)
+        assert sorted(i for g in groups for i in g) == list(range(n)), "not a partition"
+        level = []
+        for g in groups:
+            P, al, W = alias_table([weights[i] for i in g])
+            level.append((g, P, al, W))
+        levels.append(level)
+        if len(groups) == 1:
+            return levels
+        weights = [W for _, _, _, W in level]
+
+
+def alias_tree_pick(levels, draws):
+    """Descend from the root: at each level the group's alias table picks a
+    member with the next 64-bit draw; returns the original item index."""
+    g = 0
+    for depth, level in enumerate(reversed(levels)):
+        members, P, al, W = level[g]
+        g = members[alias_pick(P, al, W, draws[depth])]
+    return g
