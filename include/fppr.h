@@ -174,6 +174,23 @@ FPPR_API fppr_status fppr_graph_build_pool(fppr_graph* g, const fppr_pool_opts* 
 FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entries, uint64_t count,
                                             void* stream);
 
+/* Alias tables of every row (Sec. 2.2, Algorithm 1; Example 2), in exact
+ * integers. For a row of n edges with weights w and total W: P[e] = the
+ * switch threshold n w(e) after Algorithm 1's updates, in units of 1/W (so
+ * in [0, W]), and alias[e] = the index within the row (0-based) of the edge
+ * that slot e passes to. A pick with the 64-bit uniform D takes X =
+ * floor(D n W / 2^64), slot i = X div W and keeps i iff X mod W < P[i], else
+ * takes alias[i]; each edge is then chosen with probability w / W up to the
+ * draw's 2^-64 granularity. Algorithm 1's free choice of x and y is the first
+ * of each set in insertion order (FIFO queues seeded in edge order; an edge
+ * that drops below W joins the back of the small set).
+ * P: device u64[m], alias: device u32[m], both indexed like the CSR's edges;
+ * scratch: device u32[2 m] of any contents, used as the two queues. All
+ * three are the caller's. Reads the graph's CSR arrays as they are now.
+ * Asynchronous on `stream`; INVALID_ARGUMENT for NULL pointers (m > 0). */
+FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, uint32_t* alias,
+                                             uint32_t* scratch, void* stream);
+
 /* T(alpha) = floor(alpha * 2^32 + 1/2) clamped to [1, 2^32-1]: a walk stops
  * after a move iff that move's x2 < T (Algorithm 2's coin "q <= alpha").
  * Returns 0 when alpha is not in (0, 1). */

@@ -146,6 +146,7 @@ _SIGS = [
     ("fppr_graph_layout", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_uint32)]),
     ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
     ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
+    ("fppr_graph_alias_tables", ctypes.c_int, [P, P, P, P, P]),
     ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
     ("fppr_walks_for_guarantee", ctypes.c_uint64, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("fppr_plan", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.c_uint64,
@@ -296,6 +297,21 @@ class Graph:
         out = np.zeros(max(count, 1), dtype=np.uint64)
         _check(lib().fppr_graph_export_pool(self._h, out.ctypes.data, count, _stream_ptr(stream)))
         return out[:count]
+
+    def alias_tables(self, stream=None):
+        """Alias tables of every row (fppr_graph_alias_tables): device tensors
+        P (int64 holding the u64 thresholds) and alias (int32 holding u32
+        in-row indices), indexed like the CSR's edges."""
+        import torch
+
+        m = self.info()["m"]
+        P = torch.empty(max(m, 1), dtype=torch.int64, device="cuda")
+        al = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        scratch = torch.empty(max(2 * m, 1), dtype=torch.int32, device="cuda")
+        _check(lib().fppr_graph_alias_tables(self._h, _dptr(P), _dptr(al), _dptr(scratch),
+                                             _stream_ptr(stream)))
+        self._alias_scratch = scratch  # kept alive until the next call; the launch is asynchronous
+        return P[:m], al[:m]
 
     def rebuild(self, stream=None):
         _check(lib().fppr_graph_rebuild(self._h, _stream_ptr(stream)))
