@@ -191,6 +191,25 @@ FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entri
 FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, uint32_t* alias,
                                              uint32_t* scratch, void* stream);
 
+/* Walks that pick each edge with the alias tables (Sec. 2.2 and Sec. 2.1's
+ * walk, Algorithm 2's coin): walk w (w = row * R + i) starts at
+ * sources[row] (or node row when sources is NULL, then n_sources must be n);
+ * its move m draws Philox4x32-10 on (i, m, s, 0); at a node with d out-edges
+ * and total W the move takes X = floor((x1:x0) d W / 2^64), slot = X div W,
+ * keeps the slot iff X mod W < P[slot], else alias[slot], then stops iff
+ * x2 < T(alpha); a node without out-edges sends the walk back to s; 65,536
+ * moves at most. No stitching. endpoints: device u32[n_sources * R] (the end
+ * node; 0xFFFFFFFF for a source id >= n); steps: device u32[n_sources * R]
+ * or NULL. P and alias: the tables fppr_graph_alias_tables built for this
+ * graph (other contents give wrong walks, never an out-of-bounds access).
+ * Needs a narrow-layout graph (d W < 2^59 keeps X within 64 bits);
+ * INVALID_ARGUMENT otherwise, for alpha outside (0, 1), R == 0, NULL
+ * pointers or n_sources * R > 2^40. Asynchronous on `stream`. */
+FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+                                    double alpha, uint32_t R, uint64_t seed, const uint32_t* sources,
+                                    uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
+                                    void* stream);
+
 /* T(alpha) = floor(alpha * 2^32 + 1/2) clamped to [1, 2^32-1]: a walk stops
  * after a move iff that move's x2 < T (Algorithm 2's coin "q <= alpha").
  * Returns 0 when alpha is not in (0, 1). */

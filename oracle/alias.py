@@ -100,3 +100,70 @@ def alias_tree_pick(levels, draws):
         members, P, al, W = level[g]
         g = members[alias_pick(P, al, W, draws[depth])]
     return g
+
+
+# --------------------------------------------------------------------------
+# walks that pick with alias tables (small cases; pure Python)
+# --------------------------------------------------------------------------
+MOVE_CAP = 65536
+
+
+def row_tables(row_offsets, w):
+    """{v: (P, alias, W)} for every node with out-edges."""
+    out = {}
+    for v in range(len(row_offsets) - 1):
+        a, b = int(row_offsets[v]), int(row_offsets[v + 1])
+        if a < b:
+            out[v] = alias_table(w[a:b])
+    return out
+
+
+class LazyTables(dict):
+    """Alias tables of the rows a walk visits, built on first use."""
+
+    def __init__(self, row_offsets, w):
+        super().__init__()
+        self.row_offsets, self.w = row_offsets, w
+
+    def __missing__(self, v):
+        a, b = int(self.row_offsets[v]), int(self.row_offsets[v + 1])
+        t = alias_table(self.w[a:b])
+        self[v] = t
+        return t
+
+
+def walk(row_offsets, col, tables, T, seed, s, i):
+    """One walk from s (walk id i) under Sec. 2.1's rules with alias picks:
+    move m draws Philox4x32-10 on (i, m, s, 0) with key (seed low, seed
+    high); at a node with out-edges the edge is alias_pick(..., (x1:x0)) and
+    the walk then stops iff x2 < T; a node without out-edges returns the walk
+    to s and tosses the coin; 65,536 moves at most. Returns (end, steps)."""
+    from oracle import oracle as O
+
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    tail, steps, m = s, 0, 0
+    while True:
+        x = [int(a) for a in O.philox4x32_10((i, m, s, 0), key)]
+        a, b = int(row_offsets[tail]), int(row_offsets[tail + 1])
+        if a == b:
+            tail = s
+        else:
+            P, al, W = tables[tail]
+            tail = int(col[a + alias_pick(P, al, W, (x[1] << 32) | x[0])])
+        steps += 1
+        m += 1
+        if x[2] < T or m == MOVE_CAP:
+            return tail, steps
+
+
+def run(row_offsets, col, w, T, seed, R, sources):
+    """Endpoints and steps [len(sources), R]."""
+    import numpy as np
+
+    tables = LazyTables(row_offsets, w)
+    ep = np.zeros((len(sources), R), dtype=np.uint32)
+    ln = np.zeros((len(sources), R), dtype=np.uint32)
+    for r, s in enumerate(sources):
+        for i in range(R):
+            ep[r, i], ln[r, i] = walk(row_offsets, col, tables, T, seed, int(s), i)
+    return ep, ln

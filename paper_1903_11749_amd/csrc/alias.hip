@@ -1,4 +1,5 @@
-// Alias tables of every row (Sec. 2.2, Algorithm 1; Example 2).
+// Alias tables of every row (Sec. 2.2, Algorithm 1; Example 2), and walks
+// that pick with them.
 //
 // For a row of n edges with integer weights w and total W the switch
 // probability p(e) = n r(e) is kept as the integer P(e) = n w(e) in units of
@@ -34,6 +35,56 @@ __global__ void k_alias_rows(const uint64_t* __restrict__ off, const uint32_t* _
   alias_row(w + a, d, P + a, alias + a, scratch + 2 * a, scratch + 2 * a + d);
 }
 
+// Walks that pick with the alias tables (plain walks of Sec. 2.1: a move
+// picks an out-edge, then stops with the coin; a node without out-edges
+// sends the walk back to its source). One walk per thread; walk w is walk
+// w mod R of source row w div R, its move m draws Philox4x32-10 on (w mod R,
+// m, s, 0) as every other walk mode does. The pick: X = high 64 bits of
+// (x1:x0) * (d W), slot = X div W, keep the slot iff X mod W < P[slot], else
+// take alias[slot]. d W < 2^59 on narrow graphs, so X fits 64 bits.
+__global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
+                             const Block* __restrict__ rec, const uint64_t* __restrict__ P,
+                             const uint32_t* __restrict__ alias, uint32_t n,
+                             const uint32_t* __restrict__ sources, uint64_t n_src, uint32_t R,
+                             uint32_t T, uint32_t k0, uint32_t k1, uint32_t* __restrict__ ep,
+                             uint32_t* __restrict__ steps) {
+  const uint64_t total = n_src * R;
+  for (uint64_t wid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; wid < total;
+       wid += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t row = wid / R;
+    const uint32_t i = static_cast<uint32_t>(wid - row * R);
+    const uint32_t s = sources ? sources[row] : static_cast<uint32_t>(row);
+    if (s >= n) {
+      ep[wid] = 0xFFFFFFFFu;
+      if (steps) steps[wid] = 0;
+      continue;
+    }
+    uint32_t tail = s, len = 0, m = 0;
+    for (;;) {
+      const U4 x = philox10(i, m, s, 0u, k0, k1);
+      const uint64_t a = off[tail];
+      const uint64_t d = off[tail + 1] - a;
+      if (d == 0) {
+        tail = s;
+      } else {
+        const uint64_t W = rec[tail].key[0];
+        const uint64_t X = scaled_draw(x.x0, x.x1, d * W);
+        uint64_t slot = W ? X / W : 0;
+        if (slot >= d) slot = d - 1;  // only with tables or weights changed since the build
+        const uint64_t U = X - slot * W;
+        uint64_t e = U < P[a + slot] ? slot : alias[a + slot];
+        if (e >= d) e = slot;
+        tail = col[a + e];
+      }
+      ++len;
+      ++m;
+      if (x.x2 < T || m == kMoveCap) break;
+    }
+    ep[wid] = tail;
+    if (steps) steps[wid] = len;
+  }
+}
+
 fppr_status invalid_arg(const char* msg) {
   set_error(msg);
   return FPPR_INVALID_ARGUMENT;
@@ -55,5 +106,30 @@ FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, u
   k_alias_rows<<<blocks, kThreads, 0, s>>>(g->off, g->w, g->n, P, alias, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "alias tables");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+                                    double alpha, uint32_t R, uint64_t seed, const uint32_t* sources,
+                                    uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
+                                    void* stream) {
+  if (!g) return invalid_arg("graph is NULL");
+  if (!g->narrow) return invalid_arg("alias walks need a graph with the narrow layout (32-bit row totals)");
+  if (!P || !alias || !endpoints) return invalid_arg("P, alias or endpoints is NULL");
+  const uint32_t T = fppr_alpha_threshold(alpha);
+  if (T == 0) return invalid_arg("alpha must be in (0, 1)");
+  if (R == 0) return invalid_arg("R must be at least 1");
+  if (!sources && n_sources != g->n) return invalid_arg("without a source list n_sources must be n");
+  if (n_sources == 0) return FPPR_OK;
+  if (n_sources > (uint64_t(1) << 40) / R) return invalid_arg("n_sources * R exceeds 2^40");
+  const uint64_t total = n_sources * R;
+  uint64_t blocks = (total + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_walk_alias<<<static_cast<uint32_t>(blocks), kThreads, 0, s>>>(
+      g->off, g->col, g->rec, P, alias, g->n, sources, n_sources, R, T,
+      static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), endpoints, steps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "alias walks");
   return FPPR_OK;
 }

@@ -147,6 +147,8 @@ _SIGS = [
     ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
     ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
     ("fppr_graph_alias_tables", ctypes.c_int, [P, P, P, P, P]),
+    ("fppr_run_alias", ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
+                                      ctypes.c_uint64, P, P, P]),
     ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
     ("fppr_walks_for_guarantee", ctypes.c_uint64, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("fppr_plan", ctypes.c_int, [P, ctypes.POINTER(fppr_params), ctypes.c_uint64,
@@ -225,6 +227,27 @@ def _stream_ptr(stream):
 
 def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def run_alias(graph, P, alias, alpha: float, R: int, seed: int, sources=None, steps=True, stream=None):
+    """Walks that pick with alias tables (fppr_run_alias). P, alias: the
+    tensors Graph.alias_tables returned. sources: None (every node), a numpy
+    uint32 array or a device int32 tensor. Returns device int32 tensors
+    (endpoints, steps or None) of n_sources * R walks, walk-major per source."""
+    import torch
+
+    n = graph.info()["n"]
+    if sources is None:
+        src, n_src = None, n
+    else:
+        src = sources if isinstance(sources, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(sources, dtype=np.uint32).view(np.int32)).cuda()
+        n_src = int(src.numel())
+    ep = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda")
+    st = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda") if steps else None
+    _check(lib().fppr_run_alias(graph.handle, _dptr(P), _dptr(alias), float(alpha), int(R), int(seed),
+                                _dptr(src), n_src, _dptr(ep), _dptr(st), _stream_ptr(stream)))
+    return ep[:n_src * R], (st[:n_src * R] if st is not None else None)
 
 
 class Graph:

@@ -2,7 +2,8 @@
 row by row, to the oracle's integer alias tables: every row of graphs with
 hub rows of thousands of edges, weights up to 2^31 and unit weights, both
 layouts; on the R-MAT scale-20 graph, the largest rows and a sample of the
-rest. The build time is printed."""
+rest. Walks that pick with the tables give the oracle's endpoints and steps
+bit for bit. Build and walk times are printed."""
 import sys
 
 import numpy as np
@@ -95,3 +96,91 @@ def test_alias_tables_scale20_sampled(fp):
     rng = np.random.default_rng(9)
     sample = rng.choice(np.flatnonzero(deg > 0), 4000, replace=False)
     assert rows_equal(g, P, al, np.concatenate([top, sample])) == []
+
+
+@pytest.mark.parametrize("name", ["chung-lu hubs", "r-mat scale 12", "unit weights"])
+def test_alias_walks_equal_oracle(fp, name):
+    import torch
+
+    g = CASES[name]()
+    say(f"case: alias walks, {name}")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
+    P, al = G.alias_tables()
+    src = np.concatenate([np.arange(0, g.n, 37), [g.n - 1, 0, 0]]).astype(np.uint32)
+    T = fp.fppr_alpha_threshold(0.15)
+    ep, st = fp.run_alias(G, P, al, 0.15, 24, 123456789012, sources=src)
+    torch.cuda.synchronize()
+    ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, T, 123456789012, 24, src)
+    assert np.array_equal(ep.cpu().numpy().view(np.uint32).reshape(len(src), 24), ref_ep)
+    assert np.array_equal(st.cpu().numpy().view(np.uint32).reshape(len(src), 24), ref_st)
+
+
+def test_alias_walks_edges(fp):
+    import torch
+
+    g = CASES["unit weights"]()
+    say("case: alias walks, invalid source, all nodes, wide graph refused")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
+    P, al = G.alias_tables()
+    src = np.array([3, g.n, 7], dtype=np.uint32)
+    ep, st = fp.run_alias(G, P, al, 0.3, 5, 1, sources=src)
+    torch.cuda.synchronize()
+    e = ep.cpu().numpy().view(np.uint32).reshape(3, 5)
+    assert np.all(e[1] == 0xFFFFFFFF) and np.all(st.cpu().numpy().reshape(3, 5)[1] == 0)
+    ref_ep, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.3), 1, 5, [3, 7])
+    assert np.array_equal(e[[0, 2]], ref_ep)
+    ep_all, _ = fp.run_alias(G, P, al, 0.3, 2, 1, steps=False)
+    torch.cuda.synchronize()
+    ref_all, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.3), 1, 2, range(g.n))
+    assert np.array_equal(ep_all.cpu().numpy().view(np.uint32).reshape(g.n, 2), ref_all)
+    Gw = fp.Graph(g, layout=fp.FPPR_LAYOUT_WIDE)
+    Pw, alw = Gw.alias_tables()
+    with pytest.raises(fp.FpprError):
+        fp.run_alias(Gw, Pw, alw, 0.3, 5, 1, sources=src)
+    with pytest.raises(fp.FpprError):
+        fp.run_alias(G, P, al, 1.5, 5, 1, sources=src)
+
+
+def test_alias_walks_scale20(fp):
+    """R-MAT scale 20, R = 16 walks from every node: timed, and 512 sampled
+    sources recomputed by the oracle."""
+    import torch
+
+    g = synth.medium_graph()
+    say("case: alias walks, R-MAT scale 20, R = 16 from every node")
+    G = fp.Graph(g)
+    assert G.layout() == fp.FPPR_LAYOUT_NARROW
+    P, al = G.alias_tables()
+    fp.run_alias(G, P, al, 0.15, 16, 3)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    ep, st = fp.run_alias(G, P, al, 0.15, 16, 3)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    steps = int(st.to(torch.int64).sum().item())
+    say(f"  {g.n * 16} walks, {steps} steps in {ms:.2f} ms: {steps / ms * 1e3:.3e} walk-steps/s")
+    # the same walks on the library's prefix-sum path (no stitching), for
+    # comparison: walk time from the stage timer, steps from its statistics
+    prm = fp.make_params(0.15, 16, 3, 1, False, False, True, True)
+    ws = torch.empty((fp.fppr_plan(G, prm, g.n) + 7) // 8, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        out = fp.alloc_outputs(g.n, 16, 1, counts=False, digests=True, stats=True)
+        prof = fp.Profile()
+        out.profile = prof
+        fp.fppr_run(G, prm, None, g.n, ws, out, None)
+        torch.cuda.synchronize()
+    walk_ms, _ = prof.read()
+    cdf_steps = out.stats_dict()["steps"]
+    say(f"  prefix-sum path: {cdf_steps} steps, walk phase {walk_ms:.2f} ms: "
+        f"{cdf_steps / walk_ms * 1e3:.3e} walk-steps/s")
+    # coins depend on (walk, move, source) only, so every walk has the same
+    # number of moves, and here of steps, whichever edges it picks
+    assert cdf_steps == steps
+    rng = np.random.default_rng(4)
+    sample = np.sort(rng.choice(g.n, 512, replace=False))
+    e = ep.cpu().numpy().view(np.uint32).reshape(g.n, 16)[sample]
+    s_ = st.cpu().numpy().view(np.uint32).reshape(g.n, 16)[sample]
+    ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.15), 3, 16, sample)
+    assert np.array_equal(e, ref_ep) and np.array_equal(s_, ref_st)

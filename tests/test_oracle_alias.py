@@ -172,3 +172,54 @@ def test_rejects_bad_input():
         A.alias_table([1, 0, 2])
     with pytest.raises(ValueError):
         A.alias_tree([1, 2, 3], 1)
+
+
+# --------------------------------------------------------------------------
+# walks that pick with alias tables
+# --------------------------------------------------------------------------
+def test_alias_walk_is_the_plain_walk_on_single_edge_rows():
+    """Where every row has one edge (or none) both picks are forced, so the
+    alias walk is the C oracle's plain walk, endpoint for endpoint and step
+    for step (same draws, coins, restarts)."""
+    import synth
+    from oracle import oracle as O
+
+    rng = np.random.default_rng(12)
+    n = 300
+    src = np.flatnonzero(rng.random(n) < 0.85).astype(np.uint32)
+    dst = rng.integers(0, n, src.size).astype(np.uint32)
+    g = synth.csr_from_edges(n, src, dst, rng.integers(1, 50, src.size).astype(np.uint32))
+    T = O.alpha_threshold(0.1)
+    sources = np.arange(0, n, 7, dtype=np.uint32)
+    ref = O.run(O.Graph(g.n, g.row_offsets, g.col, g.w), 0.1, 24, 31, sources=sources,
+                want_endpoints=True, want_lengths=True, want_counts=False)
+    ep, ln = A.run(g.row_offsets, g.col, g.w, T, 31, 24, sources)
+    assert np.array_equal(ep, ref.endpoints) and np.array_equal(ln, ref.lengths)
+
+
+def test_alias_walks_estimate_plain_ppr():
+    """Alias walks estimate the plain PPR (binomial z-check of every pair
+    with enough expected walks) with the geometric length law."""
+    from scipy.stats import chisquare
+
+    import synth
+    from exact_ppr import mc_z_check, ppr_exact
+    from oracle import oracle as O
+
+    g = synth.chung_lu(150, 900, 2.2, 30, seed=81)
+    T = O.alpha_threshold(0.2)
+    a = T / 2.0**32
+    src = np.array([0, 5, 17, 60, 99], dtype=np.uint32)
+    R = 3000
+    ep, ln = A.run(g.row_offsets, g.col, g.w, T, 8, R, src)
+    pi = ppr_exact(g.n, g.row_offsets, g.col, g.w, a, src)
+    dense = np.zeros((len(src), g.n), dtype=np.int64)
+    for r in range(len(src)):
+        np.add.at(dense[r], ep[r].astype(np.int64), 1)
+    ok, info = mc_z_check(dense, pi, R)
+    assert ok, info
+    L = ln.ravel().astype(np.int64)
+    top = 10
+    obs = np.array([np.count_nonzero(L == l) for l in range(1, top)] + [np.count_nonzero(L >= top)])
+    p = np.array([a * (1 - a) ** (l - 1) for l in range(1, top)] + [(1 - a) ** (top - 1)])
+    assert chisquare(obs, p * L.size).pvalue > 1e-4
