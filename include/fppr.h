@@ -210,6 +210,33 @@ FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, cons
                                     uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
                                     void* stream);
 
+/* Exact big moves of every small node (Sec. 4.2, Algorithm 4; Lemma 2):
+ * for each node v with 1 <= out-degree <= S, the distribution of a walk's
+ * first k steps from v (pick by weight, then stop with alpha), as entries
+ * end | steps << 32 | mark << 48 (mark 1 = stopped there, 0 = still going)
+ * with integer weights in units of 2^-62. A level is expanded while the
+ * distinct end nodes reached, plus the frontier and the frozen entries, are
+ * fewer than d and the last level reached a new node (Algorithm 4's stop
+ * rule), and only if the table cannot pass `cap` entries. Frontier mass at
+ * a node without out-edges is frozen as an active outcome of its length.
+ * Masses are 62-bit fixed point with a floor after every product: first
+ * step floor(w 2^62 / W(v)); an edge (u, t) of frontier mass a carries
+ * floor(floor(a C / 2^32) w / W(u)), C = 2^32 - T(alpha); terminated weight
+ * floor(a T / 2^32), active floor(a C / 2^32). Zero weights are dropped, and
+ * entries are sorted by value.
+ * Outputs (device, indexed by node id): counts u32[n] (0 for nodes that are
+ * not small), entries u64[n * cap] and weights u64[n * cap], node v's
+ * table at [v * cap, v * cap + counts[v]); the rest is left as it was.
+ * scratch: device u64[scratch_words] of any contents, at least 8 * cap
+ * words; each 8 * cap words serve one node at a time. Needs a narrow-layout
+ * graph; INVALID_ARGUMENT otherwise, for alpha outside (0, 1), S or d = 0,
+ * cap outside [2 S, 4096], NULL pointers or too little scratch.
+ * Asynchronous on `stream`. */
+FPPR_API fppr_status fppr_graph_big_moves(const fppr_graph* g, uint32_t S, uint32_t d, uint32_t cap,
+                                          double alpha, uint64_t* entries, uint64_t* weights,
+                                          uint32_t* counts, uint64_t* scratch, uint64_t scratch_words,
+                                          void* stream);
+
 /* T(alpha) = floor(alpha * 2^32 + 1/2) clamped to [1, 2^32-1]: a walk stops
  * after a move iff that move's x2 < T (Algorithm 2's coin "q <= alpha").
  * Returns 0 when alpha is not in (0, 1). */

@@ -147,6 +147,8 @@ _SIGS = [
     ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
     ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
     ("fppr_graph_alias_tables", ctypes.c_int, [P, P, P, P, P]),
+    ("fppr_graph_big_moves", ctypes.c_int, [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_double, P, P, P, P, ctypes.c_uint64, P]),
     ("fppr_run_alias", ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
                                       ctypes.c_uint64, P, P, P]),
     ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
@@ -335,6 +337,23 @@ class Graph:
                                              _stream_ptr(stream)))
         self._alias_scratch = scratch  # kept alive until the next call; the launch is asynchronous
         return P[:m], al[:m]
+
+    def big_moves(self, S: int, d: int, cap: int, alpha: float, slots: int = 16384, stream=None):
+        """Exact big-move tables (fppr_graph_big_moves): device tensors
+        entries and weights [n, cap] (int64 holding u64) and counts [n]
+        (int32); node v's table is entries[v, :counts[v]]."""
+        import torch
+
+        n = self.info()["n"]
+        ent = torch.zeros((n, cap), dtype=torch.int64, device="cuda")
+        wts = torch.zeros((n, cap), dtype=torch.int64, device="cuda")
+        cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+        scratch = torch.empty(8 * cap * max(1, min(slots, n)), dtype=torch.int64, device="cuda")
+        _check(lib().fppr_graph_big_moves(self._h, int(S), int(d), int(cap), float(alpha), _dptr(ent),
+                                          _dptr(wts), _dptr(cnt), _dptr(scratch), scratch.numel(),
+                                          _stream_ptr(stream)))
+        self._bm_scratch = scratch  # kept alive until the next call; the launch is asynchronous
+        return ent, wts, cnt
 
     def rebuild(self, stream=None):
         _check(lib().fppr_graph_rebuild(self._h, _stream_ptr(stream)))
