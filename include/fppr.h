@@ -237,6 +237,29 @@ FPPR_API fppr_status fppr_graph_big_moves(const fppr_graph* g, uint32_t S, uint3
                                           uint32_t* counts, uint64_t* scratch, uint64_t scratch_words,
                                           void* stream);
 
+/* Walks of the paper's design (Algorithm 2 with Sec. 2.2's alias picks and
+ * Sec. 4.2's big moves): walk w = row * R + i from sources[row] (node row
+ * when sources is NULL, then n_sources must be n), move m drawing
+ * Philox4x32-10 on (i, m, s, 0). At a node with 1 <= out-degree <= S the
+ * move takes the first entry of the node's big-move table whose running
+ * weight exceeds floor((x1:x0) * total / 2^64): its end becomes the tail,
+ * its steps are added, and a terminated entry ends the walk. At any other
+ * node with out-edges it is fppr_run_alias's pick followed by the coin
+ * x2 < T(alpha); at a node without out-edges the walk returns to its
+ * source and tosses the coin. 65,536 moves at most.
+ * P, alias: from fppr_graph_alias_tables; bm_entries, bm_weights,
+ * bm_counts, cap: from fppr_graph_big_moves with the same S (other contents
+ * give wrong walks, never an out-of-bounds access). endpoints: device
+ * u32[n_sources * R] (0xFFFFFFFF for a source id >= n); steps: device
+ * u32[n_sources * R] or NULL. Narrow-layout graphs only; INVALID_ARGUMENT
+ * as for fppr_run_alias, or for cap outside [1, 4096]. Asynchronous. */
+FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+                                        const uint64_t* bm_entries, const uint64_t* bm_weights,
+                                        const uint32_t* bm_counts, uint32_t cap, uint32_t S, double alpha,
+                                        uint32_t R, uint64_t seed, const uint32_t* sources,
+                                        uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
+                                        void* stream);
+
 /* T(alpha) = floor(alpha * 2^32 + 1/2) clamped to [1, 2^32-1]: a walk stops
  * after a move iff that move's x2 < T (Algorithm 2's coin "q <= alpha").
  * Returns 0 when alpha is not in (0, 1). */

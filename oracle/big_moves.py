@@ -251,3 +251,74 @@ def run(graph, tables, T, seed, R, sources):
         for i in range(R):
             ep[r, i], ln[r, i], _ = walk(graph, tables, T, seed, int(s), i)
     return ep, ln
+
+
+class LazyBigMoves(dict):
+    """Big-move tables (sorted entries, weights) of the small nodes a walk
+    visits, built on first use with the fixed-point rules and the size cap."""
+
+    def __init__(self, row_offsets, col, w, T, d, max_entries):
+        super().__init__()
+        self.args = (row_offsets, col, w)
+        self.T, self.d, self.cap = T, d, max_entries
+
+    def __missing__(self, v):
+        bm = big_moves_fixed(*self.args, int(v), self.T, self.d, max_entries=self.cap)
+        keys = sorted(bm, key=lambda k: encode(*k))
+        t = ([encode(*k) for k in keys], [bm[k] for k in keys])
+        self[v] = t
+        return t
+
+
+def walk_with_alias(row_offsets, col, w, S, bm_tables, alias_tables, T, seed, s, i):
+    """One walk of the paper's design (Algorithm 2 with Sec. 2.2's alias
+    picks and Sec. 4.2's big moves): at a node with 1 <= out-degree <= S the
+    move takes one big move of its table (pick over the weights with the
+    move's 64-bit draw (x1:x0); a terminated entry ends the walk there, an
+    active one continues from its end); at any other node with out-edges the
+    move takes alias_pick with the same draw and then tosses the coin
+    x2 < T; a node without out-edges sends the walk to s and tosses the
+    coin. Draws: Philox4x32-10 on (i, move, s, 0). Returns (end, steps)."""
+    from oracle import alias as A
+    from oracle import oracle as O
+
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    tail, steps, m = s, 0, 0
+    while True:
+        x = [int(a) for a in O.philox4x32_10((i, m, s, 0), key)]
+        D = (x[1] << 32) | x[0]
+        a, b = int(row_offsets[tail]), int(row_offsets[tail + 1])
+        if a == b:
+            tail = s
+            steps += 1
+            stop = x[2] < T
+        elif b - a <= S:
+            ent, wts = bm_tables[tail]
+            e = pick(ent, wts, D)
+            tail = e & 0xFFFFFFFF
+            steps += (e >> 32) & 0xFFFF
+            stop = (e >> 48) & 1 == TERM
+        else:
+            P, al, W = alias_tables[tail]
+            tail = int(col[a + A.alias_pick(P, al, W, D)])
+            steps += 1
+            stop = x[2] < T
+        m += 1
+        if not stop and m == MOVE_CAP:
+            stop = True
+        if stop:
+            return tail, steps
+
+
+def run_with_alias(row_offsets, col, w, S, d, cap, T, seed, R, sources):
+    """Endpoints and steps [len(sources), R] of walk_with_alias."""
+    from oracle import alias as A
+
+    bm = LazyBigMoves(row_offsets, col, w, T, d, cap)
+    al = A.LazyTables(row_offsets, w)
+    ep = np.zeros((len(sources), R), dtype=np.uint32)
+    ln = np.zeros((len(sources), R), dtype=np.uint32)
+    for r, s in enumerate(sources):
+        for i in range(R):
+            ep[r, i], ln[r, i] = walk_with_alias(row_offsets, col, w, S, bm, al, T, seed, int(s), i)
+    return ep, ln

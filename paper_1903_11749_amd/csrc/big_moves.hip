@@ -1,5 +1,6 @@
 // Exact big-move tables of the small nodes (Sec. 4.2, Algorithm 4), one
-// thread per node over a bounded set of workspace slots. The per-node
+// thread per node over a bounded set of workspace slots, and walks that take
+// them with alias picks elsewhere (the paper's design). The per-node
 // expansion, its fixed-point rules and its size cap are in big_moves_node.hpp.
 #include "big_moves_node.hpp"
 #include "fppr_internal.hpp"
@@ -25,6 +26,83 @@ __global__ void k_big_moves(const uint64_t* __restrict__ off, const uint32_t* __
       c = big_moves_node(off, col, w, static_cast<uint32_t>(v), T, d, cap, mine, entries + v * cap,
                          weights + v * cap);
     counts[v] = c;
+  }
+}
+
+// Walks of the paper's design: at a node with 1 <= out-degree <= S the move
+// takes one big move of the node's table (the first entry whose running
+// weight exceeds X = high 64 bits of (x1:x0) * total weight; a terminated
+// entry ends the walk at its end node, an active one continues there); at
+// any other node with out-edges an alias pick with the same draw (as in
+// k_walk_alias), then the coin x2 < T; a node without out-edges sends the
+// walk back to its source. Draws: Philox4x32-10 on (i, m, s, 0).
+__global__ void k_walk_bm(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
+                          const Block* __restrict__ rec, const uint64_t* __restrict__ P,
+                          const uint32_t* __restrict__ alias, const uint64_t* __restrict__ bm_e,
+                          const uint64_t* __restrict__ bm_w, const uint32_t* __restrict__ bm_c,
+                          uint32_t cap, uint32_t S, uint32_t n, const uint32_t* __restrict__ sources,
+                          uint64_t n_src, uint32_t R, uint32_t T, uint32_t k0, uint32_t k1,
+                          uint32_t* __restrict__ ep, uint32_t* __restrict__ steps) {
+  const uint64_t total = n_src * R;
+  for (uint64_t wid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; wid < total;
+       wid += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t row = wid / R;
+    const uint32_t i = static_cast<uint32_t>(wid - row * R);
+    const uint32_t s = sources ? sources[row] : static_cast<uint32_t>(row);
+    if (s >= n) {
+      ep[wid] = 0xFFFFFFFFu;
+      if (steps) steps[wid] = 0;
+      continue;
+    }
+    uint32_t tail = s, len = 0, m = 0;
+    for (;;) {
+      const U4 x = philox10(i, m, s, 0u, k0, k1);
+      const uint64_t D = (static_cast<uint64_t>(x.x1) << 32) | x.x0;
+      const uint64_t a = off[tail];
+      const uint64_t d = off[tail + 1] - a;
+      bool stop = x.x2 < T;
+      uint32_t c = 0;
+      if (d >= 1 && d <= S) {
+        c = bm_c[tail];
+        if (c > cap) c = 0;  // not a table fppr_graph_big_moves wrote
+      }
+      if (d == 0) {
+        tail = s;
+        ++len;
+      } else if (c) {
+        const uint64_t* te = bm_e + static_cast<uint64_t>(tail) * cap;
+        const uint64_t* tw = bm_w + static_cast<uint64_t>(tail) * cap;
+        uint64_t tot = 0;
+        for (uint32_t q = 0; q < c; ++q) tot += tw[q];
+        const uint64_t X = __umul64hi(D, tot);
+        uint64_t e = te[c - 1], acc = 0;
+        for (uint32_t q = 0; q < c; ++q) {
+          acc += tw[q];
+          if (acc > X) {
+            e = te[q];
+            break;
+          }
+        }
+        const uint32_t t = static_cast<uint32_t>(e);
+        tail = t < n ? t : s;
+        len += static_cast<uint32_t>((e >> 32) & 0xFFFFu);
+        stop = ((e >> 48) & 1u) != 0;
+      } else {
+        const uint64_t W = rec[tail].key[0];
+        const uint64_t X = scaled_draw(x.x0, x.x1, d * W);
+        uint64_t slot = W ? X / W : 0;
+        if (slot >= d) slot = d - 1;
+        const uint64_t U = X - slot * W;
+        uint64_t e = U < P[a + slot] ? slot : alias[a + slot];
+        if (e >= d) e = slot;
+        tail = col[a + e];
+        ++len;
+      }
+      ++m;
+      if (stop || m == kMoveCap) break;
+    }
+    ep[wid] = tail;
+    if (steps) steps[wid] = len;
   }
 }
 
@@ -60,5 +138,34 @@ FPPR_API fppr_status fppr_graph_big_moves(const fppr_graph* g, uint32_t S, uint3
                                                                     counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "big-move tables");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+                                        const uint64_t* bm_entries, const uint64_t* bm_weights,
+                                        const uint32_t* bm_counts, uint32_t cap, uint32_t S, double alpha,
+                                        uint32_t R, uint64_t seed, const uint32_t* sources,
+                                        uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
+                                        void* stream) {
+  if (!g) return bm_invalid("graph is NULL");
+  if (!g->narrow) return bm_invalid("these walks need a graph with the narrow layout (32-bit row totals)");
+  if (!P || !alias || !bm_entries || !bm_weights || !bm_counts || !endpoints)
+    return bm_invalid("a table or the endpoints is NULL");
+  const uint32_t T = fppr_alpha_threshold(alpha);
+  if (T == 0) return bm_invalid("alpha must be in (0, 1)");
+  if (R == 0) return bm_invalid("R must be at least 1");
+  if (cap == 0 || cap > 4096) return bm_invalid("cap must be in [1, 4096]");
+  if (!sources && n_sources != g->n) return bm_invalid("without a source list n_sources must be n");
+  if (n_sources == 0) return FPPR_OK;
+  if (n_sources > (uint64_t(1) << 40) / R) return bm_invalid("n_sources * R exceeds 2^40");
+  const uint64_t total = n_sources * R;
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_walk_bm<<<static_cast<uint32_t>(blocks), 256, 0, s>>>(
+      g->off, g->col, g->rec, P, alias, bm_entries, bm_weights, bm_counts, cap, S, g->n, sources,
+      n_sources, R, T, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), endpoints, steps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "big-move walks");
   return FPPR_OK;
 }

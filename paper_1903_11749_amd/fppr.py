@@ -147,6 +147,9 @@ _SIGS = [
     ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
     ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
     ("fppr_graph_alias_tables", ctypes.c_int, [P, P, P, P, P]),
+    ("fppr_run_big_moves", ctypes.c_int, [P, P, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
+                                          ctypes.c_uint64, P, P, P]),
     ("fppr_graph_big_moves", ctypes.c_int, [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_double, P, P, P, P, ctypes.c_uint64, P]),
     ("fppr_run_alias", ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
@@ -249,6 +252,30 @@ def run_alias(graph, P, alias, alpha: float, R: int, seed: int, sources=None, st
     st = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda") if steps else None
     _check(lib().fppr_run_alias(graph.handle, _dptr(P), _dptr(alias), float(alpha), int(R), int(seed),
                                 _dptr(src), n_src, _dptr(ep), _dptr(st), _stream_ptr(stream)))
+    return ep[:n_src * R], (st[:n_src * R] if st is not None else None)
+
+
+def run_big_moves(graph, P, alias, bm, S: int, alpha: float, R: int, seed: int, sources=None,
+                  steps=True, stream=None):
+    """Walks of the paper's design (fppr_run_big_moves). P, alias: from
+    Graph.alias_tables; bm: the (entries, weights, counts) Graph.big_moves
+    returned for the same S. Returns device int32 tensors (endpoints, steps
+    or None) of n_sources * R walks, walk-major per source."""
+    import torch
+
+    ent, wts, cnt = bm
+    n = graph.info()["n"]
+    if sources is None:
+        src, n_src = None, n
+    else:
+        src = sources if isinstance(sources, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(sources, dtype=np.uint32).view(np.int32)).cuda()
+        n_src = int(src.numel())
+    ep = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda")
+    st = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda") if steps else None
+    _check(lib().fppr_run_big_moves(graph.handle, _dptr(P), _dptr(alias), _dptr(ent), _dptr(wts), _dptr(cnt),
+                                    int(ent.shape[1]), int(S), float(alpha), int(R), int(seed), _dptr(src),
+                                    n_src, _dptr(ep), _dptr(st), _stream_ptr(stream)))
     return ep[:n_src * R], (st[:n_src * R] if st is not None else None)
 
 

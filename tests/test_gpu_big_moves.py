@@ -108,3 +108,61 @@ def test_big_moves_scale20(fp):
     ent = ent.cpu().numpy().view(np.uint64)
     wts = wts.cpu().numpy().view(np.uint64)
     assert compare(fp, g, ent, wts, c, S, d, cap, alpha, sample) == []
+
+
+@pytest.mark.parametrize("case", CASES[:3] + CASES[4:], ids=[c[0] for c in CASES[:3] + CASES[4:]])
+def test_paper_design_walks_equal_oracle(fp, case):
+    """Walks with alias picks and one exact big move at each small node
+    (fppr_run_big_moves) give the oracle's endpoints and steps bit for bit."""
+    import torch
+
+    name, make, S, d, cap, alpha = case
+    g = make()
+    say(f"case: big-move walks, {name}")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
+    P, al = G.alias_tables()
+    bm = G.big_moves(S, d, cap, alpha)
+    src = np.concatenate([np.arange(0, g.n, 13), [g.n - 1, 0, 0, g.n]]).astype(np.uint32)
+    ep, st = fp.run_big_moves(G, P, al, bm, S, alpha, 16, 987654321, sources=src)
+    torch.cuda.synchronize()
+    ep = ep.cpu().numpy().view(np.uint32).reshape(len(src), 16)
+    st = st.cpu().numpy().view(np.uint32).reshape(len(src), 16)
+    assert np.all(ep[-1] == 0xFFFFFFFF) and np.all(st[-1] == 0)
+    T = fp.fppr_alpha_threshold(alpha)
+    ref_ep, ref_st = BM.run_with_alias(g.row_offsets, g.col, g.w, S, d, cap, T, 987654321, 16, src[:-1])
+    assert np.array_equal(ep[:-1], ref_ep) and np.array_equal(st[:-1], ref_st)
+
+
+def test_paper_design_walks_scale20(fp):
+    """R-MAT scale 20, R = 16 from every node, S = d = 32, cap = 64: timed
+    beside the alias walks without big moves, and 128 sampled sources
+    recomputed by the oracle."""
+    import torch
+
+    g = synth.medium_graph()
+    S, d, cap, alpha = 32, 32, 64, 0.15
+    say("case: big-move walks, R-MAT scale 20, R = 16 from every node")
+    G = fp.Graph(g)
+    P, al = G.alias_tables()
+    bm = G.big_moves(S, d, cap, alpha)
+    fp.run_big_moves(G, P, al, bm, S, alpha, 16, 3)
+    torch.cuda.synchronize()
+    res = {}
+    for label, call in (("big moves + alias", lambda: fp.run_big_moves(G, P, al, bm, S, alpha, 16, 3)),
+                        ("alias only", lambda: fp.run_alias(G, P, al, alpha, 16, 3))):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        ep, st = call()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        steps = int(st.to(torch.int64).sum().item())
+        say(f"  {label}: {steps} steps in {ms:.2f} ms: {steps / ms * 1e3:.3e} walk-steps/s")
+        res[label] = (ep, st)
+    ep, st = res["big moves + alias"]
+    sample = np.sort(np.random.default_rng(6).choice(g.n, 128, replace=False))
+    e = ep.cpu().numpy().view(np.uint32).reshape(g.n, 16)[sample]
+    s_ = st.cpu().numpy().view(np.uint32).reshape(g.n, 16)[sample]
+    ref_ep, ref_st = BM.run_with_alias(g.row_offsets, g.col, g.w, S, d, cap,
+                                       fp.fppr_alpha_threshold(alpha), 3, 16, sample)
+    assert np.array_equal(e, ref_ep) and np.array_equal(s_, ref_st)

@@ -363,3 +363,34 @@ def test_walks_with_big_moves_estimate_plain_ppr():
     obs = np.array([np.count_nonzero(L == l) for l in range(1, top)] + [np.count_nonzero(L >= top)])
     p = np.array([a * (1 - a) ** (l - 1) for l in range(1, top)] + [(1 - a) ** (top - 1)])
     assert chisquare(obs, p * L.size).pvalue > 1e-4
+
+
+def test_paper_design_walk_estimates_plain_ppr():
+    """Walks of the paper's design (alias picks, one exact big move at each
+    small node) estimate the plain PPR without bias and keep the geometric
+    length law; with S = 0 (no small nodes) they are the alias walks."""
+    from scipy.stats import chisquare
+
+    from exact_ppr import mc_z_check
+    from oracle import alias as A
+
+    g = synth.chung_lu(120, 500, 2.3, 20, seed=82)
+    T = O.alpha_threshold(0.25)
+    a = T / 2.0**32
+    src = np.array([0, 3, 11, 40, 77], dtype=np.uint32)
+    R = 3000
+    ep, ln = BM.run_with_alias(g.row_offsets, g.col, g.w, 6, 24, 64, T, 5, R, src)
+    pi = ppr_exact(g.n, g.row_offsets, g.col, g.w, a, src)
+    dense = np.zeros((len(src), g.n), dtype=np.int64)
+    for r in range(len(src)):
+        np.add.at(dense[r], ep[r].astype(np.int64), 1)
+    ok, info = mc_z_check(dense, pi, R)
+    assert ok, info
+    L = ln.ravel().astype(np.int64)
+    top = 12
+    obs = np.array([np.count_nonzero(L == l) for l in range(1, top)] + [np.count_nonzero(L >= top)])
+    p = np.array([a * (1 - a) ** (l - 1) for l in range(1, top)] + [(1 - a) ** (top - 1)])
+    assert chisquare(obs, p * L.size).pvalue > 1e-4
+    e0, l0 = BM.run_with_alias(g.row_offsets, g.col, g.w, 0, 24, 64, T, 5, 40, src)
+    e1, l1 = A.run(g.row_offsets, g.col, g.w, T, 5, 40, src)
+    assert np.array_equal(e0, e1) and np.array_equal(l0, l1)
