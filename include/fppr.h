@@ -225,7 +225,8 @@ FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, cons
  * floor(a T / 2^32), active floor(a C / 2^32). Zero weights are dropped, and
  * entries are sorted by value.
  * Outputs (device, indexed by node id): counts u32[n] (0 for nodes that are
- * not small), entries u64[n * cap] and weights u64[n * cap], node v's
+ * not small), entries u64[n * cap] and weights u64[n * cap] (the inclusive
+ * prefix of the entries' weights, so the last is the total), node v's
  * table at [v * cap, v * cap + counts[v]); the rest is left as it was.
  * scratch: device u64[scratch_words] of any contents, at least 8 * cap
  * words; each 8 * cap words serve one node at a time. Needs a narrow-layout
@@ -241,8 +242,8 @@ FPPR_API fppr_status fppr_graph_big_moves(const fppr_graph* g, uint32_t S, uint3
  * Sec. 4.2's big moves): walk w = row * R + i from sources[row] (node row
  * when sources is NULL, then n_sources must be n), move m drawing
  * Philox4x32-10 on (i, m, s, 0). At a node with 1 <= out-degree <= S the
- * move takes the first entry of the node's big-move table whose running
- * weight exceeds floor((x1:x0) * total / 2^64): its end becomes the tail,
+ * move takes the first entry of the node's big-move table whose inclusive
+ * weight prefix exceeds floor((x1:x0) * total / 2^64): its end becomes the tail,
  * its steps are added, and a terminated entry ends the walk. At any other
  * node with out-edges it is fppr_run_alias's pick followed by the coin
  * x2 < T(alpha); at a node without out-edges the walk returns to its

@@ -30,8 +30,9 @@ __global__ void k_big_moves(const uint64_t* __restrict__ off, const uint32_t* __
 }
 
 // Walks of the paper's design: at a node with 1 <= out-degree <= S the move
-// takes one big move of the node's table (the first entry whose running
-// weight exceeds X = high 64 bits of (x1:x0) * total weight; a terminated
+// takes one big move of the node's table (the first entry whose inclusive
+// weight prefix exceeds X = high 64 bits of (x1:x0) * total weight, found by
+// binary search; a terminated
 // entry ends the walk at its end node, an active one continues there); at
 // any other node with out-edges an alias pick with the same draw (as in
 // k_walk_alias), then the coin x2 < T; a node without out-edges sends the
@@ -72,17 +73,14 @@ __global__ void k_walk_bm(const uint64_t* __restrict__ off, const uint32_t* __re
       } else if (c) {
         const uint64_t* te = bm_e + static_cast<uint64_t>(tail) * cap;
         const uint64_t* tw = bm_w + static_cast<uint64_t>(tail) * cap;
-        uint64_t tot = 0;
-        for (uint32_t q = 0; q < c; ++q) tot += tw[q];
-        const uint64_t X = __umul64hi(D, tot);
-        uint64_t e = te[c - 1], acc = 0;
-        for (uint32_t q = 0; q < c; ++q) {
-          acc += tw[q];
-          if (acc > X) {
-            e = te[q];
-            break;
-          }
+        const uint64_t X = __umul64hi(D, tw[c - 1]);
+        uint32_t lo = 0, hi = c - 1;  // first inclusive prefix above X
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (tw[mid] > X) hi = mid;
+          else lo = mid + 1;
         }
+        const uint64_t e = te[lo];
         const uint32_t t = static_cast<uint32_t>(e);
         tail = t < n ? t : s;
         len += static_cast<uint32_t>((e >> 32) & 0xFFFFu);

@@ -17,8 +17,9 @@
 // frontier entry of mass a carries floor(floor(a C / 2^32) w / W(u)) with C =
 // 2^32 - T; terminated weight floor(a T / 2^32), active floor(a C / 2^32).
 // Sums are exact, so the result does not depend on visiting order. Output:
-// entries t | j << 32 | mark << 48 (mark 1 = terminated) with their
-// weights, zero weights dropped, sorted by entry.
+// entries t | j << 32 | mark << 48 (mark 1 = terminated), zero weights
+// dropped, sorted by entry, with the inclusive prefix of their weights
+// (strictly increasing, so a pick is a binary search).
 //
 // Row totals must fit 32 bits (the narrow layout's bound), which keeps every
 // product below 2^94 and every division a 96-by-32-bit one. Plain integer
@@ -73,7 +74,8 @@ __host__ __device__ inline bool bm_add(uint64_t* k, uint64_t* m, uint32_t& n, ui
 }
 
 // Workspace of one node: 8 arrays of cap words (B, F, F', Z keys and masses).
-// Returns the number of entries written to out_e / out_w (at most cap), or
+// Returns the number of entries written to out_e / out_w (entries and
+// inclusive weight prefixes, at most cap), or
 // 0xFFFFFFFF if a set outgrew cap (cannot happen when cap >= 2 deg(v)).
 __host__ __device__ inline uint32_t big_moves_node(const uint64_t* off, const uint32_t* col,
                                                    const uint32_t* w, uint32_t v, uint32_t T,
@@ -140,6 +142,7 @@ __host__ __device__ inline uint32_t big_moves_node(const uint64_t* off, const ui
   for (uint32_t i = 0; i < nb; ++i) put(bk[i] | (1ull << 48), bm_mul_shr32(bm[i], T));
   for (uint32_t i = 0; i < nf; ++i) put(fk[i] | (static_cast<uint64_t>(j) << 32), bm_mul_shr32(fm[i], C));
   for (uint32_t i = 0; i < nz; ++i) put(zk[i], bm_mul_shr32(zm[i], C));
+  for (uint32_t i = 1; i < n; ++i) out_w[i] += out_w[i - 1];  // inclusive prefix
   return n;
 }
 

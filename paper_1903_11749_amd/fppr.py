@@ -367,8 +367,8 @@ class Graph:
 
     def big_moves(self, S: int, d: int, cap: int, alpha: float, slots: int = 16384, stream=None):
         """Exact big-move tables (fppr_graph_big_moves): device tensors
-        entries and weights [n, cap] (int64 holding u64) and counts [n]
-        (int32); node v's table is entries[v, :counts[v]]."""
+        entries and inclusive weight prefixes [n, cap] (int64 holding u64)
+        and counts [n] (int32); node v's table is entries[v, :counts[v]]."""
         import torch
 
         n = self.info()["n"]

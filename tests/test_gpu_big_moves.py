@@ -1,6 +1,6 @@
 """Exact big-move tables built on the GPU (Sec. 4.2, Algorithm 4, with the
-size cap) are bit-identical to the oracle's 62-bit tables for every small
-node: several graphs, degree bounds S, stop-rule sizes d, caps and alphas,
+size cap; weights stored as inclusive prefixes) are bit-identical to the
+oracle's 62-bit tables for every small node: several graphs, degree bounds S, stop-rule sizes d, caps and alphas,
 including levels through nodes without out-edges; on the R-MAT scale-20
 graph the build is timed and a sample of small nodes recomputed."""
 import sys
@@ -47,7 +47,7 @@ def compare(fp, g, ent, wts, cnt, S, d, cap, alpha, nodes):
     for r, v in enumerate(nodes):
         c = int(cnt[v])
         if not (np.array_equal(ent[v, :c], oe[offs[r]:offs[r + 1]])
-                and np.array_equal(wts[v, :c], ow[offs[r]:offs[r + 1]])):
+                and np.array_equal(wts[v, :c], np.cumsum(ow[offs[r]:offs[r + 1]], dtype=np.uint64))):
             bad.append(int(v))
     return bad
 
