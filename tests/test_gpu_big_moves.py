@@ -37,6 +37,7 @@ CASES = [
     ("r-mat S=32 d=32 cap=128", lambda: synth.rmat(10, 8, .57, .19, .19, 10000, seed=7, zipf_s=1.2), 32, 32, 128, 0.15),
     ("chung-lu S=4 d=100 cap=1024 a=0.5", lambda: synth.chung_lu(300, 900, 2.5, 5, seed=80), 4, 100, 1024, 0.5),
     ("r-mat S=8 d=6 cap=16 a=0.85", lambda: synth.rmat(9, 4, .57, .19, .19, 100, seed=9, zipf_s=1.5), 8, 6, 16, 0.85),
+    ("r-mat dead ends S=4 d=64 cap=40", lambda: synth.rmat(11, 2, .45, .25, .25, 50, seed=12, zipf_s=1.5), 4, 64, 40, 0.1),
 ]
 
 
