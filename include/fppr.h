@@ -191,6 +191,15 @@ FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entri
 FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, uint32_t* alias,
                                              uint32_t* scratch, void* stream);
 
+/* Packs the alias tables into one 16-byte slot per edge for the walks:
+ * slots[2e] = P[e], slots[2e + 1] = col[e] | col[a + alias[e]] << 32 (a =
+ * the row's first edge), so a pick reads one slot. P, alias: from
+ * fppr_graph_alias_tables; slots: device u64[2 m], 16-byte aligned, the
+ * caller's. Asynchronous on `stream`; INVALID_ARGUMENT for NULL pointers
+ * (m > 0) or a misaligned slots. */
+FPPR_API fppr_status fppr_graph_alias_slots(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+                                            uint64_t* slots, void* stream);
+
 /* Walks that pick each edge with the alias tables (Sec. 2.2 and Sec. 2.1's
  * walk, Algorithm 2's coin): walk w (w = row * R + i) starts at
  * sources[row] (or node row when sources is NULL, then n_sources must be n);
@@ -200,15 +209,14 @@ FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, u
  * x2 < T(alpha); a node without out-edges sends the walk back to s; 65,536
  * moves at most. No stitching. endpoints: device u32[n_sources * R] (the end
  * node; 0xFFFFFFFF for a source id >= n); steps: device u32[n_sources * R]
- * or NULL. P and alias: the tables fppr_graph_alias_tables built for this
- * graph (other contents give wrong walks, never an out-of-bounds access).
+ * or NULL. slots: what fppr_graph_alias_slots packed for this graph (other
+ * contents give wrong walks, never an out-of-bounds access).
  * Needs a narrow-layout graph (d W < 2^59 keeps X within 64 bits);
  * INVALID_ARGUMENT otherwise, for alpha outside (0, 1), R == 0, NULL
  * pointers or n_sources * R > 2^40. Asynchronous on `stream`. */
-FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
-                                    double alpha, uint32_t R, uint64_t seed, const uint32_t* sources,
-                                    uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
-                                    void* stream);
+FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* slots, double alpha, uint32_t R,
+                                    uint64_t seed, const uint32_t* sources, uint64_t n_sources,
+                                    uint32_t* endpoints, uint32_t* steps, void* stream);
 
 /* Exact big moves of every small node (Sec. 4.2, Algorithm 4; Lemma 2):
  * for each node v with 1 <= out-degree <= S, the distribution of a walk's
@@ -248,13 +256,13 @@ FPPR_API fppr_status fppr_graph_big_moves(const fppr_graph* g, uint32_t S, uint3
  * node with out-edges it is fppr_run_alias's pick followed by the coin
  * x2 < T(alpha); at a node without out-edges the walk returns to its
  * source and tosses the coin. 65,536 moves at most.
- * P, alias: from fppr_graph_alias_tables; bm_entries, bm_weights,
+ * slots: from fppr_graph_alias_slots; bm_entries, bm_weights,
  * bm_counts, cap: from fppr_graph_big_moves with the same S (other contents
  * give wrong walks, never an out-of-bounds access). endpoints: device
  * u32[n_sources * R] (0xFFFFFFFF for a source id >= n); steps: device
  * u32[n_sources * R] or NULL. Narrow-layout graphs only; INVALID_ARGUMENT
  * as for fppr_run_alias, or for cap outside [1, 4096]. Asynchronous. */
-FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* slots,
                                         const uint64_t* bm_entries, const uint64_t* bm_weights,
                                         const uint32_t* bm_counts, uint32_t cap, uint32_t S, double alpha,
                                         uint32_t R, uint64_t seed, const uint32_t* sources,

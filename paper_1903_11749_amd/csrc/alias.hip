@@ -41,10 +41,12 @@ __global__ void k_alias_rows(const uint64_t* __restrict__ off, const uint32_t* _
 // w mod R of source row w div R, its move m draws Philox4x32-10 on (w mod R,
 // m, s, 0) as every other walk mode does. The pick: X = high 64 bits of
 // (x1:x0) * (d W), slot = X div W, keep the slot iff X mod W < P[slot], else
-// take alias[slot]. d W < 2^59 on narrow graphs, so X fits 64 bits.
+// take alias[slot]. d W < 2^59 on narrow graphs, so X fits 64 bits. Each
+// slot is one 16-byte record holding the threshold and both destination
+// ids, so a pick reads the row's offsets, its node line and one slot.
 __global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
-                             const Block* __restrict__ rec, const uint64_t* __restrict__ P,
-                             const uint32_t* __restrict__ alias, uint32_t n,
+                             const Block* __restrict__ rec, const ulonglong2* __restrict__ slots,
+                             uint32_t n,
                              const uint32_t* __restrict__ sources, uint64_t n_src, uint32_t R,
                              uint32_t T, uint32_t k0, uint32_t k1, uint32_t* __restrict__ ep,
                              uint32_t* __restrict__ steps) {
@@ -72,9 +74,9 @@ __global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* _
         uint64_t slot = W ? X / W : 0;
         if (slot >= d) slot = d - 1;  // only with tables or weights changed since the build
         const uint64_t U = X - slot * W;
-        uint64_t e = U < P[a + slot] ? slot : alias[a + slot];
-        if (e >= d) e = slot;
-        tail = col[a + e];
+        const ulonglong2 q = slots[a + slot];  // threshold, own id | alias's id << 32
+        const uint32_t t = U < q.x ? static_cast<uint32_t>(q.y) : static_cast<uint32_t>(q.y >> 32);
+        tail = t < n ? t : s;
       }
       ++len;
       ++m;
@@ -82,6 +84,21 @@ __global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* _
     }
     ep[wid] = tail;
     if (steps) steps[wid] = len;
+  }
+}
+
+// slot e of row v: {P[e], col[e] | col[alias[e]] << 32}
+__global__ void k_alias_slots(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
+                              uint32_t n_rows, const uint64_t* __restrict__ P,
+                              const uint32_t* __restrict__ alias, ulonglong2* __restrict__ slots) {
+  const uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  if (v >= n_rows) return;
+  const uint64_t a = off[v];
+  const uint64_t d = off[v + 1] - a;
+  for (uint64_t i = 0; i < d; ++i) {
+    uint64_t j = alias[a + i];
+    if (j >= d) j = i;
+    slots[a + i] = make_ulonglong2(P[a + i], col[a + i] | (static_cast<uint64_t>(col[a + j]) << 32));
   }
 }
 
@@ -109,13 +126,28 @@ FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, u
   return FPPR_OK;
 }
 
-FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
-                                    double alpha, uint32_t R, uint64_t seed, const uint32_t* sources,
-                                    uint64_t n_sources, uint32_t* endpoints, uint32_t* steps,
-                                    void* stream) {
+FPPR_API fppr_status fppr_graph_alias_slots(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+                                            uint64_t* slots, void* stream) {
+  if (!g) return invalid_arg("graph is NULL");
+  if (g->m && (!P || !alias || !slots)) return invalid_arg("P, alias or slots is NULL");
+  if (reinterpret_cast<uintptr_t>(slots) % 16) return invalid_arg("slots must be 16-byte aligned");
+  if (g->m == 0) return FPPR_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t blocks = static_cast<uint32_t>((g->n + kThreads - 1) / kThreads);
+  k_alias_slots<<<blocks, kThreads, 0, s>>>(g->off, g->col, g->n, P, alias,
+                                            reinterpret_cast<ulonglong2*>(slots));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "alias slots");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* slots, double alpha, uint32_t R,
+                                    uint64_t seed, const uint32_t* sources, uint64_t n_sources,
+                                    uint32_t* endpoints, uint32_t* steps, void* stream) {
   if (!g) return invalid_arg("graph is NULL");
   if (!g->narrow) return invalid_arg("alias walks need a graph with the narrow layout (32-bit row totals)");
-  if (!P || !alias || !endpoints) return invalid_arg("P, alias or endpoints is NULL");
+  if (!slots || !endpoints) return invalid_arg("slots or endpoints is NULL");
+  if (reinterpret_cast<uintptr_t>(slots) % 16) return invalid_arg("slots must be 16-byte aligned");
   const uint32_t T = fppr_alpha_threshold(alpha);
   if (T == 0) return invalid_arg("alpha must be in (0, 1)");
   if (R == 0) return invalid_arg("R must be at least 1");
@@ -127,7 +159,7 @@ FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* P, cons
   if (blocks > 65536) blocks = 65536;
   hipStream_t s = static_cast<hipStream_t>(stream);
   k_walk_alias<<<static_cast<uint32_t>(blocks), kThreads, 0, s>>>(
-      g->off, g->col, g->rec, P, alias, g->n, sources, n_sources, R, T,
+      g->off, g->col, g->rec, reinterpret_cast<const ulonglong2*>(slots), g->n, sources, n_sources, R, T,
       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), endpoints, steps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "alias walks");

@@ -32,14 +32,14 @@ __global__ void k_big_moves(const uint64_t* __restrict__ off, const uint32_t* __
 // Walks of the paper's design: at a node with 1 <= out-degree <= S the move
 // takes one big move of the node's table (the first entry whose inclusive
 // weight prefix exceeds X = high 64 bits of (x1:x0) * total weight, found by
-// binary search; a terminated
-// entry ends the walk at its end node, an active one continues there); at
-// any other node with out-edges an alias pick with the same draw (as in
-// k_walk_alias), then the coin x2 < T; a node without out-edges sends the
-// walk back to its source. Draws: Philox4x32-10 on (i, m, s, 0).
+// binary search; a terminated entry ends the walk at its end node, an active
+// one continues there); at any other node with out-edges an alias pick with
+// the same draw (as in k_walk_alias, one 16-byte slot), then the coin
+// x2 < T; a node without out-edges sends the walk back to its source.
+// Draws: Philox4x32-10 on (i, m, s, 0).
 __global__ void k_walk_bm(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
-                          const Block* __restrict__ rec, const uint64_t* __restrict__ P,
-                          const uint32_t* __restrict__ alias, const uint64_t* __restrict__ bm_e,
+                          const Block* __restrict__ rec, const ulonglong2* __restrict__ slots,
+                          const uint64_t* __restrict__ bm_e,
                           const uint64_t* __restrict__ bm_w, const uint32_t* __restrict__ bm_c,
                           uint32_t cap, uint32_t S, uint32_t n, const uint32_t* __restrict__ sources,
                           uint64_t n_src, uint32_t R, uint32_t T, uint32_t k0, uint32_t k1,
@@ -91,9 +91,9 @@ __global__ void k_walk_bm(const uint64_t* __restrict__ off, const uint32_t* __re
         uint64_t slot = W ? X / W : 0;
         if (slot >= d) slot = d - 1;
         const uint64_t U = X - slot * W;
-        uint64_t e = U < P[a + slot] ? slot : alias[a + slot];
-        if (e >= d) e = slot;
-        tail = col[a + e];
+        const ulonglong2 q = slots[a + slot];
+        const uint32_t t = U < q.x ? static_cast<uint32_t>(q.y) : static_cast<uint32_t>(q.y >> 32);
+        tail = t < n ? t : s;
         ++len;
       }
       ++m;
@@ -139,7 +139,7 @@ FPPR_API fppr_status fppr_graph_big_moves(const fppr_graph* g, uint32_t S, uint3
   return FPPR_OK;
 }
 
-FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
+FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* slots,
                                         const uint64_t* bm_entries, const uint64_t* bm_weights,
                                         const uint32_t* bm_counts, uint32_t cap, uint32_t S, double alpha,
                                         uint32_t R, uint64_t seed, const uint32_t* sources,
@@ -147,8 +147,9 @@ FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* P, 
                                         void* stream) {
   if (!g) return bm_invalid("graph is NULL");
   if (!g->narrow) return bm_invalid("these walks need a graph with the narrow layout (32-bit row totals)");
-  if (!P || !alias || !bm_entries || !bm_weights || !bm_counts || !endpoints)
+  if (!slots || !bm_entries || !bm_weights || !bm_counts || !endpoints)
     return bm_invalid("a table or the endpoints is NULL");
+  if (reinterpret_cast<uintptr_t>(slots) % 16) return bm_invalid("slots must be 16-byte aligned");
   const uint32_t T = fppr_alpha_threshold(alpha);
   if (T == 0) return bm_invalid("alpha must be in (0, 1)");
   if (R == 0) return bm_invalid("R must be at least 1");
@@ -161,7 +162,7 @@ FPPR_API fppr_status fppr_run_big_moves(const fppr_graph* g, const uint64_t* P, 
   if (blocks > 65536) blocks = 65536;
   hipStream_t s = static_cast<hipStream_t>(stream);
   k_walk_bm<<<static_cast<uint32_t>(blocks), 256, 0, s>>>(
-      g->off, g->col, g->rec, P, alias, bm_entries, bm_weights, bm_counts, cap, S, g->n, sources,
+      g->off, g->col, g->rec, reinterpret_cast<const ulonglong2*>(slots), bm_entries, bm_weights, bm_counts, cap, S, g->n, sources,
       n_sources, R, T, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), endpoints, steps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "big-move walks");

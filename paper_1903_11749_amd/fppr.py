@@ -147,12 +147,13 @@ _SIGS = [
     ("fppr_graph_build_pool", ctypes.c_int, [P, ctypes.POINTER(fppr_pool_opts), P]),
     ("fppr_graph_export_pool", ctypes.c_int, [P, P, ctypes.c_uint64, P]),
     ("fppr_graph_alias_tables", ctypes.c_int, [P, P, P, P, P]),
-    ("fppr_run_big_moves", ctypes.c_int, [P, P, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32,
+    ("fppr_run_big_moves", ctypes.c_int, [P, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32,
                                           ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
                                           ctypes.c_uint64, P, P, P]),
     ("fppr_graph_big_moves", ctypes.c_int, [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_double, P, P, P, P, ctypes.c_uint64, P]),
-    ("fppr_run_alias", ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
+    ("fppr_graph_alias_slots", ctypes.c_int, [P, P, P, P, P]),
+    ("fppr_run_alias", ctypes.c_int, [P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
                                       ctypes.c_uint64, P, P, P]),
     ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
     ("fppr_walks_for_guarantee", ctypes.c_uint64, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -234,9 +235,9 @@ def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def run_alias(graph, P, alias, alpha: float, R: int, seed: int, sources=None, steps=True, stream=None):
-    """Walks that pick with alias tables (fppr_run_alias). P, alias: the
-    tensors Graph.alias_tables returned. sources: None (every node), a numpy
+def run_alias(graph, slots, alpha: float, R: int, seed: int, sources=None, steps=True, stream=None):
+    """Walks that pick with alias tables (fppr_run_alias). slots: the tensor
+    Graph.alias_slots returned. sources: None (every node), a numpy
     uint32 array or a device int32 tensor. Returns device int32 tensors
     (endpoints, steps or None) of n_sources * R walks, walk-major per source."""
     import torch
@@ -250,15 +251,15 @@ def run_alias(graph, P, alias, alpha: float, R: int, seed: int, sources=None, st
         n_src = int(src.numel())
     ep = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda")
     st = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda") if steps else None
-    _check(lib().fppr_run_alias(graph.handle, _dptr(P), _dptr(alias), float(alpha), int(R), int(seed),
+    _check(lib().fppr_run_alias(graph.handle, _dptr(slots), float(alpha), int(R), int(seed),
                                 _dptr(src), n_src, _dptr(ep), _dptr(st), _stream_ptr(stream)))
     return ep[:n_src * R], (st[:n_src * R] if st is not None else None)
 
 
-def run_big_moves(graph, P, alias, bm, S: int, alpha: float, R: int, seed: int, sources=None,
+def run_big_moves(graph, slots, bm, S: int, alpha: float, R: int, seed: int, sources=None,
                   steps=True, stream=None):
-    """Walks of the paper's design (fppr_run_big_moves). P, alias: from
-    Graph.alias_tables; bm: the (entries, weights, counts) Graph.big_moves
+    """Walks of the paper's design (fppr_run_big_moves). slots: from
+    Graph.alias_slots; bm: the (entries, weights, counts) Graph.big_moves
     returned for the same S. Returns device int32 tensors (endpoints, steps
     or None) of n_sources * R walks, walk-major per source."""
     import torch
@@ -273,7 +274,7 @@ def run_big_moves(graph, P, alias, bm, S: int, alpha: float, R: int, seed: int, 
         n_src = int(src.numel())
     ep = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda")
     st = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda") if steps else None
-    _check(lib().fppr_run_big_moves(graph.handle, _dptr(P), _dptr(alias), _dptr(ent), _dptr(wts), _dptr(cnt),
+    _check(lib().fppr_run_big_moves(graph.handle, _dptr(slots), _dptr(ent), _dptr(wts), _dptr(cnt),
                                     int(ent.shape[1]), int(S), float(alpha), int(R), int(seed), _dptr(src),
                                     n_src, _dptr(ep), _dptr(st), _stream_ptr(stream)))
     return ep[:n_src * R], (st[:n_src * R] if st is not None else None)
@@ -364,6 +365,17 @@ class Graph:
                                              _stream_ptr(stream)))
         self._alias_scratch = scratch  # kept alive until the next call; the launch is asynchronous
         return P[:m], al[:m]
+
+    def alias_slots(self, P, alias, stream=None):
+        """Packed 16-byte alias slots (fppr_graph_alias_slots) from the
+        tensors alias_tables returned: a device int64 tensor [m, 2]."""
+        import torch
+
+        m = self.info()["m"]
+        slots = torch.empty((max(m, 1), 2), dtype=torch.int64, device="cuda")
+        _check(lib().fppr_graph_alias_slots(self._h, _dptr(P), _dptr(alias), _dptr(slots),
+                                            _stream_ptr(stream)))
+        return slots[:m]
 
     def big_moves(self, S: int, d: int, cap: int, alpha: float, slots: int = 16384, stream=None):
         """Exact big-move tables (fppr_graph_big_moves): device tensors

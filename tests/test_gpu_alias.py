@@ -70,6 +70,18 @@ def test_alias_tables_equal_oracle(fp, name):
         G = fp.Graph(g, layout=lay)
         P, al = fetch(fp, G)
         assert rows_equal(g, P, al, range(g.n)) == []
+        # packed slots: threshold, own destination, the alias's destination
+        import torch
+
+        Pt, alt = G.alias_tables()
+        sl = G.alias_slots(Pt, alt)
+        torch.cuda.synchronize()
+        sl = sl.cpu().numpy().view(np.uint64)
+        rows = np.repeat(np.arange(g.n), g.degrees())
+        first = g.row_offsets[:-1].astype(np.int64)[rows]
+        assert np.array_equal(sl[:, 0], P)
+        want = g.col.astype(np.uint64) | (g.col[first + al.astype(np.int64)].astype(np.uint64) << np.uint64(32))
+        assert np.array_equal(sl[:, 1], want)
         # a second call on the same graph gives the same tables
         P2, al2 = fetch(fp, G)
         assert np.array_equal(P, P2) and np.array_equal(al, al2)
@@ -106,9 +118,10 @@ def test_alias_walks_equal_oracle(fp, name):
     say(f"case: alias walks, {name}")
     G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
     P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
     src = np.concatenate([np.arange(0, g.n, 37), [g.n - 1, 0, 0]]).astype(np.uint32)
     T = fp.fppr_alpha_threshold(0.15)
-    ep, st = fp.run_alias(G, P, al, 0.15, 24, 123456789012, sources=src)
+    ep, st = fp.run_alias(G, sl, 0.15, 24, 123456789012, sources=src)
     torch.cuda.synchronize()
     ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, T, 123456789012, 24, src)
     assert np.array_equal(ep.cpu().numpy().view(np.uint32).reshape(len(src), 24), ref_ep)
@@ -122,23 +135,24 @@ def test_alias_walks_edges(fp):
     say("case: alias walks, invalid source, all nodes, wide graph refused")
     G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
     P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
     src = np.array([3, g.n, 7], dtype=np.uint32)
-    ep, st = fp.run_alias(G, P, al, 0.3, 5, 1, sources=src)
+    ep, st = fp.run_alias(G, sl, 0.3, 5, 1, sources=src)
     torch.cuda.synchronize()
     e = ep.cpu().numpy().view(np.uint32).reshape(3, 5)
     assert np.all(e[1] == 0xFFFFFFFF) and np.all(st.cpu().numpy().reshape(3, 5)[1] == 0)
     ref_ep, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.3), 1, 5, [3, 7])
     assert np.array_equal(e[[0, 2]], ref_ep)
-    ep_all, _ = fp.run_alias(G, P, al, 0.3, 2, 1, steps=False)
+    ep_all, _ = fp.run_alias(G, sl, 0.3, 2, 1, steps=False)
     torch.cuda.synchronize()
     ref_all, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.3), 1, 2, range(g.n))
     assert np.array_equal(ep_all.cpu().numpy().view(np.uint32).reshape(g.n, 2), ref_all)
     Gw = fp.Graph(g, layout=fp.FPPR_LAYOUT_WIDE)
     Pw, alw = Gw.alias_tables()
     with pytest.raises(fp.FpprError):
-        fp.run_alias(Gw, Pw, alw, 0.3, 5, 1, sources=src)
+        fp.run_alias(Gw, Gw.alias_slots(Pw, alw), 0.3, 5, 1, sources=src)
     with pytest.raises(fp.FpprError):
-        fp.run_alias(G, P, al, 1.5, 5, 1, sources=src)
+        fp.run_alias(G, sl, 1.5, 5, 1, sources=src)
 
 
 def test_alias_walks_scale20(fp):
@@ -151,11 +165,12 @@ def test_alias_walks_scale20(fp):
     G = fp.Graph(g)
     assert G.layout() == fp.FPPR_LAYOUT_NARROW
     P, al = G.alias_tables()
-    fp.run_alias(G, P, al, 0.15, 16, 3)
+    sl = G.alias_slots(P, al)
+    fp.run_alias(G, sl, 0.15, 16, 3)
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
-    ep, st = fp.run_alias(G, P, al, 0.15, 16, 3)
+    ep, st = fp.run_alias(G, sl, 0.15, 16, 3)
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)

@@ -122,9 +122,10 @@ def test_paper_design_walks_equal_oracle(fp, case):
     say(f"case: big-move walks, {name}")
     G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
     P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
     bm = G.big_moves(S, d, cap, alpha)
     src = np.concatenate([np.arange(0, g.n, 13), [g.n - 1, 0, 0, g.n]]).astype(np.uint32)
-    ep, st = fp.run_big_moves(G, P, al, bm, S, alpha, 16, 987654321, sources=src)
+    ep, st = fp.run_big_moves(G, sl, bm, S, alpha, 16, 987654321, sources=src)
     torch.cuda.synchronize()
     ep = ep.cpu().numpy().view(np.uint32).reshape(len(src), 16)
     st = st.cpu().numpy().view(np.uint32).reshape(len(src), 16)
@@ -145,12 +146,13 @@ def test_paper_design_walks_scale20(fp):
     say("case: big-move walks, R-MAT scale 20, R = 16 from every node")
     G = fp.Graph(g)
     P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
     bm = G.big_moves(S, d, cap, alpha)
-    fp.run_big_moves(G, P, al, bm, S, alpha, 16, 3)
+    fp.run_big_moves(G, sl, bm, S, alpha, 16, 3)
     torch.cuda.synchronize()
     res = {}
-    for label, call in (("big moves + alias", lambda: fp.run_big_moves(G, P, al, bm, S, alpha, 16, 3)),
-                        ("alias only", lambda: fp.run_alias(G, P, al, alpha, 16, 3))):
+    for label, call in (("big moves + alias", lambda: fp.run_big_moves(G, sl, bm, S, alpha, 16, 3)),
+                        ("alias only", lambda: fp.run_alias(G, sl, alpha, 16, 3))):
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0.record()
         ep, st = call()
