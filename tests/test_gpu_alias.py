@@ -199,3 +199,48 @@ def test_alias_walks_scale20(fp):
     s_ = st.cpu().numpy().view(np.uint32).reshape(g.n, 16)[sample]
     ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.15), 3, 16, sample)
     assert np.array_equal(e, ref_ep) and np.array_equal(s_, ref_st)
+
+
+def test_alias_walks_scale24_ab(fp):
+    """R-MAT scale 24 (the benchmark graph), R = 16 from every node, no
+    stitching: alias walks against the prefix-tree path on the same walks
+    (equal step counts, since coins do not depend on the picks), both timed;
+    16 sampled walks recomputed by the oracle."""
+    import torch
+
+    g = synth.scale24_graph()
+    say(f"case: alias walks, R-MAT scale 24 (n={g.n}, m={g.m}), R = 16 from every node")
+    G = fp.Graph(g)
+    assert G.layout() == fp.FPPR_LAYOUT_NARROW
+    P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
+    del P, al
+    fp.run_alias(G, sl, 0.15, 16, 3, steps=False)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    ep, st = fp.run_alias(G, sl, 0.15, 16, 3)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    steps = int(st.to(torch.int64).sum().item())
+    say(f"  alias walks: {steps} steps in {ms:.2f} ms: {steps / ms * 1e3:.3e} walk-steps/s")
+    prm = fp.make_params(0.15, 16, 3, 1, False, False, True, True)
+    ws = torch.empty((fp.fppr_plan(G, prm, g.n) + 7) // 8, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        out = fp.alloc_outputs(g.n, 16, 1, counts=False, digests=True, stats=True)
+        prof = fp.Profile()
+        out.profile = prof
+        fp.fppr_run(G, prm, None, g.n, ws, out, None)
+        torch.cuda.synchronize()
+    walk_ms, _ = prof.read()
+    kern_ms, _ = prof.read_walk()
+    cdf_steps = out.stats_dict()["steps"]
+    say(f"  prefix-tree path: {cdf_steps} steps, walk phase {walk_ms:.2f} ms (walk kernel {kern_ms:.2f} ms): "
+        f"{cdf_steps / walk_ms * 1e3:.3e} walk-steps/s")
+    assert cdf_steps == steps
+    src = np.array([5, 77777, 4_000_000, 16_000_000], dtype=np.uint32)
+    e = ep.cpu().numpy().view(np.uint32).reshape(g.n, 16)[src, :4]
+    s_ = st.cpu().numpy().view(np.uint32).reshape(g.n, 16)[src, :4]
+    ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.15), 3, 4, src)
+    assert np.array_equal(e, ref_ep) and np.array_equal(s_, ref_st)
