@@ -200,6 +200,14 @@ FPPR_API fppr_status fppr_graph_alias_tables(const fppr_graph* g, uint64_t* P, u
 FPPR_API fppr_status fppr_graph_alias_slots(const fppr_graph* g, const uint64_t* P, const uint32_t* alias,
                                             uint64_t* slots, void* stream);
 
+/* One 16-byte record per node for the alias walks: nodes[2v] = the row's
+ * first edge, nodes[2v + 1] = W(v) | deg(v) << 32 (row total and out-degree),
+ * so a move reads its node in one line. nodes: device u64[2 n], 16-byte
+ * aligned, the caller's. Narrow-layout graphs only (W < 2^32).
+ * Asynchronous on `stream`; INVALID_ARGUMENT for a wide graph, NULL or a
+ * misaligned nodes. */
+FPPR_API fppr_status fppr_graph_alias_nodes(const fppr_graph* g, uint64_t* nodes, void* stream);
+
 /* Walks that pick each edge with the alias tables (Sec. 2.2 and Sec. 2.1's
  * walk, Algorithm 2's coin): walk w (w = row * R + i) starts at
  * sources[row] (or node row when sources is NULL, then n_sources must be n);
@@ -209,14 +217,15 @@ FPPR_API fppr_status fppr_graph_alias_slots(const fppr_graph* g, const uint64_t*
  * x2 < T(alpha); a node without out-edges sends the walk back to s; 65,536
  * moves at most. No stitching. endpoints: device u32[n_sources * R] (the end
  * node; 0xFFFFFFFF for a source id >= n); steps: device u32[n_sources * R]
- * or NULL. slots: what fppr_graph_alias_slots packed for this graph (other
- * contents give wrong walks, never an out-of-bounds access).
+ * or NULL. nodes, slots: what fppr_graph_alias_nodes and
+ * fppr_graph_alias_slots built for this graph (other contents give wrong
+ * walks, never an out-of-bounds access).
  * Needs a narrow-layout graph (d W < 2^59 keeps X within 64 bits);
  * INVALID_ARGUMENT otherwise, for alpha outside (0, 1), R == 0, NULL
  * pointers or n_sources * R > 2^40. Asynchronous on `stream`. */
-FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* slots, double alpha, uint32_t R,
-                                    uint64_t seed, const uint32_t* sources, uint64_t n_sources,
-                                    uint32_t* endpoints, uint32_t* steps, void* stream);
+FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* nodes, const uint64_t* slots,
+                                    double alpha, uint32_t R, uint64_t seed, const uint32_t* sources,
+                                    uint64_t n_sources, uint32_t* endpoints, uint32_t* steps, void* stream);
 
 /* Exact big moves of every small node (Sec. 4.2, Algorithm 4; Lemma 2):
  * for each node v with 1 <= out-degree <= S, the distribution of a walk's

@@ -42,11 +42,11 @@ __global__ void k_alias_rows(const uint64_t* __restrict__ off, const uint32_t* _
 // m, s, 0) as every other walk mode does. The pick: X = high 64 bits of
 // (x1:x0) * (d W), slot = X div W, keep the slot iff X mod W < P[slot], else
 // take alias[slot]. d W < 2^59 on narrow graphs, so X fits 64 bits. Each
-// slot is one 16-byte record holding the threshold and both destination
-// ids, so a pick reads the row's offsets, its node line and one slot.
-__global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
-                             const Block* __restrict__ rec, const ulonglong2* __restrict__ slots,
-                             uint32_t n,
+// node is one 16-byte record (row start, total and degree) and each slot one
+// 16-byte record (threshold and both destination ids), so a move reads two
+// lines.
+__global__ void k_walk_alias(const ulonglong2* __restrict__ nodes, const ulonglong2* __restrict__ slots,
+                             uint64_t m, uint32_t n,
                              const uint32_t* __restrict__ sources, uint64_t n_src, uint32_t R,
                              uint32_t T, uint32_t k0, uint32_t k1, uint32_t* __restrict__ ep,
                              uint32_t* __restrict__ steps) {
@@ -61,15 +61,17 @@ __global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* _
       if (steps) steps[wid] = 0;
       continue;
     }
-    uint32_t tail = s, len = 0, m = 0;
+    uint32_t tail = s, len = 0, mv = 0;
     for (;;) {
-      const U4 x = philox10(i, m, s, 0u, k0, k1);
-      const uint64_t a = off[tail];
-      const uint64_t d = off[tail + 1] - a;
+      const U4 x = philox10(i, mv, s, 0u, k0, k1);
+      const ulonglong2 nd = nodes[tail];  // row start, total | degree << 32
+      const uint64_t a = nd.x;
+      uint64_t d = nd.y >> 32;
+      if (a > m || d > m - a) d = 0;  // only with a node table from another graph
       if (d == 0) {
         tail = s;
       } else {
-        const uint64_t W = rec[tail].key[0];
+        const uint64_t W = static_cast<uint32_t>(nd.y);
         const uint64_t X = scaled_draw(x.x0, x.x1, d * W);
         uint64_t slot = W ? X / W : 0;
         if (slot >= d) slot = d - 1;  // only with tables or weights changed since the build
@@ -79,12 +81,22 @@ __global__ void k_walk_alias(const uint64_t* __restrict__ off, const uint32_t* _
         tail = t < n ? t : s;
       }
       ++len;
-      ++m;
-      if (x.x2 < T || m == kMoveCap) break;
+      ++mv;
+      if (x.x2 < T || mv == kMoveCap) break;
     }
     ep[wid] = tail;
     if (steps) steps[wid] = len;
   }
+}
+
+// node v: {row start, W(v) | deg(v) << 32} (W < 2^32 on narrow graphs)
+__global__ void k_alias_nodes(const uint64_t* __restrict__ off, const Block* __restrict__ rec,
+                              uint32_t n, ulonglong2* __restrict__ nodes) {
+  const uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t a = off[v], d = off[v + 1] - a;
+  const uint64_t W = d ? (rec[v].key[0] & 0xFFFFFFFFull) : 0;
+  nodes[v] = make_ulonglong2(a, W | (d << 32));
 }
 
 // slot e of row v: {P[e], col[e] | col[alias[e]] << 32}
@@ -141,13 +153,27 @@ FPPR_API fppr_status fppr_graph_alias_slots(const fppr_graph* g, const uint64_t*
   return FPPR_OK;
 }
 
-FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* slots, double alpha, uint32_t R,
-                                    uint64_t seed, const uint32_t* sources, uint64_t n_sources,
-                                    uint32_t* endpoints, uint32_t* steps, void* stream) {
+FPPR_API fppr_status fppr_graph_alias_nodes(const fppr_graph* g, uint64_t* nodes, void* stream) {
+  if (!g) return invalid_arg("graph is NULL");
+  if (!g->narrow) return invalid_arg("alias node records need the narrow layout (32-bit row totals)");
+  if (!nodes) return invalid_arg("nodes is NULL");
+  if (reinterpret_cast<uintptr_t>(nodes) % 16) return invalid_arg("nodes must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t blocks = static_cast<uint32_t>((g->n + kThreads - 1) / kThreads);
+  k_alias_nodes<<<blocks, kThreads, 0, s>>>(g->off, g->rec, g->n, reinterpret_cast<ulonglong2*>(nodes));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "alias nodes");
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* nodes, const uint64_t* slots,
+                                    double alpha, uint32_t R, uint64_t seed, const uint32_t* sources,
+                                    uint64_t n_sources, uint32_t* endpoints, uint32_t* steps, void* stream) {
   if (!g) return invalid_arg("graph is NULL");
   if (!g->narrow) return invalid_arg("alias walks need a graph with the narrow layout (32-bit row totals)");
-  if (!slots || !endpoints) return invalid_arg("slots or endpoints is NULL");
-  if (reinterpret_cast<uintptr_t>(slots) % 16) return invalid_arg("slots must be 16-byte aligned");
+  if (!nodes || !slots || !endpoints) return invalid_arg("nodes, slots or endpoints is NULL");
+  if (reinterpret_cast<uintptr_t>(slots) % 16 || reinterpret_cast<uintptr_t>(nodes) % 16)
+    return invalid_arg("nodes and slots must be 16-byte aligned");
   const uint32_t T = fppr_alpha_threshold(alpha);
   if (T == 0) return invalid_arg("alpha must be in (0, 1)");
   if (R == 0) return invalid_arg("R must be at least 1");
@@ -159,7 +185,8 @@ FPPR_API fppr_status fppr_run_alias(const fppr_graph* g, const uint64_t* slots, 
   if (blocks > 65536) blocks = 65536;
   hipStream_t s = static_cast<hipStream_t>(stream);
   k_walk_alias<<<static_cast<uint32_t>(blocks), kThreads, 0, s>>>(
-      g->off, g->col, g->rec, reinterpret_cast<const ulonglong2*>(slots), g->n, sources, n_sources, R, T,
+      reinterpret_cast<const ulonglong2*>(nodes), reinterpret_cast<const ulonglong2*>(slots), g->m, g->n,
+      sources, n_sources, R, T,
       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), endpoints, steps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "alias walks");

@@ -153,7 +153,8 @@ _SIGS = [
     ("fppr_graph_big_moves", ctypes.c_int, [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_double, P, P, P, P, ctypes.c_uint64, P]),
     ("fppr_graph_alias_slots", ctypes.c_int, [P, P, P, P, P]),
-    ("fppr_run_alias", ctypes.c_int, [P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
+    ("fppr_graph_alias_nodes", ctypes.c_int, [P, P, P]),
+    ("fppr_run_alias", ctypes.c_int, [P, P, P, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, P,
                                       ctypes.c_uint64, P, P, P]),
     ("fppr_alpha_threshold", ctypes.c_uint32, [ctypes.c_double]),
     ("fppr_walks_for_guarantee", ctypes.c_uint64, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -235,9 +236,9 @@ def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def run_alias(graph, slots, alpha: float, R: int, seed: int, sources=None, steps=True, stream=None):
-    """Walks that pick with alias tables (fppr_run_alias). slots: the tensor
-    Graph.alias_slots returned. sources: None (every node), a numpy
+def run_alias(graph, nodes, slots, alpha: float, R: int, seed: int, sources=None, steps=True, stream=None):
+    """Walks that pick with alias tables (fppr_run_alias). nodes, slots: the
+    tensors Graph.alias_nodes and Graph.alias_slots returned. sources: None (every node), a numpy
     uint32 array or a device int32 tensor. Returns device int32 tensors
     (endpoints, steps or None) of n_sources * R walks, walk-major per source."""
     import torch
@@ -251,7 +252,7 @@ def run_alias(graph, slots, alpha: float, R: int, seed: int, sources=None, steps
         n_src = int(src.numel())
     ep = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda")
     st = torch.empty(max(n_src * R, 1), dtype=torch.int32, device="cuda") if steps else None
-    _check(lib().fppr_run_alias(graph.handle, _dptr(slots), float(alpha), int(R), int(seed),
+    _check(lib().fppr_run_alias(graph.handle, _dptr(nodes), _dptr(slots), float(alpha), int(R), int(seed),
                                 _dptr(src), n_src, _dptr(ep), _dptr(st), _stream_ptr(stream)))
     return ep[:n_src * R], (st[:n_src * R] if st is not None else None)
 
@@ -376,6 +377,16 @@ class Graph:
         _check(lib().fppr_graph_alias_slots(self._h, _dptr(P), _dptr(alias), _dptr(slots),
                                             _stream_ptr(stream)))
         return slots[:m]
+
+    def alias_nodes(self, stream=None):
+        """16-byte node records for the alias walks (fppr_graph_alias_nodes):
+        a device int64 tensor [n, 2]."""
+        import torch
+
+        n = self.info()["n"]
+        nodes = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+        _check(lib().fppr_graph_alias_nodes(self._h, _dptr(nodes), _stream_ptr(stream)))
+        return nodes
 
     def big_moves(self, S: int, d: int, cap: int, alpha: float, slots: int = 16384, stream=None):
         """Exact big-move tables (fppr_graph_big_moves): device tensors

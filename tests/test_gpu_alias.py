@@ -82,6 +82,15 @@ def test_alias_tables_equal_oracle(fp, name):
         assert np.array_equal(sl[:, 0], P)
         want = g.col.astype(np.uint64) | (g.col[first + al.astype(np.int64)].astype(np.uint64) << np.uint64(32))
         assert np.array_equal(sl[:, 1], want)
+        if lay == fp.FPPR_LAYOUT_NARROW:
+            # node records: row start, total | degree << 32
+            ndr = G.alias_nodes()
+            torch.cuda.synchronize()
+            ndr = ndr.cpu().numpy().view(np.uint64)
+            W = np.zeros(g.n, dtype=np.uint64)
+            np.add.at(W, rows, g.w.astype(np.uint64))
+            assert np.array_equal(ndr[:, 0], g.row_offsets[:-1].astype(np.uint64))
+            assert np.array_equal(ndr[:, 1], W | (g.degrees().astype(np.uint64) << np.uint64(32)))
         # a second call on the same graph gives the same tables
         P2, al2 = fetch(fp, G)
         assert np.array_equal(P, P2) and np.array_equal(al, al2)
@@ -119,9 +128,10 @@ def test_alias_walks_equal_oracle(fp, name):
     G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
     P, al = G.alias_tables()
     sl = G.alias_slots(P, al)
+    nd = G.alias_nodes()
     src = np.concatenate([np.arange(0, g.n, 37), [g.n - 1, 0, 0]]).astype(np.uint32)
     T = fp.fppr_alpha_threshold(0.15)
-    ep, st = fp.run_alias(G, sl, 0.15, 24, 123456789012, sources=src)
+    ep, st = fp.run_alias(G, nd, sl, 0.15, 24, 123456789012, sources=src)
     torch.cuda.synchronize()
     ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, T, 123456789012, 24, src)
     assert np.array_equal(ep.cpu().numpy().view(np.uint32).reshape(len(src), 24), ref_ep)
@@ -136,23 +146,24 @@ def test_alias_walks_edges(fp):
     G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
     P, al = G.alias_tables()
     sl = G.alias_slots(P, al)
+    nd = G.alias_nodes()
     src = np.array([3, g.n, 7], dtype=np.uint32)
-    ep, st = fp.run_alias(G, sl, 0.3, 5, 1, sources=src)
+    ep, st = fp.run_alias(G, nd, sl, 0.3, 5, 1, sources=src)
     torch.cuda.synchronize()
     e = ep.cpu().numpy().view(np.uint32).reshape(3, 5)
     assert np.all(e[1] == 0xFFFFFFFF) and np.all(st.cpu().numpy().reshape(3, 5)[1] == 0)
     ref_ep, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.3), 1, 5, [3, 7])
     assert np.array_equal(e[[0, 2]], ref_ep)
-    ep_all, _ = fp.run_alias(G, sl, 0.3, 2, 1, steps=False)
+    ep_all, _ = fp.run_alias(G, nd, sl, 0.3, 2, 1, steps=False)
     torch.cuda.synchronize()
     ref_all, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.3), 1, 2, range(g.n))
     assert np.array_equal(ep_all.cpu().numpy().view(np.uint32).reshape(g.n, 2), ref_all)
     Gw = fp.Graph(g, layout=fp.FPPR_LAYOUT_WIDE)
     Pw, alw = Gw.alias_tables()
     with pytest.raises(fp.FpprError):
-        fp.run_alias(Gw, Gw.alias_slots(Pw, alw), 0.3, 5, 1, sources=src)
+        fp.run_alias(Gw, nd, Gw.alias_slots(Pw, alw), 0.3, 5, 1, sources=src)
     with pytest.raises(fp.FpprError):
-        fp.run_alias(G, sl, 1.5, 5, 1, sources=src)
+        fp.run_alias(G, nd, sl, 1.5, 5, 1, sources=src)
 
 
 def test_alias_walks_scale20(fp):
@@ -166,11 +177,12 @@ def test_alias_walks_scale20(fp):
     assert G.layout() == fp.FPPR_LAYOUT_NARROW
     P, al = G.alias_tables()
     sl = G.alias_slots(P, al)
-    fp.run_alias(G, sl, 0.15, 16, 3)
+    nd = G.alias_nodes()
+    fp.run_alias(G, nd, sl, 0.15, 16, 3)
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
-    ep, st = fp.run_alias(G, sl, 0.15, 16, 3)
+    ep, st = fp.run_alias(G, nd, sl, 0.15, 16, 3)
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
@@ -214,12 +226,13 @@ def test_alias_walks_scale24_ab(fp):
     assert G.layout() == fp.FPPR_LAYOUT_NARROW
     P, al = G.alias_tables()
     sl = G.alias_slots(P, al)
+    nd = G.alias_nodes()
     del P, al
-    fp.run_alias(G, sl, 0.15, 16, 3, steps=False)
+    fp.run_alias(G, nd, sl, 0.15, 16, 3, steps=False)
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
-    ep, st = fp.run_alias(G, sl, 0.15, 16, 3)
+    ep, st = fp.run_alias(G, nd, sl, 0.15, 16, 3)
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)

@@ -123,6 +123,7 @@ def test_paper_design_walks_equal_oracle(fp, case):
     G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
     P, al = G.alias_tables()
     sl = G.alias_slots(P, al)
+    nd = G.alias_nodes()
     bm = G.big_moves(S, d, cap, alpha)
     src = np.concatenate([np.arange(0, g.n, 13), [g.n - 1, 0, 0, g.n]]).astype(np.uint32)
     ep, st = fp.run_big_moves(G, sl, bm, S, alpha, 16, 987654321, sources=src)
@@ -147,12 +148,13 @@ def test_paper_design_walks_scale20(fp):
     G = fp.Graph(g)
     P, al = G.alias_tables()
     sl = G.alias_slots(P, al)
+    nd = G.alias_nodes()
     bm = G.big_moves(S, d, cap, alpha)
     fp.run_big_moves(G, sl, bm, S, alpha, 16, 3)
     torch.cuda.synchronize()
     res = {}
     for label, call in (("big moves + alias", lambda: fp.run_big_moves(G, sl, bm, S, alpha, 16, 3)),
-                        ("alias only", lambda: fp.run_alias(G, sl, alpha, 16, 3))):
+                        ("alias only", lambda: fp.run_alias(G, nd, sl, alpha, 16, 3))):
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0.record()
         ep, st = call()
