@@ -22,18 +22,27 @@ __host__ __device__ inline void alias_row(const uint32_t* w, uint64_t d, uint64_
     if (p < W) small[ns++] = static_cast<uint32_t>(i);
     else if (p > W) large[nl++] = static_cast<uint32_t>(i);
   }
-  uint64_t hs = 0, hl = 0;
+  // The head of the large set keeps its threshold in a register until it
+  // leaves the set (the same arithmetic; no memory round trip per step).
+  uint64_t hs = 0, hl = 0, py = 0;
+  bool held = false;
   while (hl < nl && hs < ns) {
     const uint32_t x = small[hs++];
     const uint32_t y = large[hl];
+    if (!held) {
+      py = P[y];
+      held = true;
+    }
     alias[x] = y;
-    const uint64_t py = P[y] - (W - P[x]);
-    P[y] = py;
+    py -= W - P[x];
     if (py <= W) {
+      P[y] = py;
+      held = false;
       ++hl;
       if (py < W) small[ns++] = y;
     }
   }
+  if (held) P[large[hl]] = py;
 }
 
 }  // namespace fppr
