@@ -99,18 +99,25 @@ __global__ void k_alias_nodes(const uint64_t* __restrict__ off, const Block* __r
   nodes[v] = make_ulonglong2(a, W | (d << 32));
 }
 
-// slot e of row v: {P[e], col[e] | col[alias[e]] << 32}
+// slot e of row v: {P[e], col[e] | col[alias[e]] << 32}. One wave per row
+// (grid-stride over rows), its lanes striding the row's edges, so a hub's
+// slots are written 64 at a time.
+constexpr uint32_t kSlotBlocks = 16384;
+
 __global__ void k_alias_slots(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
                               uint32_t n_rows, const uint64_t* __restrict__ P,
                               const uint32_t* __restrict__ alias, ulonglong2* __restrict__ slots) {
-  const uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-  if (v >= n_rows) return;
-  const uint64_t a = off[v];
-  const uint64_t d = off[v + 1] - a;
-  for (uint64_t i = 0; i < d; ++i) {
-    uint64_t j = alias[a + i];
-    if (j >= d) j = i;
-    slots[a + i] = make_ulonglong2(P[a + i], col[a + i] | (static_cast<uint64_t>(col[a + j]) << 32));
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+  for (uint64_t v = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) >> 6; v < n_rows;
+       v += waves) {
+    const uint64_t a = off[v];
+    const uint64_t d = off[v + 1] - a;
+    for (uint64_t i = lane; i < d; i += 64) {
+      uint64_t j = alias[a + i];
+      if (j >= d) j = i;
+      slots[a + i] = make_ulonglong2(P[a + i], col[a + i] | (static_cast<uint64_t>(col[a + j]) << 32));
+    }
   }
 }
 
@@ -145,9 +152,10 @@ FPPR_API fppr_status fppr_graph_alias_slots(const fppr_graph* g, const uint64_t*
   if (reinterpret_cast<uintptr_t>(slots) % 16) return invalid_arg("slots must be 16-byte aligned");
   if (g->m == 0) return FPPR_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint32_t blocks = static_cast<uint32_t>((g->n + kThreads - 1) / kThreads);
-  k_alias_slots<<<blocks, kThreads, 0, s>>>(g->off, g->col, g->n, P, alias,
-                                            reinterpret_cast<ulonglong2*>(slots));
+  uint64_t blocks = (static_cast<uint64_t>(g->n) * 64 + kThreads - 1) / kThreads;
+  if (blocks > kSlotBlocks) blocks = kSlotBlocks;
+  k_alias_slots<<<static_cast<uint32_t>(blocks), kThreads, 0, s>>>(g->off, g->col, g->n, P, alias,
+                                                                    reinterpret_cast<ulonglong2*>(slots));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "alias slots");
   return FPPR_OK;
