@@ -393,6 +393,30 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
                               uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
                               const fppr_out* out, void* stream);
 
+/* Size of the device workspace that fppr_run_static uses (per GPU). */
+#define FPPR_STATIC_SCRATCH_BYTES (64ull << 20)
+
+/* fppr_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same walks, counting and outputs as fppr_run, with its workspace taken
+ * from a fixed device array of FPPR_STATIC_SCRATCH_BYTES inside the library
+ * (one per GPU, created when the library's code is loaded on that GPU and
+ * kept until the process ends). No hipMalloc, hipFree or other allocation is
+ * made. The array's address is looked up on the first call on each device.
+ * Runs larger than the array go in blocks of sources as fppr_run does with
+ * a small workspace; results are identical to fppr_run's. `out` is the
+ * caller's, as for fppr_run; the graph's device must be the current device.
+ * INVALID_ARGUMENT as for fppr_run, or when one source needs more workspace
+ * than the array holds, or when out->endpoints is given and the whole run
+ * does not fit the array. Asynchronous on `stream`.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two streams, two host threads) race and give wrong results; calls
+ * in sequence on one stream are safe, and each clears what it needs.
+ * There is no fppr_run_check for this form: a source id >= n gets no walks,
+ * so its row has n_distinct 0 and a top-k of padding entries. */
+FPPR_API fppr_status fppr_run_static(fppr_graph* g, const fppr_params* p, const uint32_t* sources,
+                                     uint64_t n_sources, const fppr_out* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many graphs or source sets in one persistent walk launch.
  * Algorithm 2 runs all walks of all nodes together; a batch extends that to

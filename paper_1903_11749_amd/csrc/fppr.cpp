@@ -622,6 +622,64 @@ FPPR_API fppr_status fppr_run(fppr_graph* g, const fppr_params* p, const uint32_
   return FPPR_OK;
 }
 
+}  // extern "C"
+
+// Workspace of fppr_run_static: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends. Host code never passes
+// the array's name to a kernel or a copy (on the host it is only a stand-in
+// for the symbol); it uses the device address hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[FPPR_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's copy of `scratch` (looked up on the
+// first call on that device)
+fppr_status static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return invalid("device index out of range for the static workspace");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(static workspace)");
+    if (!ptr) return invalid("hipGetSymbolAddress returned no address for the static workspace");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FPPR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+FPPR_API fppr_status fppr_run_static(fppr_graph* g, const fppr_params* p, const uint32_t* sources,
+                                     uint64_t n_sources, const fppr_out* out, void* stream) {
+  fppr_status st = check_params(g, p);
+  if (st != FPPR_OK) return st;
+  if (!out) return invalid("out is NULL");
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != g->device) return invalid("fppr_run_static: the graph's device must be the current device");
+  uint64_t one = 0, all = 0;
+  fppr_plan(g, p, 1, &one);
+  fppr_plan(g, p, n_sources, &all);
+  if (one > FPPR_STATIC_SCRATCH_BYTES)
+    return invalid("fppr_run_static: one source needs " + std::to_string(one) +
+                   " bytes of workspace, above the static workspace of " +
+                   std::to_string(FPPR_STATIC_SCRATCH_BYTES) + " bytes");
+  if (out->endpoints && all > FPPR_STATIC_SCRATCH_BYTES)
+    return invalid("fppr_run_static: with out->endpoints the whole run (" + std::to_string(all) +
+                   " bytes) must fit the static workspace of " + std::to_string(FPPR_STATIC_SCRATCH_BYTES) +
+                   " bytes");
+  void* ws = nullptr;
+  if ((st = static_scratch(dev, &ws)) != FPPR_OK) return st;
+  return fppr_run(g, p, sources, n_sources, ws, FPPR_STATIC_SCRATCH_BYTES, out, stream);
+}
+
 FPPR_API fppr_status fppr_profile_create(fppr_profile** out) {
   if (!out) return invalid("out is NULL");
   auto* p = new fppr_profile();

@@ -165,6 +165,8 @@ _SIGS = [
     ("fppr_run", ctypes.c_int, [P, ctypes.POINTER(fppr_params), P, ctypes.c_uint64, P, ctypes.c_uint64,
                                 ctypes.POINTER(fppr_out), P]),
     ("fppr_run_check", ctypes.c_int, [P, P]),
+    ("fppr_run_static", ctypes.c_int, [P, ctypes.POINTER(fppr_params), P, ctypes.c_uint64,
+                                       ctypes.POINTER(fppr_out), P]),
     ("fppr_profile_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
     ("fppr_profile_destroy", ctypes.c_int, [P]),
     ("fppr_profile_read", ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double),
@@ -519,6 +521,17 @@ def fppr_run(graph: Graph, params: fppr_params, sources, n_sources: int, workspa
     _check(lib().fppr_run(graph.handle, ctypes.byref(params), _dptr(sources), n_sources,
                           _dptr(workspace), workspace.numel() * workspace.element_size(),
                           ctypes.byref(o), _stream_ptr(stream)))
+
+
+def fppr_run_static(graph: Graph, params: fppr_params, sources, n_sources: int, out: Outputs,
+                    stream=None):
+    """fppr_run with the library's fixed device workspace (no allocation in
+    the library). sources: torch int32 device tensor or None (all nodes)."""
+    o = fppr_out(_dptr(out.topk), _dptr(out.counts), _dptr(out.n_distinct), _dptr(out.digest),
+                 _dptr(out.endpoints), _dptr(out.stats),
+                 out.profile.handle if out.profile is not None else None)
+    _check(lib().fppr_run_static(graph.handle, ctypes.byref(params), _dptr(sources), n_sources,
+                                 ctypes.byref(o), _stream_ptr(stream)))
 
 
 class Profile:
