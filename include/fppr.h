@@ -481,6 +481,9 @@ FPPR_API fppr_status fppr_batch_launch(fppr_batch* b, void* stream);
 /* Synchronises `stream`; INVALID_ARGUMENT if a batch run met a source id >= n
  * or (FPPR_BATCH_REBUILD) a graph failed its rebuild's validation. */
 FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream);
+/* Waits until the batch's last run or replay has finished, then frees the
+ * batch (its streams, events and captured graph; not the caller's
+ * workspace, graphs or outputs, which may be freed after this returns). */
 FPPR_API fppr_status fppr_batch_destroy(fppr_batch* b);
 
 /* ------------------------------------------------------------------------

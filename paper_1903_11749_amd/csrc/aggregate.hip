@@ -8,6 +8,7 @@
 // scan, and the runs give the sparse (t, count) list in increasing t. The
 // ranking order for top-k is (count desc, t asc), obtained by sorting the
 // 64-bit keys (~count << 32 | t) ascending.
+#include "agg_hash.hpp"
 #include "fppr_internal.hpp"
 
 namespace fppr {
@@ -357,10 +358,12 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
 // exact radix select over the 64-bit ranking keys finds the k-th key first.
 // The last pass over a global table also empties it for the next source.
 // ---------------------------------------------------------------------------
-constexpr int kBigThreads = 1024;
-constexpr uint32_t kHistBins = 2048;
-constexpr uint32_t kCandCap = 2048;
-constexpr uint64_t kEmpty = 0xFFFFFFFF00000000ull;
+using agg::kBigThreads;
+using agg::kCandCap;
+using agg::kEmpty;
+using agg::kHistBins;
+using agg::kLdsProbes;
+using agg::kLdsSlots;
 
 // loads that see other threads' atomics (served by L2, not the CU's cache)
 __device__ __forceinline__ uint64_t load_l2(const uint64_t* p) {
@@ -399,7 +402,6 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
 template <bool kReset, typename F>
 __device__ __forceinline__ void table_pass(uint64_t* tab, uint32_t H, F&& f) {
   uint4* t4 = reinterpret_cast<uint4*>(tab);
-  const uint32_t n4 = H / 2;
   const uint4 empty2 = make_uint4(0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu);  // two kEmpty slots
   auto visit = [&](const uint4& v) {
     const uint64_t e0 = (static_cast<uint64_t>(v.y) << 32) | v.x;
@@ -407,27 +409,28 @@ __device__ __forceinline__ void table_pass(uint64_t* tab, uint32_t H, F&& f) {
     if (e0 != kEmpty) f(e0);
     if (e1 != kEmpty) f(e1);
   };
-  uint32_t j = threadIdx.x;
-  for (; j + 3 * kBigThreads < n4; j += 4 * kBigThreads) {
-    uint4 v[4];
+  agg::pass_pairs(
+      threadIdx.x, H,
+      [&](uint32_t j) {
+        uint4 v[4];
 #pragma unroll
-    for (uint32_t u = 0; u < 4; ++u) v[u] = t4[j + u * kBigThreads];
+        for (uint32_t u = 0; u < 4; ++u) v[u] = t4[j + u * kBigThreads];
 #pragma unroll
-    for (uint32_t u = 0; u < 4; ++u) {
-      visit(v[u]);
-      if (kReset) t4[j + u * kBigThreads] = empty2;
-    }
-  }
-  for (; j < n4; j += kBigThreads) {
-    const uint4 v = t4[j];
-    visit(v);
-    if (kReset) t4[j] = empty2;
-  }
+        for (uint32_t u = 0; u < 4; ++u) {
+          visit(v[u]);
+          if (kReset) t4[j + u * kBigThreads] = empty2;
+        }
+      },
+      [&](uint32_t j) {
+        const uint4 v = t4[j];
+        visit(v);
+        if (kReset) t4[j] = empty2;
+      });
 }
 
 // Adds one walk ending at t to the table, starting from slot h whose value
 // was read as cur.
-__device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint32_t t, uint32_t c, uint32_t h,
+__device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t log2, uint32_t t, uint32_t c, uint32_t h,
                                              uint64_t cur) {
   for (;;) {
     if (cur != kEmpty) {
@@ -435,7 +438,7 @@ __device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint3
         atomicAdd(reinterpret_cast<unsigned long long*>(tab + h), static_cast<unsigned long long>(c));
         return;
       }
-      h = (h + 1) & mask;
+      h = agg::table_next(h, log2);
       cur = load_l2(tab + h);
       continue;
     }
@@ -447,17 +450,14 @@ __device__ __forceinline__ void table_insert(uint64_t* tab, uint32_t mask, uint3
   }
 }
 
-constexpr uint32_t kLdsLog2 = 14;
-constexpr uint32_t kLdsSlots = 1u << kLdsLog2;  // LDS counting table: keys + counts, 128 KB
-constexpr uint32_t kLdsProbes = 8;
 static_assert(kLdsSlots % (4 * kBigThreads) == 0, "whole flush rounds");
 
 // Counts t in the LDS table (keys lk, counts lc; empty key kNoNode); false if
 // no slot was free within kLdsProbes probes. Double hashing (an odd stride
 // from a second hash) keeps probe windows from running into each other.
 __device__ __forceinline__ bool lds_insert(uint32_t* lk, uint32_t* lc, uint32_t t) {
-  uint32_t h = (t * 0x9E3779B1u) >> (32 - kLdsLog2);
-  const uint32_t step = ((t * 0x85EBCA6Bu) >> (32 - kLdsLog2)) | 1u;
+  uint32_t h = agg::lds_home(t);
+  const uint32_t step = agg::lds_stride(t);
   for (uint32_t p = 0; p < kLdsProbes; ++p) {
     uint32_t k = lk[h];
     if (k == kNoNode) {
@@ -468,7 +468,7 @@ __device__ __forceinline__ bool lds_insert(uint32_t* lk, uint32_t* lc, uint32_t 
       atomicAdd(&lc[h], 1u);
       return true;
     }
-    h = (h + step) & (kLdsSlots - 1);
+    h = agg::lds_next(h, step);
   }
   return false;
 }
@@ -478,12 +478,11 @@ __device__ __forceinline__ bool lds_insert(uint32_t* lk, uint32_t* lc, uint32_t 
 // flight together; a key that meets another key there probes on alone.
 __device__ __forceinline__ void table_insert4(uint64_t* tab, uint32_t log2, const uint32_t (&t)[4],
                                               const uint32_t (&c)[4], const bool (&live)[4]) {
-  const uint32_t mask = (1u << log2) - 1;
   uint32_t h[4];
   uint64_t old[4];
 #pragma unroll
   for (uint32_t u = 0; u < 4; ++u) {
-    h[u] = (t[u] * 0x9E3779B1u) >> (32 - log2);
+    h[u] = agg::table_home(t[u], log2);
     old[u] = live[u] ? atomicCAS(reinterpret_cast<unsigned long long*>(tab + h[u]),
                                  static_cast<unsigned long long>(kEmpty),
                                  static_cast<unsigned long long>((static_cast<uint64_t>(t[u]) << 32) | c[u]))
@@ -491,7 +490,7 @@ __device__ __forceinline__ void table_insert4(uint64_t* tab, uint32_t log2, cons
   }
 #pragma unroll
   for (uint32_t u = 0; u < 4; ++u)
-    if (live[u] && old[u] != kEmpty) table_insert(tab, mask, t[u], c[u], h[u], old[u]);
+    if (live[u] && old[u] != kEmpty) table_insert(tab, log2, t[u], c[u], h[u], old[u]);
 }
 
 __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
@@ -504,10 +503,8 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
   __shared__ uint32_t s_cstar, s_cand, s_n, s_digit, s_rem, s_spill;
   const uint32_t tid = threadIdx.x;
   const uint32_t H = 1u << a.H_log2;
-  const uint32_t mask = H - 1;
   uint64_t* tab = a.table + (static_cast<uint64_t>(blockIdx.x) << a.H_log2);
   const uint32_t R = a.R;
-  (void)mask;
 
   for (uint64_t row = blockIdx.x; row < a.n_src; row += gridDim.x) {
     const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
@@ -560,7 +557,7 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
       const uint32_t t = static_cast<uint32_t>(e >> 32), c = static_cast<uint32_t>(e);
       dg += digest_term(src, t, c);
       ++nd;
-      atomicAdd(&hist[c < kHistBins - 1 ? c : kHistBins - 1], 1u);
+      atomicAdd(&hist[agg::hist_bin(c)], 1u);
     });
     dg = block_sum_u64(dg, red);
     nd = block_sum_u64(nd, red);
@@ -672,28 +669,6 @@ __global__ void __launch_bounds__(kBigThreads) k_aggregate_big(AggLaunch a) {
 }
 
 }  // namespace
-
-uint32_t agg_table_log2(uint32_t R) {
-  uint32_t l = 1;
-  while ((1ull << l) < 2ull * R) ++l;
-  return l;
-}
-
-uint32_t agg_table_groups(uint64_t n_src, uint32_t R) {
-  const uint64_t slot_bytes = 8ull << agg_table_log2(R);
-  uint64_t g = (1ull << 30) / slot_bytes;  // about 1 GiB of tables at most
-  if (g > kAggBigGroups) g = kAggBigGroups;
-  if (g < 64) g = 64;
-  if (g > n_src) g = n_src;
-  return static_cast<uint32_t>(g ? g : 1);
-}
-
-bool agg_uses_table(uint32_t R, bool counts) { return R > kAggWaveMaxR && !counts; }
-
-uint64_t agg_table_bytes(uint64_t n_src, uint32_t R, bool counts) {
-  if (!agg_uses_table(R, counts) || n_src == 0) return 0;
-  return static_cast<uint64_t>(agg_table_groups(n_src, R)) << (agg_table_log2(R) + 3);
-}
 
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s) {
   if (a.n_src == 0) return hipSuccess;

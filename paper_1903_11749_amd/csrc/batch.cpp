@@ -14,15 +14,14 @@
 #include <string>
 #include <vector>
 
+#include "batch_layout.hpp"
 #include "fppr_internal.hpp"
 
 using namespace fppr;
 
 namespace {
 
-constexpr uint64_t kAlign = 256;
-uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-constexpr uint64_t kCtlBytes = 256;
+constexpr uint64_t kCtlBytes = kBatchCtlBytes;
 constexpr int kLanes = 4;  // the caller's stream + 3 of the batch's
 
 fppr_status invalid(const std::string& msg) {
@@ -51,6 +50,7 @@ struct fppr_batch {
   hipStream_t aux[kLanes - 1] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kLanes - 1] = {};
+  hipEvent_t done = nullptr;  // recorded behind every run and replay; destroy waits for it
   std::vector<int> graph_lane, item_lane;  // lane of each graph's rebuild / item's counting
   std::vector<bool> split;                 // all-nodes item: coin-only kernel for nodes without out-edges
 };
@@ -73,23 +73,26 @@ fppr_status check_items(const fppr_batch_item* items, uint32_t count) {
   return FPPR_OK;
 }
 
-uint64_t endpoint_bytes(const fppr_batch_item& it) {
-  return align_up(item_sources(it) * it.params.R * 4ull);
-}
-
-// items aggregate one after the other on one stream: one table area serves all
-uint64_t table_bytes(const fppr_batch_item* items, uint32_t count) {
-  uint64_t t = 0;
+// the shapes batch_layout needs (an all-nodes item over a graph with many
+// nodes without out-edges is split: see fppr_batch_create)
+std::vector<BatchItemShape> shapes(const fppr_batch_item* items, uint32_t count) {
+  std::vector<BatchItemShape> v(count);
   for (uint32_t k = 0; k < count; ++k) {
-    const uint64_t b = align_up(agg_table_bytes(item_sources(items[k]), items[k].params.R,
-                                                 (items[k].params.flags & FPPR_COUNTS) != 0));
-    if (b > t) t = b;
+    const fppr_batch_item& it = items[k];
+    v[k].n_rows = item_sources(it);
+    v[k].R = it.params.R;
+    v[k].counts = (it.params.flags & FPPR_COUNTS) != 0;
+    v[k].split = !it.sources && split_dangling(it.graph);
+    v[k].n_live = it.graph->n_live;
   }
-  return t;
+  return v;
 }
 
 void free_batch(fppr_batch* b) {
   if (!b) return;
+  // the last run or replay (on the caller's stream) may still read the
+  // captured graph and write the workspace the caller frees after this call
+  if (b->done) (void)hipEventSynchronize(b->done);
   for (hipStream_t a : b->aux)
     if (a) (void)hipStreamSynchronize(a);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -99,6 +102,7 @@ void free_batch(fppr_batch* b) {
   for (hipEvent_t e : b->join)
     if (e) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->done) (void)hipEventDestroy(b->done);
   delete b;
 }
 
@@ -183,9 +187,7 @@ FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t coun
   fppr_status st = check_items(items, count);
   if (st != FPPR_OK) return st;
   if (!workspace_bytes) return invalid("workspace_bytes is NULL");
-  uint64_t bytes = kCtlBytes + align_up(count * sizeof(WalkDesc)) + table_bytes(items, count);
-  for (uint32_t k = 0; k < count; ++k) bytes += endpoint_bytes(items[k]);
-  *workspace_bytes = bytes;
+  *workspace_bytes = batch_layout(shapes(items, count), sizeof(WalkDesc), kWalkChunk).bytes;
   return FPPR_OK;
 }
 
@@ -205,42 +207,35 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
   for (uint32_t k = 0; k < count; ++k)
     if (std::find(b->graphs.begin(), b->graphs.end(), items[k].graph) == b->graphs.end())
       b->graphs.push_back(items[k].graph);
+  // Largest items first in the walk table, so that small ones fill the tail
+  // of the launch. An item over all nodes of its graph walks only from the
+  // nodes with out-edges in the walk launch (endpoints placed by source id);
+  // the walks from the other nodes only restart at their source and run in a
+  // coin-only kernel before the item's counting. Draws and results are
+  // unchanged.
+  const std::vector<BatchItemShape> sh = shapes(items, count);
+  const BatchLayout lay = batch_layout(sh, sizeof(WalkDesc), kWalkChunk);
   char* base = static_cast<char*>(workspace);
-  b->ctl = reinterpret_cast<unsigned long long*>(base);
-  b->table = reinterpret_cast<WalkDesc*>(base + kCtlBytes);
-  b->agg_table = reinterpret_cast<uint64_t*>(base + kCtlBytes + align_up(count * sizeof(WalkDesc)));
-  char* ep = base + kCtlBytes + align_up(count * sizeof(WalkDesc)) + table_bytes(items, count);
+  b->ctl = reinterpret_cast<unsigned long long*>(base + lay.ctl);
+  b->table = reinterpret_cast<WalkDesc*>(base + lay.table);
+  b->agg_table = reinterpret_cast<uint64_t*>(base + lay.agg_table);
   b->endpoints.resize(count);
-  for (uint32_t k = 0; k < count; ++k) {
-    b->endpoints[k] = reinterpret_cast<uint32_t*>(ep);
-    ep += endpoint_bytes(items[k]);
-  }
-  // largest items first, so that small ones fill the tail of the launch
-  std::vector<uint32_t> order(count);
-  std::iota(order.begin(), order.end(), 0u);
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-    return item_sources(items[x]) * items[x].params.R > item_sources(items[y]) * items[y].params.R;
-  });
-  // An item over all nodes of its graph walks only from the nodes with
-  // out-edges in the walk launch (endpoints placed by source id); the walks
-  // from the other nodes only restart at their source and run in a coin-only
-  // kernel before the item's counting. Draws and results are unchanged.
   b->split.assign(count, false);
-  for (uint32_t k = 0; k < count; ++k) b->split[k] = !items[k].sources && split_dangling(items[k].graph);
-  uint64_t first = 0;
-  for (uint32_t k : order) {
-    const fppr_batch_item& it = items[k];
-    const uint64_t walks = (b->split[k] ? it.graph->n_live : item_sources(it)) * it.params.R;
-    if (walks == 0) continue;
-    WalkDesc D = b->split[k] ? make_desc(it.graph, &it.params, it.graph->live, it.graph->n_live, b->endpoints[k],
-                                         first, 0, walks)
-                             : make_desc(it.graph, &it.params, it.sources, item_sources(it), b->endpoints[k],
-                                         first, 0, walks);
-    if (b->split[k]) D.flags |= kDescEpBySource;
-    b->host_table.push_back(D);
-    first += (walks + kWalkChunk - 1) / kWalkChunk * kWalkChunk;
+  for (uint32_t k = 0; k < count; ++k) {
+    b->endpoints[k] = reinterpret_cast<uint32_t*>(base + lay.endpoints[k]);
+    b->split[k] = sh[k].split;
   }
-  b->total = first;
+  for (const BatchRun& r : lay.runs) {
+    const fppr_batch_item& it = items[r.item];
+    WalkDesc D = b->split[r.item]
+                     ? make_desc(it.graph, &it.params, it.graph->live, it.graph->n_live, b->endpoints[r.item],
+                                 r.first, 0, r.count)
+                     : make_desc(it.graph, &it.params, it.sources, item_sources(it), b->endpoints[r.item],
+                                 r.first, 0, r.count);
+    if (b->split[r.item]) D.flags |= kDescEpBySource;
+    b->host_table.push_back(D);
+  }
+  b->total = lay.total;
   {
     std::vector<uint64_t> gcost(b->graphs.size());
     std::vector<bool> gpin(b->graphs.size(), false);
@@ -256,6 +251,7 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
   }
   {
     hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     for (int a = 0; a < kLanes - 1 && e == hipSuccess; ++a) {
       e = hipStreamCreateWithFlags(&b->aux[a], hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[a], hipEventDisableTiming);
@@ -280,7 +276,11 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
 FPPR_API fppr_status fppr_batch_run(fppr_batch* b, fppr_stats* stats, fppr_profile* profile,
                                     void* stream) {
   if (!b) return invalid("batch is NULL");
-  return enqueue(b, stats, profile, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const fppr_status st = enqueue(b, stats, profile, s);
+  if (st != FPPR_OK) return st;
+  const hipError_t e = hipEventRecord(b->done, s);
+  return e == hipSuccess ? FPPR_OK : hip_fail(e, "event");
 }
 
 FPPR_API fppr_status fppr_batch_capture(fppr_batch* b, fppr_stats* stats, void* stream) {
@@ -316,6 +316,7 @@ FPPR_API fppr_status fppr_batch_launch(fppr_batch* b, void* stream) {
   if (!b->exec) return invalid("no captured graph (fppr_batch_capture)");
   hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  if ((e = hipEventRecord(b->done, static_cast<hipStream_t>(stream))) != hipSuccess) return hip_fail(e, "event");
   return FPPR_OK;
 }
 

@@ -143,6 +143,40 @@ __device__ __forceinline__ uint64_t scaled_draw(uint32_t x0, uint32_t x1, uint64
   return __umul64hi((static_cast<uint64_t>(x1) << 32) | x0, W);
 }
 
+// High 64 bits of a 64 x 64-bit product.
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return static_cast<uint64_t>((static_cast<unsigned __int128>(a) * b) >> 64);
+#endif
+}
+
+// Source row q = w div R of walk index w (and *rem = w mod R), with R_magic =
+// floor((2^64 - 1) / R): the estimate mulhi(w, R_magic) is q or q - 1.
+__host__ __device__ __forceinline__ uint64_t walk_row(uint64_t w, uint32_t R, uint64_t R_magic, uint64_t* rem) {
+  uint64_t q = mulhi64(w, R_magic);
+  uint64_t r = w - q * R;
+  if (r >= R) {
+    q += 1;
+    r -= R;
+  }
+  *rem = r;
+  return q;
+}
+
+// Descriptor of walk id c in a table sorted by first id: the last one whose
+// first id is <= c (first(0) = 0 <= c). first(k) reads descriptor k's first id.
+template <typename First>
+__host__ __device__ __forceinline__ uint32_t desc_of(uint64_t c, uint32_t ndesc, First&& first) {
+  uint32_t lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (first(mid) <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 struct GraphView {
   const Block* __restrict__ rec;     // node lines (plain table)
   const Block* __restrict__ blocks;  // row regions

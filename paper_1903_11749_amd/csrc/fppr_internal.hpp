@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/fppr.h"
+#include "agg_hash.hpp"
 #include "fppr_device.hpp"
 
 namespace fppr {
@@ -109,6 +110,7 @@ hipError_t launch_pool(fppr_graph* g, hipStream_t s);
 // first) of the run; walk index w is walk w % R of source row w / R, and its
 // endpoint goes to endpoints[w]. first is a multiple of kWalkChunk.
 constexpr uint64_t kWalkChunk = 256;
+constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk in LDS (rows it spans + 1)
 struct WalkDesc {
   const Block* rec;          // plain node lines, or the stitched table
   const Block* blocks;       // row regions
@@ -173,16 +175,6 @@ struct AggLaunch {
 hipError_t launch_aggregate(const AggLaunch& a, hipStream_t s);
 AggLaunch make_agg(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
                    uint64_t n_sources, const fppr_out* out);
-constexpr uint32_t kAggWaveMaxR = 256;   // largest R of the one-wave-per-source path
-constexpr uint32_t kAggMaxR = 4096;      // largest R with counts (the LDS tile sort)
-constexpr uint32_t kMaxR = 1u << 20;     // largest R (hash path above kAggMaxR: no counts)
-constexpr uint32_t kAggBigGroups = 512;  // blocks (and hash tables) of the hash path
-// Counting without per-source counts and R > kAggWaveMaxR takes the hash path,
-// which needs agg_table_bytes of scratch: log2 of the slots per global table,
-// the tables (= blocks) used, and the bytes (0 when the path is not taken).
-bool agg_uses_table(uint32_t R, bool counts);
-uint32_t agg_table_log2(uint32_t R);
-uint32_t agg_table_groups(uint64_t n_src, uint32_t R);
-uint64_t agg_table_bytes(uint64_t n_src, uint32_t R, bool counts);
+// sizes of the counting paths and their hash tables: agg_hash.hpp
 
 }  // namespace fppr

@@ -44,7 +44,7 @@ namespace fppr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk (rows spanned + 1)
+using fppr::kSrcBuf;
 // Restarts at the head handled inline per loop iteration: 4 in general
 // (2..16 measured), 1 for tables of all-nodes runs whose nodes without
 // out-edges went to the coin-only kernel: restarts are rare there, and a
@@ -171,12 +171,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
             break;
           }
           // descriptor holding chunk c: the last one with first <= c
-          uint32_t lo = 0, hi = t.ndesc - 1;
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (t.descs[mid].first <= c) lo = mid; else hi = mid - 1;
-          }
-          dn = sread(lo);
+          dn = sread(desc_of(c, t.ndesc, [&](uint32_t k) { return t.descs[k].first; }));
         }
         if (dn != d) {
           const WalkDesc& Dn = t.descs[dn];
@@ -214,13 +209,9 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         if (sources) {
           // the chunk's source rows [q_lo, q_hi] to LDS in one coalesced load,
           // so that refills read source ids without waiting on memory
-          auto row_of = [&](uint64_t id) {
-            const uint64_t wi = walk0 + (id - first);
-            uint64_t q = __umul64hi(wi, R_magic);
-            if (wi - q * R >= R) q += 1;
-            return q;
-          };
-          const uint64_t q_lo = row_of(cur), q_hi = row_of(end - 1);
+          uint64_t rm;
+          const uint64_t q_lo = walk_row(walk0 + (cur - first), R, R_magic, &rm);
+          const uint64_t q_hi = walk_row(walk0 + (end - 1 - first), R, R_magic, &rm);
           const uint32_t rows = static_cast<uint32_t>(q_hi - q_lo + 1);  // <= kSrcBuf
           for (uint32_t j = lane; j < rows; j += 64) sh_src[wv][j] = sources[q_lo + j];
           src_q0 = q_lo;
@@ -234,12 +225,8 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         const uint32_t r = mask_rank(idle);
         if (r < take) {
           const uint64_t w = walk0 + (cur + r - first);  // walk index within its run
-          uint64_t q = __umul64hi(w, R_magic);
-          uint64_t rem = w - q * R;
-          if (rem >= R) {
-            q += 1;
-            rem -= R;
-          }
+          uint64_t rem;
+          const uint64_t q = walk_row(w, R, R_magic, &rem);
           L.s = sources ? sh_src[wv][q - src_q0] : static_cast<uint32_t>(q);
           L.i = static_cast<uint32_t>(rem);
           if (kLaneKeys) {
@@ -561,12 +548,8 @@ __global__ void __launch_bounds__(kThreads) k_dangling(const uint32_t* __restric
   uint64_t q = 0;
   uint32_t i = 0, s = 0, s_next = 0, m = 0;
   if (left) {
-    q = __umul64hi(w0, R_magic);
-    uint64_t rem = w0 - q * R;
-    if (rem >= R) {
-      q += 1;
-      rem -= R;
-    }
+    uint64_t rem;
+    q = walk_row(w0, R, R_magic, &rem);
     i = static_cast<uint32_t>(rem);
     s = dang[q];
     if (left > R - i) s_next = dang[q + 1];  // the range continues into the next row

@@ -225,3 +225,29 @@ def test_batch_with_rebuild_captured(fp, items):
             assert np.array_equal(u32(o.counts), c), rep
             assert np.array_equal(u64(o.digest), d), rep
     B.close()
+
+
+def test_destroy_waits_for_the_last_replay(fp, items):
+    """fppr_batch_destroy right after a replay (no synchronisation by the
+    caller) returns only once the replay has finished: the outputs read after
+    it are complete, and the workspace can be freed at once."""
+    import torch
+
+    say("case: destroy right after an unsynchronised replay")
+    B = fp.Batch(items)
+    B.run()
+    torch.cuda.synchronize()
+    want = [(u32(o.counts).copy(), u64(o.digest).copy()) for o in B.outputs]
+    stream = torch.cuda.Stream()
+    B.capture(stream)
+    for o in B.outputs:
+        o.counts.fill_(-1)
+        o.digest.fill_(-1)
+    torch.cuda.synchronize()
+    B.launch(stream)
+    outs = B.outputs
+    B.close()
+    B.workspace = None
+    for (c, d), o in zip(want, outs):
+        assert np.array_equal(u32(o.counts), c)
+        assert np.array_equal(u64(o.digest), d)
