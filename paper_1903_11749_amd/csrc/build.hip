@@ -1,7 +1,8 @@
 // Graph ingest: CSR validation, per-row inclusive uint64 weight prefixes laid
-// out with the destination ids in 128-byte leaf blocks, 128-byte node lines
-// and the rows' prefix trees (top level in the node line, 16-ary below),
-// all in one pass over the edges.
+// out with the destination ids (class-tagged in graphs of at most 2^30
+// nodes) in 128-byte leaf blocks, 128-byte node lines and the rows' prefix
+// trees (top level in the node line, 16-ary below), all in one pass over
+// the edges.
 //
 // Routing probability r(s,t) = w(s,t) / sum_v w(s,v) (Sec. 2.1) is realised
 // on exact integers: the prefix P of a row is strictly increasing (w >= 1),
@@ -85,6 +86,17 @@ __device__ __forceinline__ void write_record(Block* rec, uint64_t u, uint64_t W,
   for (uint32_t k = 1; k < kNodeKeys / 2; ++k) dst[k] = make_ulonglong2(~0ull, ~0ull);
 }
 
+// Destination c of an edge of row u as a leaf stores it: with its class tag
+// in tagged graphs. A rebuild validates the CSR on the device without
+// waiting, so an id >= n can reach here; it is stored as u itself, so that
+// no kernel ever reads a node line past n (the graph's check reports the
+// invalid CSR, and its results mean nothing until it is fixed).
+__device__ __forceinline__ uint32_t leaf_dest(const uint8_t* __restrict__ cls, uint32_t n, uint32_t c,
+                                              uint64_t u) {
+  if (c >= n) c = static_cast<uint32_t>(u);
+  return cls ? c | (static_cast<uint32_t>(cls[c]) << kTagShift) : c;
+}
+
 // Edge j of a row (prefix P, destination c) into its leaf block, by layout;
 // slots past the row's end get P = ~0.
 __device__ __forceinline__ void put_edge(Block* leaves, uint64_t j, uint64_t P, uint32_t c, bool nar) {
@@ -118,7 +130,7 @@ __device__ __forceinline__ void put_key(Block* nd, uint64_t t, uint64_t P, bool 
 template <bool nar>
 __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t* __restrict__ col,
                                const uint32_t* __restrict__ w, const uint64_t* __restrict__ region,
-                               uint32_t n, uint32_t tree_min, uint64_t cap,
+                               const uint8_t* __restrict__ cls, uint32_t n, uint32_t tree_min, uint64_t cap,
                                Block* __restrict__ blk, Block* __restrict__ rec, uint32_t* rows,
                                uint32_t* n_rows, uint32_t* n_tree_rows, uint32_t* err) {
   uint64_t trees = 0;
@@ -161,7 +173,7 @@ __global__ void k_leaves_short(const uint64_t* __restrict__ off, const uint32_t*
     uint64_t acc = 0;
     for (uint64_t j = 0; j < d; ++j) {
       acc += w[a + j];
-      put_edge(leaves, j, acc, col[a + j], nar);
+      put_edge(leaves, j, acc, leaf_dest(cls, n, col[a + j], u), nar);
       if (tree && ((j % E) == E - 1 || j == d - 1)) put_top(rec + u, j / E, acc, nar);
     }
     for (uint64_t j = d; j < leaf_blocks(d, nar) * E; ++j) pad_edge(leaves, j, nar);
@@ -208,6 +220,7 @@ __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __rest
                                                           const uint32_t* __restrict__ col,
                                                           const uint32_t* __restrict__ w,
                                                           const uint64_t* __restrict__ region,
+                                                          const uint8_t* __restrict__ cls, uint32_t n,
                                                           uint32_t tree_min, Block* __restrict__ blk,
                                                           Block* __restrict__ rec,
                                                           const uint32_t* rows,
@@ -245,7 +258,7 @@ __global__ void __launch_bounds__(kThreads) k_leaves_long(const uint64_t* __rest
         const uint64_t j = j0 + k;
         if (j < d) {
           const uint64_t P = carry + excl + v[k];
-          put_edge(leaves, j, P, col[a + j], nar);
+          put_edge(leaves, j, P, leaf_dest(cls, n, col[a + j], u), nar);
           if (tree) place_tree_key(blk + r0, rec + u, d, L, T, j, P, nar);
           if (j == d - 1) {
             rec[u].key[0] = P;
@@ -329,6 +342,16 @@ __global__ void k_split_nodes(const uint32_t* __restrict__ flag, const uint64_t*
   }
 }
 
+// class of every node for the destination tags: no out-edges, small under
+// the pool's bound S (1 <= out-degree <= S), or neither
+__global__ void k_node_class(const uint64_t* __restrict__ off, uint32_t n, uint32_t S, uint8_t* cls) {
+  for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < n;
+       v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t d = off[v + 1] - off[v];
+    cls[v] = static_cast<uint8_t>(d == 0 ? kTagDangling : (d <= S ? kTagSmall : 0u));
+  }
+}
+
 uint32_t grid_for(uint64_t items) {
   uint64_t b = (items + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
@@ -381,11 +404,19 @@ hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s) {
 template <bool kNar>
 void launch_leaves_t(fppr_graph* g, hipStream_t s, bool count_trees) {
   uint32_t* n_long = g->d_err + 1;
+  const uint8_t* cls = g->tagged ? g->cls : nullptr;
   hipLaunchKernelGGL(k_leaves_short<kNar>, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->col,
-                     g->w, g->region, g->n, g->tree_min, g->n_blocks, g->blocks, g->rec,
+                     g->w, g->region, cls, g->n, g->tree_min, g->n_blocks, g->blocks, g->rec,
                      g->rows, n_long, count_trees ? g->d_err + 9 : nullptr, g->d_err);
   hipLaunchKernelGGL(k_leaves_long<kNar>, dim3(2048), dim3(kThreads), 0, s, g->off, g->col, g->w,
-                     g->region, g->tree_min, g->blocks, g->rec, g->rows, n_long, g->d_err);
+                     g->region, cls, g->n, g->tree_min, g->blocks, g->rec, g->rows, n_long, g->d_err);
+}
+
+hipError_t launch_node_class(fppr_graph* g, uint32_t S, hipStream_t s) {
+  if (!g->tagged) return hipSuccess;
+  hipLaunchKernelGGL(k_node_class, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->n, S, g->cls);
+  g->S_tag = S;
+  return hipGetLastError();
 }
 
 hipError_t launch_leaves(fppr_graph* g, hipStream_t s, bool count_trees) {

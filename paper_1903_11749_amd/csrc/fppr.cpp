@@ -61,8 +61,8 @@ void free_graph(fppr_graph* g) {
   dfree(g->scan_blocks);
   dfree(g->d_err);
   dfree(g->pool);
-  dfree(g->rec_st);
   dfree(g->small_nodes);
+  dfree(g->cls);
   dfree(g->live);
   dfree(g->dang);
   if (g->side) (void)hipStreamDestroy(g->side);
@@ -162,8 +162,10 @@ WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* so
   (void)n_sources;
   const bool stitch = (p->flags & FPPR_STITCH) != 0;
   WalkDesc D{};
-  D.rec = stitch ? g->rec_st : g->rec;
+  D.rec = g->rec;
   D.blocks = g->blocks;
+  D.pool = stitch ? g->pool : nullptr;
+  D.S_small = stitch ? g->pool_opts.S : 0u;
   D.sources = sources;
   D.endpoints = endpoints;
   D.first = first;
@@ -177,7 +179,7 @@ WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* so
   D.T = fppr_alpha_threshold(p->alpha);
   D.tree_min = g->tree_min;
   D.K_log2 = stitch ? g->K_log2 : 0;
-  D.flags = g->narrow ? kDescNarrow : 0u;
+  D.flags = (g->narrow ? kDescNarrow : 0u) | (g->tagged ? kDescTagged : 0u);
   return D;
 }
 
@@ -256,6 +258,7 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   g->n = csr->n;
   g->m = csr->m;
   g->tree_min = H;
+  g->tagged = csr->n <= kMaxTaggedNodes;
   hipError_t e = hipGetDevice(&g->device);
   if (e != hipSuccess) {
     delete g;
@@ -331,6 +334,10 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   }
   g->n_blocks = c.blocks;
   FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
+  if (g->tagged) {
+    FPPR_TRY(dmalloc(&g->cls, n, acc), "hipMalloc(node classes)");
+    FPPR_TRY(launch_node_class(g, 0, s), "node classes");
+  }
   FPPR_TRY(launch_leaves(g, s, true), "leaf blocks");
   FPPR_TRY(read_ctl(g, s, &c), "read build status");
   if (c.err) {
@@ -386,15 +393,18 @@ FPPR_API fppr_status fppr_graph_build_pool(fppr_graph* g, const fppr_pool_opts* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   uint64_t n_small = g->n_small;
-  if (!g->has_pool || g->pool_opts.S != o->S) {
+  const bool retag = g->tagged && g->S_tag != o->S;
+  if (!g->has_pool || g->pool_opts.S != o->S || retag) {
     if ((e = launch_small_flags(g, o->S, s)) != hipSuccess) return hip_fail(e, "small flags");
     Ctl c{};
     if ((e = read_ctl(g, s, &c)) != hipSuccess) return hip_fail(e, "read small count");
+    if (c.err) return invalid("graph failed its last validation:" + err_bits(c.err));
     n_small = c.small;
   }
-  const uint64_t need = n_small * o->K;
-  if (!g->rec_st) {
-    if ((e = dmalloc(&g->rec_st, g->n, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(rec_st)");
+  // node-indexed: node v's K entries at v * K, so a walk that arrives at a
+  // small node over a tagged edge finds its entry without the node's line
+  const uint64_t need = static_cast<uint64_t>(g->n) * o->K;
+  if (!g->small_nodes) {
     if ((e = dmalloc(&g->small_nodes, g->n, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(small nodes)");
   }
   if (need > g->pool_cap || !g->pool) {
@@ -412,6 +422,11 @@ FPPR_API fppr_status fppr_graph_build_pool(fppr_graph* g, const fppr_pool_opts* 
   g->K_log2 = log2_exact(o->K);
   g->n_small = n_small;
   g->has_pool = true;
+  if (retag) {  // the leaves' small-node tags follow the pool's S (the leaf kernels count long rows from 0)
+    if ((e = zero_ctl(g, s)) != hipSuccess) return hip_fail(e, "zero control words");
+    if ((e = launch_node_class(g, o->S, s)) != hipSuccess) return hip_fail(e, "node classes");
+    if ((e = derive(g, s)) != hipSuccess) return hip_fail(e, "leaf blocks");
+  }
   return pool_kernels(g, s);
 }
 
@@ -422,12 +437,15 @@ FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entri
   const uint64_t total = g->n_small * g->pool_opts.K;
   if (count < total) return invalid("entries too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "sync");
-  if (total) {
-    e = hipMemcpy(entries, g->pool, total * 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "copy pool");
-  }
+  if (!total) return FPPR_OK;
+  uint64_t* tmp = nullptr;  // the canonical order, gathered from the node-indexed pool
+  hipError_t e = hipMalloc(&tmp, total * 8);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(pool export)");
+  e = launch_pool_export(g, tmp, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(entries, tmp, total * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "export pool");
   return FPPR_OK;
 }
 

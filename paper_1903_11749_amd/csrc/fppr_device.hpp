@@ -10,13 +10,13 @@ namespace fppr {
 // ---------------------------------------------------------------------------
 // Node line: 128 bytes per node (one memory line, read by one dependent
 // load), laid out as a Block:
-//   key[0]: total weight W of the row (plain table), or the address of the
-//           node's first pool entry (stitched table, small nodes)
+//   key[0]: total weight W of the row
 //   key[1]: (first block of the row's region << 28) | flags
 //   bytes 16..127: the top level of the row's prefix tree (~0 past its end
 //           and in rows without a tree): up to 14 u64 keys (wide layout) or
 //           up to 28 u32 keys (narrow layout)
-// flags: bits 0..26 out-degree, bit 27 = small node served by the pool.
+// flags: bits 0..26 out-degree; bit 27 is set by the walk kernel in its own
+// registers for a small node of a stitched run (never stored).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRegionShift = 28;
 constexpr uint64_t kDegMask = (1u << 27) - 1;
@@ -25,6 +25,18 @@ constexpr uint64_t kMaxDeg = kDegMask;           // rows up to 2^27 - 1 edges
 constexpr uint64_t kMaxEdges = 1ull << 36;
 constexpr uint32_t kMoveCap = 65536u;
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
+
+// Destination tags. In graphs of at most 2^30 nodes every destination id
+// stored in a leaf block (and every pool entry's end node) carries its node's
+// class in bits 30..31, so a walk that arrives over an edge knows, without
+// reading the node's line, that the node has no out-edges (the move restarts
+// at the head) or is a small node of the pool (a stitched run reads the pool
+// entry directly). Larger graphs store plain ids (tag 0 everywhere).
+constexpr uint32_t kTagShift = 30;
+constexpr uint32_t kIdMask = (1u << kTagShift) - 1;
+constexpr uint32_t kTagDangling = 1;  // no out-edges
+constexpr uint32_t kTagSmall = 2;     // 1 <= out-degree <= the pool's S
+constexpr uint64_t kMaxTaggedNodes = 1ull << kTagShift;
 
 // ---------------------------------------------------------------------------
 // Row regions. Every row owns a run of 128-byte blocks (one memory line):

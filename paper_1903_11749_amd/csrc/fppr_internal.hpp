@@ -42,6 +42,9 @@ struct fppr_graph {
   uint32_t tree_min = 8;            // rows with more edges carry a prefix tree
   bool narrow = false;              // narrow layout: u32 prefixes (fixed at creation)
   uint32_t n_tree = 0;              // rows with a tree
+  bool tagged = false;              // leaf destinations carry class tags (n <= 2^30)
+  uint8_t* cls = nullptr;           // [n] class of each node (kTagDangling, kTagSmall or 0)
+  uint32_t S_tag = 0;               // small-node bound the tags were made with (0: none)
   // scratch (kept for rebuilds)
   uint32_t* flag = nullptr;         // [n]   per-node u32 input of scans
   uint64_t* scan = nullptr;         // [n]   exclusive scan output
@@ -54,7 +57,7 @@ struct fppr_graph {
   uint32_t pool_T = 0;
   uint32_t K_log2 = 0;
   uint64_t n_small = 0;
-  uint64_t* pool = nullptr;          // [n_small * K]
+  uint64_t* pool = nullptr;          // [n * K]: node v's K entries at v * K (only small nodes' are written)
   // nodes with out-edges and without, each in id order (degrees never change
   // after create, so these are built once)
   uint32_t* live = nullptr;          // [n_live]
@@ -66,7 +69,6 @@ struct fppr_graph {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::mutex side_mu;  // keeps each event record and its wait together across host threads
   uint64_t pool_cap = 0;             // entries allocated
-  fppr::Block* rec_st = nullptr;    // [n] stitched node lines
   uint32_t* small_nodes = nullptr;   // [n] rank -> node
   uint64_t device_bytes = 0;
 };
@@ -94,6 +96,8 @@ hipError_t launch_region_sizes(fppr_graph* g, hipStream_t s);
 hipError_t launch_split_nodes(fppr_graph* g, hipStream_t s);
 // prefixes and destinations into leaf blocks, node records
 hipError_t launch_leaves(fppr_graph* g, hipStream_t s, bool count_trees);
+// class of every node for the destination tags (S: the pool's small-node bound, 0 = none)
+hipError_t launch_node_class(fppr_graph* g, uint32_t S, hipStream_t s);
 // exclusive scan of u32 input to u64 output; writes the total to *total_dev
 hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* blocks,
                            uint64_t* total_dev, hipStream_t s);
@@ -103,6 +107,9 @@ uint64_t scan_block_count(uint64_t n);
 hipError_t launch_small_flags(fppr_graph* g, uint32_t S, hipStream_t s);
 hipError_t launch_small_compact(fppr_graph* g, uint32_t S, hipStream_t s);
 hipError_t launch_pool(fppr_graph* g, hipStream_t s);
+// the pool's entries in canonical order (small nodes by id, then slot; end ids
+// without tags) into out[n_small * K]
+hipError_t launch_pool_export(const fppr_graph* g, uint64_t* out, hipStream_t s);
 
 // walk.hip
 // One descriptor of the walk table: a run of walks on one graph. Ids
@@ -112,8 +119,9 @@ hipError_t launch_pool(fppr_graph* g, hipStream_t s);
 constexpr uint64_t kWalkChunk = 256;
 constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk in LDS (rows it spans + 1)
 struct WalkDesc {
-  const Block* rec;          // plain node lines, or the stitched table
+  const Block* rec;          // node lines
   const Block* blocks;       // row regions
+  const uint64_t* pool;      // stitched runs: the graph's pool (node v's entries at v << K_log2)
   const uint32_t* sources;   // source ids by row, or null for row = node id
   uint32_t* endpoints;
   uint64_t first;
@@ -121,13 +129,16 @@ struct WalkDesc {
   uint64_t walk0;
   uint64_t R_magic;          // floor((2^64 - 1) / R)
   uint32_t R, n, key0, key1, T, tree_min, K_log2;
-  uint32_t flags;            // kDescEpBySource
+  uint32_t S_small;          // stitched runs: small nodes have 1 <= out-degree <= S_small; 0 = plain
+  uint32_t flags;            // kDescEpBySource, kDescNarrow, kDescTagged
 };
 // the endpoint of walk i of source s goes to endpoints[s * R + i] (a run over
 // a list of some of the nodes that fills an all-nodes endpoint buffer)
 constexpr uint32_t kDescEpBySource = 1;
 // the graph has the narrow layout (u32 prefixes, 16-edge leaves, 32-key nodes)
 constexpr uint32_t kDescNarrow = 2;
+// the graph's leaf destinations and pool entries carry class tags
+constexpr uint32_t kDescTagged = 4;
 // lane_keys: the per-lane-key form of the kernel (for tables whose
 // descriptors all read one graph; see same_graph_table)
 // descs: the table on the device; host: the same table in host memory (it

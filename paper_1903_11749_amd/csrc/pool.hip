@@ -6,9 +6,12 @@
 // small node (1 <= out-degree <= S) keeps K sampled walks of at most L plain
 // steps with the same marks, so a walk at a small node takes one pool entry
 // with a single 8-byte load. Entry: end | steps << 32 | mark << 48
-// (mark 1 = terminated). A pool walk stops on its coin (terminated), after L
-// steps, or on arriving at a node without out-neighbours (active: the restart
-// to the walk's own head is taken by the walk's next move).
+// (mark 1 = terminated; in tagged graphs the end id carries its class tag).
+// Node v's entries sit at v * K, so a walk that knows v is small (from the
+// tag of the edge it arrived over) reads its entry without v's node line.
+// A pool walk stops on its coin (terminated), after L steps, or on arriving
+// at a node without out-neighbours (active: the restart to the walk's own
+// head is taken by the walk's next move).
 #include "fppr_internal.hpp"
 
 namespace fppr {
@@ -33,32 +36,29 @@ __global__ void k_small_flags(const uint64_t* __restrict__ off, uint32_t n, uint
   }
 }
 
-// small_nodes[rank] = u and the stitched node-line table: small nodes point
-// at their pool block (absolute address), every other node keeps its plain
-// line. Eight lanes copy one 128-byte line, 16 bytes each.
-__global__ void k_small_compact(const uint32_t* __restrict__ flag,
-                                const uint64_t* __restrict__ rank, const Block* __restrict__ rec,
-                                uint32_t n, uint32_t K_log2, uint64_t cap, const uint64_t* pool,
-                                uint32_t* __restrict__ small_nodes, Block* __restrict__ rec_st,
-                                uint32_t* err) {
-  const uint64_t total = static_cast<uint64_t>(n) * 8;
-  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < total;
-       t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t u = t >> 3;
-    const uint32_t part = static_cast<uint32_t>(t & 7);
-    ulonglong2 v = reinterpret_cast<const ulonglong2*>(rec + u)[part];
-    if (part == 0 && flag[u]) {
-      const uint64_t k = rank[u];
-      if (k >= cap) {
-        atomicOr(err, kErrCapacity);
-      } else {
-        small_nodes[k] = static_cast<uint32_t>(u);
-        // the stitched line carries the address of the node's first entry
-        v.x = reinterpret_cast<uint64_t>(pool + (k << K_log2));
-        v.y |= kPoolFlag;
-      }
-    }
-    reinterpret_cast<ulonglong2*>(rec_st + u)[part] = v;
+// small_nodes[rank] = u: the small nodes in id order (the pool kernel's work list)
+__global__ void k_small_compact(const uint32_t* __restrict__ flag, const uint64_t* __restrict__ rank,
+                                uint32_t n, uint64_t cap, uint32_t* __restrict__ small_nodes, uint32_t* err) {
+  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < n;
+       u += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    if (!flag[u]) continue;
+    const uint64_t k = rank[u];
+    if (k >= cap) atomicOr(err, kErrCapacity);
+    else small_nodes[k] = static_cast<uint32_t>(u);
+  }
+}
+
+// canonical order for export: rank k's entries from node small_nodes[k]'s
+// block, end ids without their tags
+__global__ void k_pool_export(const uint64_t* __restrict__ pool, const uint32_t* __restrict__ small_nodes,
+                              uint64_t n_small, uint32_t K_log2, bool tagged, uint64_t* __restrict__ out) {
+  const uint64_t keep = tagged ? ~static_cast<uint64_t>(~kIdMask & 0xFFFFFFFFu) : ~0ull;
+  const uint64_t total = n_small << K_log2;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t v = small_nodes[i >> K_log2];
+    const uint64_t e = pool[(v << K_log2) + (i & ((1ull << K_log2) - 1))];
+    out[i] = e & keep;
   }
 }
 
@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t count_q(uint4 q, uint64_t X) {
 template <bool kNar>
 __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* __restrict__ small_nodes,
                                                    uint64_t n_small, uint32_t K_log2, uint32_t L,
-                                                   uint32_t T, uint32_t key0, uint32_t key1,
+                                                   uint32_t T, uint32_t key0, uint32_t key1, bool tagged,
                                                    uint64_t* __restrict__ pool) {
   const uint64_t total = n_small << K_log2;
   const uint32_t half = threadIdx.x & 1u;
@@ -102,8 +102,9 @@ __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* 
        idx += stride) {
     const uint32_t j = static_cast<uint32_t>(idx & ((1ull << K_log2) - 1));
     const uint32_t v = small_nodes[idx >> K_log2];
-    uint32_t cur = v, steps = 0, mark = 0;
+    uint32_t cur = v, tag = 0, steps = 0, mark = 0;
     for (uint32_t t = 0; t < L; ++t) {
+      if (tag == kTagDangling) break;  // arrived at a node without out-edges: stays active, no load
       // node line: weight and flags (even lane's first 16 bytes) and top keys
       const uint4* ln = reinterpret_cast<const uint4*>(g.rec + cur) + half * 4;
       const uint4 q0 = ln[0], q1 = ln[1], q2 = ln[2], q3 = ln[3];
@@ -158,7 +159,8 @@ __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* 
         dst = k == 0 ? w.x : (k == 1 ? w.y : (k == 2 ? w.z : w.w));
       }
       dst += pair_swap(dst);
-      cur = dst;
+      cur = tagged ? dst & kIdMask : dst;
+      tag = tagged ? dst >> kTagShift : 0u;
       steps += 1;
       if (x.x2 < T) {
         mark = 1;
@@ -166,8 +168,9 @@ __global__ void __launch_bounds__(kThreads) k_pool(GraphView g, const uint32_t* 
       }
     }
     if (half == 0)
-      pool[idx] = static_cast<uint64_t>(cur) | (static_cast<uint64_t>(steps) << 32) |
-                  (static_cast<uint64_t>(mark) << 48);
+      pool[(static_cast<uint64_t>(v) << K_log2) + j] = static_cast<uint64_t>(cur | (tag << kTagShift)) |
+                                                      (static_cast<uint64_t>(steps) << 32) |
+                                                      (static_cast<uint64_t>(mark) << 48);
   }
 }
 
@@ -181,10 +184,16 @@ hipError_t launch_small_flags(fppr_graph* g, uint32_t S, hipStream_t s) {
 }
 
 hipError_t launch_small_compact(fppr_graph* g, uint32_t /*S*/, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_compact, dim3(grid_for(static_cast<uint64_t>(g->n) * 8)), dim3(kThreads), 0, s,
-                     g->flag, g->scan,
-                     g->rec, g->n, g->K_log2, g->n_small, g->pool, g->small_nodes, g->rec_st,
-                     g->d_err);
+  hipLaunchKernelGGL(k_small_compact, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->flag, g->scan, g->n,
+                     g->n_small, g->small_nodes, g->d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_export(const fppr_graph* g, uint64_t* out, hipStream_t s) {
+  const uint64_t total = g->n_small << g->K_log2;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool_export, dim3(grid_for(total)), dim3(kThreads), 0, s, g->pool, g->small_nodes,
+                     g->n_small, g->K_log2, g->tagged, out);
   return hipGetLastError();
 }
 
@@ -196,11 +205,11 @@ hipError_t launch_pool(fppr_graph* g, hipStream_t s) {
   if (g->narrow)
     hipLaunchKernelGGL(k_pool<true>, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
                        g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,
-                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->pool);
+                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->tagged, g->pool);
   else
     hipLaunchKernelGGL(k_pool<false>, dim3(grid_for(total * 2)), dim3(kThreads), 0, s, gv, g->small_nodes,
                        g->n_small, g->K_log2, g->pool_opts.L, g->pool_T,
-                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->pool);
+                       static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), g->tagged, g->pool);
   return hipGetLastError();
 }
 

@@ -37,6 +37,10 @@
 //   small node (stitched runs): pool entry floor(x0 * K / 2^32) of the node
 //   otherwise: X = floor((x1:x0) * W / 2^64), first edge with prefix > X
 //   stop iff x2 < T (or the stitched entry is terminated), or m hits the cap
+// In graphs of at most 2^30 nodes every destination a leaf block or a pool
+// entry holds carries its node's class, so a move at a node without
+// out-edges needs no load and a stitched move reads only its pool entry
+// (node v's entries sit at v * K); only picks read the tail's node line.
 #include "fppr_internal.hpp"
 
 namespace fppr {
@@ -147,10 +151,11 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
   uint64_t walks = 0;  // walks started by this wave
   const Block* rec = nullptr;
   const Block* blocks = nullptr;
+  const uint64_t* pool = nullptr;
   const uint32_t* sources = nullptr;
   uint32_t* endpoints = nullptr;
   uint64_t first = 0, walk0 = 0, R_magic = 0, src_q0 = 0;
-  uint32_t R = 1, n = 0, T = 0, key0 = 0, key1 = 0, tree_min = 0, K_log2 = 0, dflags = 0;
+  uint32_t R = 1, n = 0, T = 0, key0 = 0, key1 = 0, tree_min = 0, K_log2 = 0, S_small = 0, dflags = 0;
 
   for (;;) {
     // ---- refill idle lanes from the wave's chunk of walk ids ----
@@ -176,7 +181,8 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         if (dn != d) {
           const WalkDesc& Dn = t.descs[dn];
           const bool same_graph = kLaneKeys && d != ~0u && Dn.rec == rec && Dn.blocks == blocks &&
-                                  Dn.tree_min == tree_min && Dn.K_log2 == K_log2;
+                                  Dn.tree_min == tree_min && Dn.K_log2 == K_log2 && Dn.pool == pool &&
+                                  Dn.S_small == S_small;
           if (!same_graph && __ballot(L.ph != kIdle) != 0) {  // finish the running walks first
             pend = c;
             pend_d = dn;
@@ -186,6 +192,8 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           const WalkDesc& D = t.descs[d];
           rec = D.rec;
           blocks = D.blocks;
+          pool = D.pool;
+          S_small = D.S_small;
           sources = D.sources;
           endpoints = D.endpoints;
           first = D.first;
@@ -357,8 +365,14 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
 
     // ---- consume: a finished step, a new move to start, or a search step ----
     bool begin = false, step = false, coin = false;
+    uint32_t tag = 0;                  // class tag of the node a step arrived at
+    const bool tagged = (dflags & kDescTagged) != 0;
     uint64_t bw = L.sW, bod = L.s_od;  // record of the move to start
     if (ph == kSrcRec || ph == kRec) {
+      // a small node of a stitched run (1 <= out-degree <= S_small) is marked
+      // in the register copy of its flags
+      const uint32_t dg = static_cast<uint32_t>(v1 & kDegMask);
+      if (dg - 1u < S_small) v1 |= kPoolFlag;
       if (ph == kSrcRec) {
         L.sW = v0;
         L.s_od = v1;
@@ -382,13 +396,16 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         L.ph = kLeaf;
       }
     } else if (ph == kLeaf) {
-      L.tail = line_res;
+      L.tail = tagged ? line_res & kIdMask : line_res;
+      tag = tagged ? line_res >> kTagShift : 0u;
       L.len += 1;
       step = true;
       coin = L.x2 < (kLaneKeys ? L.T : T);
     } else if (ph == kPool) {
       const uint64_t e = v0;
-      L.tail = static_cast<uint32_t>(e);
+      const uint32_t end = static_cast<uint32_t>(e);
+      L.tail = tagged ? end & kIdMask : end;
+      tag = tagged ? end >> kTagShift : 0u;
       L.len += static_cast<uint32_t>(e >> 32) & 0xFFFFu;
       if (kStats) ++L.st_stitch;
       step = true;
@@ -405,6 +422,14 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         capped = !coin;
       } else if (L.tail == L.s) {
         begin = true;  // back at the head: its weight and flags are in registers
+      } else if (tag == kTagDangling) {
+        begin = true;  // no out-edges (known from the edge's tag): the move restarts, no load
+        bw = 0;
+        bod = 0;
+      } else if (tag == kTagSmall && S_small) {
+        begin = true;  // small node of the pool (known from the tag): the move reads its entry directly
+        bw = 0;
+        bod = kPoolFlag | 1u;
       } else {
         L.ph = kRec;
       }
@@ -436,8 +461,9 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
           }
           continue;
         }
-        if (bod & kPoolFlag) {  // small node: its line holds the pool block address
-          L.X = bw + (((static_cast<uint64_t>(x.x0) << K_log2) >> 32) << 3);
+        if (bod & kPoolFlag) {  // small node: entry floor(x0 K / 2^32) of its K at tail * K
+          const uint64_t slot = (static_cast<uint64_t>(x.x0) << K_log2) >> 32;
+          L.X = reinterpret_cast<uint64_t>(pool + ((static_cast<uint64_t>(L.tail) << K_log2) + slot));
           L.ph = kPool;
           break;
         }
@@ -707,7 +733,7 @@ hipError_t launch_walk(const WalkDesc* descs, const WalkDesc* host, uint32_t nde
 bool same_graph_table(const WalkDesc* h, uint32_t ndesc) {
   for (uint32_t k = 1; k < ndesc; ++k)
     if (h[k].rec != h[0].rec || h[k].blocks != h[0].blocks || h[k].tree_min != h[0].tree_min ||
-        h[k].K_log2 != h[0].K_log2)
+        h[k].K_log2 != h[0].K_log2 || h[k].pool != h[0].pool || h[k].S_small != h[0].S_small)
       return false;
   return ndesc > 1;
 }
