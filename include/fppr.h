@@ -481,6 +481,20 @@ FPPR_API fppr_status fppr_batch_launch(fppr_batch* b, void* stream);
 /* Synchronises `stream`; INVALID_ARGUMENT if a batch run met a source id >= n
  * or (FPPR_BATCH_REBUILD) a graph failed its rebuild's validation. */
 FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream);
+
+/* The batch's run manifest as JSON (host output): for every item its graph
+ * (n, m, layout, hub threshold, tree rows, and the short-walk pool S, L, K,
+ * seed, alpha when one is built: the parameters that change a stitched
+ * run's results, and that a checker must use), its parameters (alpha, R,
+ * seed, top-k, flags), its source count, whether its nodes without
+ * out-edges run in the coin-only kernel, its place in the walk table and
+ * its counting stream; and the launch width. It records the knobs the
+ * autotuner (fppr_autotune) left on each graph before the batch was made
+ * (Sec. 4.3's gamma, chosen and then recorded). json: host buffer of `cap`
+ * bytes or NULL; *needed (required) gets the length including the final
+ * NUL. INVALID_ARGUMENT when json is given and cap < *needed (nothing
+ * written). */
+FPPR_API fppr_status fppr_batch_manifest(const fppr_batch* b, char* json, size_t cap, size_t* needed);
 /* Waits until the batch's last run or replay has finished, then frees the
  * batch (its streams, events and captured graph; not the caller's
  * workspace, graphs or outputs, which may be freed after this returns). */
@@ -588,7 +602,19 @@ typedef struct {
   uint64_t peak_in_flight;     /* most queries in flight at once */
   uint64_t peak_device_bytes;  /* most device memory held by queries */
   fppr_stats walk_stats;       /* summed over all walk launches */
+  uint64_t cancelled;          /* queries cancelled before they completed */
 } fppr_server_counters;
+
+/* Latency statistics over completed queries (latency = submit to results in
+ * pinned host memory). Percentiles are nearest-rank: p50 is the smallest
+ * latency with at least half of the queries at or below it. qps = count /
+ * span, span = first submit to last completion of the counted queries. */
+typedef struct {
+  uint64_t count;
+  double p50_ms, p99_ms, mean_ms, max_ms;
+  double span_s;
+  double qps;
+} fppr_latency;
 
 /* Creates the server and its scheduler thread on the current device (the
  * graph's). The graph (and pool) must stay alive and unchanged until
@@ -603,7 +629,8 @@ FPPR_API fppr_status fppr_server_submit(fppr_server* s, const fppr_query* q, uin
 /* FPPR_NOT_READY while query `id` runs; FPPR_OK once done: copies its results
  * (host buffers: topk [n_sources][k][2] uint32 as for fppr_run, digest
  * [n_sources] uint64; either may be NULL) and `info`, and forgets the id.
- * fppr_server_wait blocks until done. */
+ * fppr_server_wait blocks until done. Both return FPPR_CANCELLED (and forget
+ * the id) for a query cancelled by fppr_server_cancel. */
 FPPR_API fppr_status fppr_server_poll(fppr_server* s, uint64_t id, uint32_t* topk, uint64_t* digest,
                                       fppr_query_info* info);
 FPPR_API fppr_status fppr_server_wait(fppr_server* s, uint64_t id, uint32_t* topk, uint64_t* digest,
@@ -612,7 +639,23 @@ FPPR_API fppr_status fppr_server_wait(fppr_server* s, uint64_t id, uint32_t* top
 /* Counters since create (host output; walk_stats synchronises the device). */
 FPPR_API fppr_status fppr_server_stats(fppr_server* s, fppr_server_counters* out);
 
-/* Finishes every query already submitted, stops the thread, frees everything. */
+/* Latency statistics (host output) over the queries with id >= first_id
+ * that completed since create (0 = all), whether or not their results were
+ * taken. The p50/p99 reported beside throughput (Sec. 4.3's in-flight bound
+ * makes latency, not only throughput, the server's measure). */
+FPPR_API fppr_status fppr_server_latency(fppr_server* s, uint64_t first_id, fppr_latency* out);
+
+/* Cancels query `id` (thread-safe; returns at once). A queued query never
+ * reaches the GPU. An admitted one gets no further walk slices; the work
+ * already queued for it finishes, and its device memory is freed only after
+ * that. A finished query that was not yet taken loses its results. From
+ * then on fppr_server_poll / fppr_server_wait of `id` return FPPR_CANCELLED
+ * (once the GPU is done with it) and forget the id. INVALID_ARGUMENT for an
+ * unknown (or already taken) id. */
+FPPR_API fppr_status fppr_server_cancel(fppr_server* s, uint64_t id);
+
+/* Finishes every query already submitted (queued ones included, unless
+ * cancelled), stops the thread, frees everything. */
 FPPR_API fppr_status fppr_server_destroy(fppr_server* s);
 
 /* Synchronises `stream` and reports whether a run that used `workspace` met

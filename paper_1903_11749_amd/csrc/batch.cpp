@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -53,6 +55,7 @@ struct fppr_batch {
   hipEvent_t done = nullptr;  // recorded behind every run and replay; destroy waits for it
   std::vector<int> graph_lane, item_lane;  // lane of each graph's rebuild / item's counting
   std::vector<bool> split;                 // all-nodes item: coin-only kernel for nodes without out-edges
+  std::vector<BatchRun> runs;              // the walk table (item, first id, walks), largest first
 };
 
 namespace {
@@ -236,6 +239,7 @@ FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t co
     b->host_table.push_back(D);
   }
   b->total = lay.total;
+  b->runs = lay.runs;
   {
     std::vector<uint64_t> gcost(b->graphs.size());
     std::vector<bool> gpin(b->graphs.size(), false);
@@ -334,6 +338,52 @@ FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream) {
         return invalid("graph " + std::to_string(k) + " of the batch failed its rebuild: " + fppr_last_error());
     }
   }
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_batch_manifest(const fppr_batch* b, char* json, size_t cap, size_t* needed) {
+  if (!b || !needed) return invalid("batch or needed is NULL");
+  std::string j = "{\"launch_blocks_per_cu\": " + std::to_string(b->opts.blocks_per_cu) +
+                  ", \"rebuild\": " + ((b->opts.flags & FPPR_BATCH_REBUILD) ? "true" : "false") +
+                  ", \"walk_ids\": " + std::to_string(b->total) + ", \"items\": [";
+  char num[64];
+  auto dbl = [&](double v) {
+    std::snprintf(num, sizeof num, "%.17g", v);
+    return std::string(num);
+  };
+  for (size_t k = 0; k < b->items.size(); ++k) {
+    const fppr_batch_item& it = b->items[k];
+    const fppr_graph* g = it.graph;
+    const fppr_params& p = it.params;
+    uint64_t first = 0, walks = 0;
+    for (const BatchRun& r : b->runs)
+      if (r.item == k) {
+        first = r.first;
+        walks = r.count;
+      }
+    std::string pool = "null";
+    if (g->has_pool)
+      pool = "{\"S\": " + std::to_string(g->pool_opts.S) + ", \"L\": " + std::to_string(g->pool_opts.L) +
+             ", \"K\": " + std::to_string(g->pool_opts.K) + ", \"seed\": " + std::to_string(g->pool_opts.seed) +
+             ", \"alpha\": " + dbl(g->pool_opts.alpha) + ", \"small_nodes\": " + std::to_string(g->n_small) + "}";
+    j += std::string(k ? ", " : "") + "{\"item\": " + std::to_string(k) + ", \"graph\": {\"n\": " +
+         std::to_string(g->n) + ", \"m\": " + std::to_string(g->m) + ", \"layout\": \"" +
+         (g->narrow ? "narrow" : "wide") + "\", \"hub_threshold\": " + std::to_string(g->tree_min) +
+         ", \"tree_rows\": " + std::to_string(g->n_tree) + ", \"pool\": " + pool +
+         "}, \"alpha\": " + dbl(p.alpha) + ", \"R\": " + std::to_string(p.R) +
+         ", \"seed\": " + std::to_string(p.seed) + ", \"topk\": " + std::to_string(p.topk) +
+         ", \"stitch\": " + ((p.flags & FPPR_STITCH) ? "true" : "false") +
+         ", \"flags\": " + std::to_string(p.flags) + ", \"sources\": " + std::to_string(item_sources(it)) +
+         ", \"all_nodes\": " + (it.sources ? "false" : "true") +
+         ", \"coin_only_split\": " + (b->split[k] ? "true" : "false") +
+         ", \"first_walk_id\": " + std::to_string(first) + ", \"launch_walks\": " + std::to_string(walks) +
+         ", \"counting_stream\": " + std::to_string(b->item_lane[k]) + "}";
+  }
+  j += "]}";
+  *needed = j.size() + 1;
+  if (!json) return FPPR_OK;
+  if (cap < *needed) return invalid("manifest buffer too small (see *needed)");
+  std::memcpy(json, j.c_str(), j.size() + 1);
   return FPPR_OK;
 }
 

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -109,7 +110,7 @@ class Arena {
   uint64_t used_ = 0, peak_ = 0;
 };
 
-enum class St { kQueued, kActive, kAggregating, kDone };
+enum class St { kQueued, kActive, kAggregating, kDone, kCancelled };
 
 struct Req {
   uint64_t id = 0;
@@ -127,6 +128,12 @@ struct Req {
   hipEvent_t done = nullptr;
   fppr_query_info info{};
   St st = St::kQueued;
+  bool cancel = false;  // set by fppr_server_cancel while the query is on the GPU
+};
+
+// submit and completion times of a finished query, for the latency statistics
+struct Done {
+  uint64_t id, submit_ns, done_ns;
 };
 
 // device: sources | endpoints | top-k | digests
@@ -167,6 +174,7 @@ struct fppr_server {
   bool failed = false;
   std::string error;
   fppr_server_counters st{};
+  std::vector<Done> finished;  // every completed query since create, in completion order
   std::thread thr;
 };
 
@@ -193,6 +201,17 @@ bool enqueue_aggregate(fppr_server* S, Req* r, hipStream_t s) {
     return fail(S, e, "copy top-k");
   if ((e = hipMemcpyAsync(r->h_digest, r->d_digest, r->n * 8ull, hipMemcpyDeviceToHost, s)) != hipSuccess)
     return fail(S, e, "copy digests");
+  if ((e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming)) != hipSuccess) return fail(S, e, "event");
+  if ((e = hipEventRecord(r->done, s)) != hipSuccess) return fail(S, e, "event record");
+  r->st = St::kAggregating;
+  return true;
+}
+
+// A cancelled query still on the GPU: no counting; an event behind what is
+// already queued for it (the caller made agg_s wait for the slices in flight)
+// frees its memory once the kernels that use it have finished.
+bool enqueue_retire(fppr_server* S, Req* r, hipStream_t s) {
+  hipError_t e;
   if ((e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming)) != hipSuccess) return fail(S, e, "event");
   if ((e = hipEventRecord(r->done, s)) != hipSuccess) return fail(S, e, "event record");
   r->st = St::kAggregating;
@@ -252,9 +271,16 @@ void loop(fppr_server* S) {
       std::lock_guard<std::mutex> lk(S->mu);
       r->info.done_ns = now_ns();
       S->dev_arena.release(r->dev_off, r->dev_bytes);
-      r->st = St::kDone;
       --S->in_flight;
-      ++S->st.completed;
+      if (r->cancel) {  // results not wanted: the pinned staging goes too
+        S->host_arena.release(r->host_off, r->host_bytes);
+        r->st = St::kCancelled;
+        ++S->st.cancelled;
+      } else {
+        r->st = St::kDone;
+        ++S->st.completed;
+        S->finished.push_back(Done{r->id, r->info.submit_ns, r->info.done_ns});
+      }
       S->cv_done.notify_all();
       progress = true;
     }
@@ -317,6 +343,35 @@ void loop(fppr_server* S) {
       aggregating.push_back(r);
       std::lock_guard<std::mutex> lk(S->mu);
       ++S->st.slices;
+    }
+    // 4a. cancelled admitted queries get no more walks; their memory is freed
+    // once the slices in flight (which may hold their walks) have finished
+    {
+      std::vector<Req*> gone;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto it = active.begin(); it != active.end();) {
+          if ((*it)->cancel) {
+            gone.push_back(*it);
+            it = active.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      if (!gone.empty()) {
+        for (int x : slices) {
+          if (hipStreamWaitEvent(S->agg_s, S->ev[x], 0) != hipSuccess) {
+            fail(S, hipErrorUnknown, "stream wait");
+            return;
+          }
+        }
+        for (Req* r : gone) {
+          if (!enqueue_retire(S, r, S->agg_s)) return;
+          aggregating.push_back(r);
+        }
+        progress = true;
+      }
     }
     // 4. continuous: the next slice over every admitted query with walks left
     if (!fifo && !active.empty() && slices.size() < kMaxSlicesInFlight) {
@@ -427,6 +482,14 @@ void free_server(fppr_server* S) {
   if (S->up_ev) (void)hipEventDestroy(S->up_ev);
   if (S->agg_s) (void)hipStreamDestroy(S->agg_s);
   delete S;
+}
+
+// poll / wait of a cancelled query: FPPR_CANCELLED, and the id is forgotten
+fppr_status forget_cancelled(fppr_server* S, Req* r) {
+  S->reqs.erase(r->id);
+  delete r;
+  set_error("query was cancelled");
+  return FPPR_CANCELLED;
 }
 
 fppr_status take_result(fppr_server* S, Req* r, uint32_t* topk, uint64_t* digest, fppr_query_info* info) {
@@ -561,6 +624,7 @@ FPPR_API fppr_status fppr_server_poll(fppr_server* S, uint64_t id, uint32_t* top
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->reqs.find(id);
   if (it == S->reqs.end()) return invalid("unknown query id");
+  if (it->second->st == St::kCancelled) return forget_cancelled(S, it->second);
   if (it->second->st != St::kDone) {
     if (S->failed) {
       set_error(S->error);
@@ -579,6 +643,7 @@ FPPR_API fppr_status fppr_server_wait(fppr_server* S, uint64_t id, uint32_t* top
     auto it = S->reqs.find(id);
     if (it == S->reqs.end()) return invalid("unknown query id");
     if (it->second->st == St::kDone) return take_result(S, it->second, topk, digest, info);
+    if (it->second->st == St::kCancelled) return forget_cancelled(S, it->second);
     if (S->failed) {
       set_error(S->error);
       return FPPR_DEVICE_ERROR;
@@ -595,6 +660,72 @@ FPPR_API fppr_status fppr_server_stats(fppr_server* S, fppr_server_counters* out
   std::lock_guard<std::mutex> lk(S->mu);
   *out = S->st;
   out->walk_stats = ws;
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_server_cancel(fppr_server* S, uint64_t id) {
+  if (!S) return invalid("server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return invalid("unknown query id");
+    Req* r = it->second;
+    switch (r->st) {
+      case St::kQueued:  // never admitted: nothing on the GPU
+        S->queued.erase(std::find(S->queued.begin(), S->queued.end(), r));
+        S->host_arena.release(r->host_off, r->host_bytes);
+        r->st = St::kCancelled;
+        ++S->st.cancelled;
+        break;
+      case St::kDone:  // finished but not taken: its results are dropped
+        S->host_arena.release(r->host_off, r->host_bytes);
+        r->st = St::kCancelled;
+        break;
+      case St::kActive:
+      case St::kAggregating:
+        r->cancel = true;  // the scheduler stops its walks and frees it when the GPU is done with it
+        break;
+      case St::kCancelled:
+        break;
+    }
+  }
+  S->cv_work.notify_all();
+  S->cv_done.notify_all();
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_server_latency(fppr_server* S, uint64_t first_id, fppr_latency* out) {
+  if (!S || !out) return invalid("server or out is NULL");
+  std::vector<uint64_t> lat;
+  uint64_t t0 = ~0ull, t1 = 0;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    lat.reserve(S->finished.size());
+    for (const Done& d : S->finished) {
+      if (d.id < first_id) continue;
+      lat.push_back(d.done_ns - d.submit_ns);
+      t0 = std::min(t0, d.submit_ns);
+      t1 = std::max(t1, d.done_ns);
+    }
+  }
+  *out = fppr_latency{};
+  out->count = lat.size();
+  if (lat.empty()) return FPPR_OK;
+  std::sort(lat.begin(), lat.end());
+  // nearest-rank percentile: the smallest latency with at least q of the queries at or below it
+  auto pct = [&](double q) {
+    uint64_t r = static_cast<uint64_t>(std::ceil(q * static_cast<double>(lat.size())));
+    if (r < 1) r = 1;
+    return static_cast<double>(lat[r - 1]) * 1e-6;
+  };
+  double sum = 0.0;
+  for (uint64_t v : lat) sum += static_cast<double>(v);
+  out->p50_ms = pct(0.50);
+  out->p99_ms = pct(0.99);
+  out->mean_ms = sum / static_cast<double>(lat.size()) * 1e-6;
+  out->max_ms = static_cast<double>(lat.back()) * 1e-6;
+  out->span_s = static_cast<double>(t1 - t0) * 1e-9;
+  out->qps = out->span_s > 0 ? static_cast<double>(lat.size()) / out->span_s : 0.0;
   return FPPR_OK;
 }
 

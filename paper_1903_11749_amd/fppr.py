@@ -126,7 +126,13 @@ class fppr_server_counters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("slices", ctypes.c_uint64), ("walk_launches", ctypes.c_uint64),
                 ("peak_in_flight", ctypes.c_uint64), ("peak_device_bytes", ctypes.c_uint64),
-                ("walk_stats", fppr_stats_t)]
+                ("walk_stats", fppr_stats_t), ("cancelled", ctypes.c_uint64)]
+
+
+class fppr_latency(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("span_s", ctypes.c_double),
+                ("qps", ctypes.c_double)]
 
 
 _lib = None
@@ -189,6 +195,10 @@ _SIGS = [
     ("fppr_server_wait", ctypes.c_int, [P, ctypes.c_uint64, P, P, ctypes.POINTER(fppr_query_info)]),
     ("fppr_server_stats", ctypes.c_int, [P, ctypes.POINTER(fppr_server_counters)]),
     ("fppr_server_destroy", ctypes.c_int, [P]),
+    ("fppr_server_cancel", ctypes.c_int, [P, ctypes.c_uint64]),
+    ("fppr_server_latency", ctypes.c_int, [P, ctypes.c_uint64, ctypes.POINTER(fppr_latency)]),
+    ("fppr_batch_manifest", ctypes.c_int, [P, ctypes.c_char_p, ctypes.c_size_t,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
     ("fppr_last_error", ctypes.c_char_p, []),
 ]
 
@@ -654,6 +664,16 @@ class Batch:
     def check(self, stream=None):
         _check(lib().fppr_batch_check(self._h, _stream_ptr(stream)))
 
+    def manifest(self) -> dict:
+        """The library's run manifest (fppr_batch_manifest) as a dict."""
+        import json
+
+        need = ctypes.c_size_t()
+        _check(lib().fppr_batch_manifest(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().fppr_batch_manifest(self._h, buf, need.value, ctypes.byref(need)))
+        return json.loads(buf.value.decode())
+
     def close(self):
         if getattr(self, "_h", None):
             lib().fppr_batch_destroy(self._h)
@@ -692,6 +712,8 @@ class Server:
         return qid.value
 
     def _take(self, fn, qid):
+        if qid not in self._shape:
+            raise FpprError(FPPR_INVALID_ARGUMENT, "unknown query id")
         n, k = self._shape[qid]
         topk = np.empty((n, k, 2), dtype=np.uint32)
         digest = np.empty(n, dtype=np.uint64)
@@ -699,6 +721,8 @@ class Server:
         st = fn(self._h, qid, topk.ctypes.data, digest.ctypes.data, ctypes.byref(info))
         if st == FPPR_NOT_READY:
             return None
+        if st == FPPR_CANCELLED:
+            del self._shape[qid]
         _check(st)
         del self._shape[qid]
         return topk, digest, dict(submit_ns=info.submit_ns, admit_ns=info.admit_ns, done_ns=info.done_ns,
@@ -709,6 +733,16 @@ class Server:
 
     def wait(self, qid):
         return self._take(lib().fppr_server_wait, qid)
+
+    def cancel(self, qid):
+        """fppr_server_cancel: poll/wait of qid then raise FpprError(FPPR_CANCELLED)."""
+        _check(lib().fppr_server_cancel(self._h, int(qid)))
+
+    def latency(self, first_id=0):
+        """fppr_server_latency over completed queries with id >= first_id."""
+        lt = fppr_latency()
+        _check(lib().fppr_server_latency(self._h, int(first_id), ctypes.byref(lt)))
+        return {f: getattr(lt, f) for f, _ in fppr_latency._fields_}
 
     def stats(self):
         st = fppr_server_counters()

@@ -251,3 +251,32 @@ def test_destroy_waits_for_the_last_replay(fp, items):
     for (c, d), o in zip(want, outs):
         assert np.array_equal(u32(o.counts), c)
         assert np.array_equal(u64(o.digest), d)
+
+
+def test_manifest_records_each_items_knobs(fp, items):
+    """fppr_batch_manifest: every item's graph layout, hub threshold and pool
+    (S, L, K, seed), its parameters, and a walk table that tiles the launch."""
+    say("case: batch manifest")
+    B = fp.Batch(items, blocks_per_cu=2)
+    m = B.manifest()
+    assert m["launch_blocks_per_cu"] == 2 and len(m["items"]) == len(items)
+    runs = []
+    for it, mi in zip(items, m["items"]):
+        assert mi["R"] == it["R"] and mi["seed"] == it["seed"] and mi["topk"] == it["topk"]
+        assert abs(mi["alpha"] - it["alpha"]) < 1e-15 and mi["stitch"] == it["stitch"]
+        assert mi["graph"]["n"] == it["csr"].n and mi["graph"]["m"] == it["csr"].m
+        assert mi["graph"]["layout"] == ("narrow" if it["graph"].layout() == fp.FPPR_LAYOUT_NARROW else "wide")
+        if it["stitch"]:
+            assert mi["graph"]["pool"] == dict(S=16, L=3, K=32, seed=it["seed"] + 100, alpha=it["alpha"],
+                                               small_nodes=it["graph"].info()["small"])
+        n_src = it["csr"].n if it["sources"] is None else len(it["sources"])
+        assert mi["sources"] == n_src and mi["all_nodes"] == (it["sources"] is None)
+        if mi["launch_walks"]:
+            runs.append((mi["first_walk_id"], mi["launch_walks"]))
+    runs.sort()
+    pos = 0
+    for first, walks in runs:
+        assert first == pos
+        pos = first + (walks + 255) // 256 * 256
+    assert pos == m["walk_ids"]
+    B.close()

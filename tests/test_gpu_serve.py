@@ -53,20 +53,36 @@ def alone(fp, G, q):
     return o.topk.cpu().numpy().view(np.uint32), o.digest.cpu().numpy().view(np.uint64)
 
 
-def serve_all(fp, G, queries, **kw):
+def serve_all(fp, G, queries, want_latency=False, **kw):
     S = fp.Server(G, **kw)
     ids = [S.submit(q["sources"], q["R"], q["alpha"], q["seed"], q["topk"], q["stitch"]) for q in queries]
     out = [S.wait(i) for i in ids]
     st = S.stats()
+    lat = S.latency()
     S.close()
-    return out, st
+    return (out, st, lat) if want_latency else (out, st)
+
+
+def nearest_rank(v, q):
+    v = np.sort(np.asarray(v, dtype=np.float64))
+    return v[max(1, int(np.ceil(q * v.size))) - 1]
 
 
 def test_continuous_equals_alone_and_oracle(fp, world):
     g, G, queries = world
     say("case: 40 mixed queries, continuous, 2^16-walk slices")
-    out, st = serve_all(fp, G, queries, mode="continuous", max_requests=16, slice_walks=1 << 16)
+    out, st, lat = serve_all(fp, G, queries, want_latency=True, mode="continuous", max_requests=16,
+                             slice_walks=1 << 16)
     say(f"  stats: {st}")
+    say(f"  latency: {lat}")
+    # the library's latency statistics are those of the queries' own times
+    ms = [(info["done_ns"] - info["submit_ns"]) * 1e-6 for _, _, info in out]
+    assert lat["count"] == len(queries)
+    assert abs(lat["p50_ms"] - nearest_rank(ms, 0.5)) < 1e-6
+    assert abs(lat["p99_ms"] - nearest_rank(ms, 0.99)) < 1e-6
+    assert abs(lat["max_ms"] - max(ms)) < 1e-6 and abs(lat["mean_ms"] - np.mean(ms)) < 1e-6
+    span = (max(i["done_ns"] for _, _, i in out) - min(i["submit_ns"] for _, _, i in out)) * 1e-9
+    assert abs(lat["qps"] - len(queries) / span) < 1e-6 * lat["qps"]
     assert st["completed"] == len(queries)
     assert st["slices"] > len(queries)  # queries spanned several slices
     assert st["peak_in_flight"] > 1
@@ -140,3 +156,69 @@ def test_invalid_queries_and_backpressure(fp, world):
     for i in ids[1:]:
         S.wait(i)
     S.close()
+
+
+def test_cancel_queued_in_flight_and_finished(fp, world):
+    """One query in flight at a time: a long query is cancelled while its
+    slices run, a queued one before it reaches the GPU, a finished one
+    before its results are taken. Each then polls as FPPR_CANCELLED; the
+    others keep their results; the cancelled query's memory comes back."""
+    import time
+
+    g, G, queries = world
+    say("case: cancel queued, in-flight and finished queries")
+    rng = np.random.default_rng(2040)
+    S = fp.Server(G, mode="continuous", max_requests=1, memory_bytes=96 << 20, slice_walks=1 << 16)
+    big = dict(sources=rng.integers(0, g.n, 300).astype(np.uint32), R=60000, alpha=0.15, seed=7, topk=64,
+               stitch=True)  # 72 MB of endpoints, ~275 slices of 2^16 walks
+    small = [dict(sources=rng.integers(0, g.n, 20).astype(np.uint32), R=500, alpha=0.15, seed=70 + i, topk=16,
+                  stitch=bool(i % 2)) for i in range(3)]
+    sub = lambda q: S.submit(q["sources"], q["R"], q["alpha"], q["seed"], q["topk"], q["stitch"])
+    a = sub(big)
+    b, c, d = (sub(q) for q in small)
+    t0 = time.time()
+    while S.stats()["slices"] < 3 and time.time() - t0 < 30:  # the big query is on the GPU
+        time.sleep(0.001)
+    assert S.stats()["slices"] >= 3
+    S.cancel(c)  # still queued behind the big one
+    S.cancel(a)  # in flight
+    for qid in (a, c):
+        with pytest.raises(fp.FpprError) as ei:
+            S.wait(qid)
+        assert ei.value.status == fp.FPPR_CANCELLED
+    with pytest.raises(fp.FpprError):  # forgotten after FPPR_CANCELLED
+        S.poll(a)
+    for qid, q in ((b, small[0]), (d, small[2])):
+        topk, digest, _ = S.wait(qid)
+        t, dg = alone(fp, G, q)
+        assert np.array_equal(topk, t) and np.array_equal(digest, dg)
+    st = S.stats()
+    assert st["cancelled"] == 2 and st["completed"] == 2
+    assert st["walk_stats"]["walks"] < big["sources"].size * big["R"]  # the rest was never launched
+    # the big query's memory is free again: the same query runs to the end
+    e = sub(big)
+    topk, digest, _ = S.wait(e)
+    t, dg = alone(fp, G, big)
+    assert np.array_equal(topk, t) and np.array_equal(digest, dg)
+    # a finished query whose results were not taken
+    f = sub(small[1])
+    t0 = time.time()
+    while S.stats()["completed"] < 4 and time.time() - t0 < 30:
+        time.sleep(0.001)
+    S.cancel(f)
+    with pytest.raises(fp.FpprError) as ei:
+        S.poll(f)
+    assert ei.value.status == fp.FPPR_CANCELLED
+    S.close()
+
+
+def test_destroy_with_work_queued(fp, world):
+    """Destroying a server right after submitting (queries queued and in
+    flight, one cancelled) finishes the rest and returns cleanly."""
+    g, G, queries = world
+    say("case: destroy with queued work")
+    for mode in ("continuous", "fifo"):
+        S = fp.Server(G, mode=mode, max_requests=2, slice_walks=1 << 16)
+        ids = [S.submit(q["sources"], q["R"], q["alpha"], q["seed"], q["topk"], q["stitch"]) for q in queries[:12]]
+        S.cancel(ids[5])
+        S.close()  # raises if the library reports a failure
