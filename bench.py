@@ -200,10 +200,32 @@ def _bench_batch(args, fppr, torch, np, stream):
         got = B.outputs[i]
         oracle_ok &= bool(np.array_equal(got.digest.cpu().numpy().view(np.uint64), ref.digest)
                           and np.array_equal(got.topk.cpu().numpy().view(np.uint32), ref.topk))
+    # and a stratified sample of the rest: every 7th graph by size (large,
+    # autotuned, stitched ones included), 1,024 random sources each
+    rest = sorted(range(len(specs)), key=lambda i: specs[i]["n"])[4::7]
+    sampled_ok, sampled_graphs, sampled_stitched = True, 0, 0
+    rs = np.random.default_rng(4242)
+    for i in rest:
+        og = O.Graph.from_csr(graphs[i])
+        pool = None
+        if manifest[i]["pool"] is not None:
+            po = manifest[i]["pool"]
+            pool = O.Pool(og, S=po["S"], L=po["L"], K=po["K"], alpha=specs[i]["alpha"], seed=po["seed"])
+            sampled_stitched += 1
+        src = np.sort(rs.choice(graphs[i].n, min(1024, graphs[i].n), replace=False)).astype(np.uint32)
+        ref = O.run(og, specs[i]["alpha"], specs[i]["R"], specs[i]["walk_seed"], sources=src, topk=BATCH_TOPK,
+                    pool=pool, want_counts=False)
+        got = B.outputs[i]
+        sampled_ok &= bool(np.array_equal(got.digest.cpu().numpy().view(np.uint64)[src], ref.digest)
+                           and np.array_equal(got.topk.cpu().numpy().view(np.uint32)[src], ref.topk))
+        sampled_graphs += 1
+    log(f"batch: oracle on the 4 smallest graphs {oracle_ok}, on 1024 sources of {sampled_graphs} more "
+        f"({sampled_stitched} stitched) {sampled_ok}")
     n_src = sum(g.n for g in graphs)
+    lib_manifest = B.manifest()
     if args.manifest:
         with open(args.manifest, "w") as fh:
-            json.dump(dict(graphs=manifest, batch_blocks_per_cu=width), fh, indent=1)
+            json.dump(dict(tuner=manifest, batch=lib_manifest), fh, indent=1)
     res = {
         "workload": ("64 directed Chung-Lu graphs, n log-uniform in [1e3, 1e6], mean degree U[8,24], "
                      "exponent U[2.1,2.5], weights U{1..255}, alpha in {.1,.15,.2}, R in {64,256}, "
@@ -216,6 +238,8 @@ def _bench_batch(args, fppr, torch, np, stream):
         "plain_sources_per_s": round(n_src / (plain_ms / 1e3), 1),
         "speedup": round(plain_ms / batch_ms, 3),
         "bit_exact_vs_plain": bool(same), "oracle_bit_exact_smallest4": bool(oracle_ok),
+        "oracle_bit_exact_sampled": {"graphs": sampled_graphs, "stitched_graphs": sampled_stitched,
+                                     "sources_each": 1024, "bit_exact": bool(sampled_ok)},
         "tuning_s": round(tune_s, 2),
         "tuned": {"stitched_graphs": sum(m["pool"] is not None for m in manifest),
                   "hub_thresholds": dict(collections.Counter(str(m["hub_threshold"]) for m in manifest)),
@@ -231,10 +255,11 @@ SERVE_TOPK = 64
 SERVE_ALPHA = 0.15
 
 
-def _serve_run(fppr, G, queries, mode, times=None, stitch=True, **kw):
+def _serve_run(fppr, G, queries, mode, times=None, stitch=True, first_counted=0, **kw):
     """Submits `queries` (at their arrival offsets in `times`, seconds, or all
-    at once) and collects every result. Returns (results by query, per-query
-    latency s, makespan s, server stats)."""
+    at once) and collects every result. Returns (results by query, the
+    library's latency statistics over queries first_counted.., makespan s,
+    server stats)."""
     import collections
 
     import numpy as np
@@ -270,10 +295,10 @@ def _serve_run(fppr, G, queries, mode, times=None, stitch=True, **kw):
         drain()
     drain(block=True)
     st = S.stats()
+    lat = S.latency(first_id=ids[first_counted])  # ids grow in submission order
     S.close()
     sub = np.array([results[i][2]["submit_ns"] for i in range(len(queries))], dtype=np.float64)
     done = np.array([results[i][2]["done_ns"] for i in range(len(queries))], dtype=np.float64)
-    lat = (done - sub) / 1e9
     makespan = (done.max() - sub.min()) / 1e9
     return results, lat, makespan, st
 
@@ -302,12 +327,12 @@ def bench_serve(args, fppr, torch, G, n_nodes, oracle_pool=None, oracle_graph=No
     out = {}
     res_by_mode = {}
     for mode in ("fifo", "continuous"):
-        res, lat, span, st = _serve_run(fppr, G, queries, mode, times=times, **kw)
-        m = lat[warm:]
-        out[mode] = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
-                     "mean_ms": round(float(m.mean()) * 1e3, 3),
-                     "queries_per_s": round(len(lat) / span, 2),
+        res, lat, span, st = _serve_run(fppr, G, queries, mode, times=times, first_counted=warm, **kw)
+        out[mode] = {"p50_ms": round(lat["p50_ms"], 3), "p99_ms": round(lat["p99_ms"], 3),
+                     "mean_ms": round(lat["mean_ms"], 3), "max_ms": round(lat["max_ms"], 3),
+                     "latency_from": "fppr_server_latency over the queries after the warm-up",
+                     "counted_queries": int(lat["count"]), "counted_qps": round(lat["qps"], 2),
+                     "queries_per_s": round(len(queries) / span, 2),
                      "sources_per_s": round(sum(q["sources"].size for q in queries) / span, 1),
                      "walk_steps_per_s": round(st["walk_stats"]["steps"] / span, 1),
                      "walks": int(st["walk_stats"]["walks"]), "slices": int(st["slices"]),
@@ -318,10 +343,14 @@ def bench_serve(args, fppr, torch, G, n_nodes, oracle_pool=None, oracle_graph=No
     same = all(np.array_equal(res_by_mode["fifo"][i][0], res_by_mode["continuous"][i][0]) and
                np.array_equal(res_by_mode["fifo"][i][1], res_by_mode["continuous"][i][1])
                for i in range(len(queries)))
-    # a sample rerun alone with fppr_run
-    rng = np.random.default_rng(17)
+    # 200 queries stratified by walk budget (every budget decile, small and
+    # large R, few and many sources): each rerun alone with fppr_run, and in
+    # the oracle on two of its sources (sources are independent, so a
+    # source's row is exact on its own) plus every source of the 3 smallest
+    order = sorted(range(len(queries)), key=lambda i: queries[i]["sources"].size * queries[i]["R"])
+    pick = [order[int(j)] for j in np.linspace(0, len(order) - 1, min(200, len(order)))]
     alone_ok = True
-    for i in rng.choice(len(queries), 8, replace=False):
+    for i in pick:
         q = queries[i]
         o = fppr.run(G, SERVE_ALPHA, q["R"], q["seed"], sources=q["sources"], topk=SERVE_TOPK, stitch=True,
                      counts=False, stats=False)
@@ -329,18 +358,22 @@ def bench_serve(args, fppr, torch, G, n_nodes, oracle_pool=None, oracle_graph=No
         alone_ok &= bool(np.array_equal(o.topk.cpu().numpy().view(np.uint32), res_by_mode["continuous"][i][0])
                          and np.array_equal(o.digest.cpu().numpy().view(np.uint64),
                                             res_by_mode["continuous"][i][1]))
-    oracle_ok = None
+    oracle_ok, oracle_walks = None, 0
     if oracle_pool is not None:
         from oracle import oracle as O
 
-        small = sorted(range(len(queries)), key=lambda i: queries[i]["sources"].size * queries[i]["R"])[:3]
+        rng = np.random.default_rng(17)
         oracle_ok = True
-        for i in small:
+        for i in list(pick) + order[:3]:
             q = queries[i]
-            ref = O.run(oracle_graph, SERVE_ALPHA, q["R"], q["seed"], sources=q["sources"], topk=SERVE_TOPK,
+            rows = (np.arange(q["sources"].size) if i in order[:3]
+                    else np.unique(rng.choice(q["sources"].size, min(2, q["sources"].size), replace=False)))
+            ref = O.run(oracle_graph, SERVE_ALPHA, q["R"], q["seed"], sources=q["sources"][rows], topk=SERVE_TOPK,
                         pool=oracle_pool, want_counts=False)
-            oracle_ok &= bool(np.array_equal(res_by_mode["continuous"][i][0], ref.topk)
-                              and np.array_equal(res_by_mode["continuous"][i][1], ref.digest))
+            oracle_walks += rows.size * q["R"]
+            oracle_ok &= bool(np.array_equal(res_by_mode["continuous"][i][0][rows], ref.topk)
+                              and np.array_equal(res_by_mode["continuous"][i][1][rows], ref.digest))
+        log(f"serve: {len(pick)} queries alone {alone_ok}, oracle {oracle_ok} ({oracle_walks} walks)")
     return {
         "workload": (f"resident rmat-scale24 graph + short-walk pool; {nq} Poisson queries after {warm} "
                      "warm-up, 1..1024 uniform sources each, R log-uniform in [1e3, 1e5], alpha 0.15, "
@@ -349,9 +382,129 @@ def bench_serve(args, fppr, torch, G, n_nodes, oracle_pool=None, oracle_graph=No
         "continuous_saturation_qps": round(cont_sat, 2),
         "fifo": out["fifo"], "continuous": out["continuous"],
         "p99_speedup": round(out["fifo"]["p99_ms"] / out["continuous"]["p99_ms"], 3),
-        "bit_exact_fifo_vs_continuous": bool(same), "bit_exact_alone_sample8": bool(alone_ok),
-        "oracle_bit_exact_smallest3": oracle_ok,
+        "bit_exact_fifo_vs_continuous": bool(same),
+        "replay": {"queries": len(pick), "stratified_by": "walk budget n_sources x R",
+                   "bit_exact_alone": bool(alone_ok),
+                   "oracle": ("two random sources of each of the 200 queries and every source of the 3 "
+                              "smallest, full R"),
+                   "oracle_walks": int(oracle_walks), "oracle_bit_exact": oracle_ok},
     }
+
+
+PAPER_REFERENCE = {
+    "absolute_numbers": None,
+    "note": ("the paper prints no absolute running times or rates for this path (its result "
+             "plots are not in the text), so vs_baseline is null; its relative figures, "
+             "with the hardware they were measured on:"),
+    "hardware": ("51 machines (1 master + 50 workers), each a 12-core Intel Xeon E5-2670 with "
+                 "16 GB RAM, Spark 2.0 / Scala; 13 SNAP graphs of 5K-68M nodes and 29K-2.6B edges; "
+                 "eps = delta = alpha = 0.5, p_f = 1/n; mean of 3 runs, 24 h cutoff"),
+    "relative": {
+        "vs Doubling and GraphX-PPR": "up to two orders of magnitude faster (Sec. 5)",
+        "big moves": "about 1.5x (Fig. 5(b))",
+        "alias tree": "about 1.0x, but needed for Twitter (d_max about 3.0M)",
+        "all three optimisations": "up to 2x",
+        "accuracy vs Doubling": "NDCG up to +21 %, MAP up to +19 % at top-1000 (Sec. 5.2)",
+    },
+}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def ablation(args, fppr, torch, np, g, ro, col, w, cfg, st_cfg, stream, value, ms_per_step):
+    """The paper's optimisation ablation (Fig. 5(b)) on this path: the same
+    step without the short-walk pool (plain walks) and without prefix trees
+    (every row binary-searched over its leaf blocks), each as a graph of
+    its own on the same borrowed CSR, timed like the main step."""
+    alpha, R, seed, k = cfg["alpha"], cfg["R"], cfg["seed"], cfg["topk"]
+    variants = {"stitched_trees": {"ms_per_step": round(ms_per_step, 3), "walk_steps_per_s": round(value, 1)}}
+    for name, stitch, H in (("plain_trees", False, 0), ("stitched_no_trees", True, 0xFFFFFFFF),
+                            ("plain_no_trees", False, 0xFFFFFFFF)):
+        G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=H)
+        if stitch:
+            G.build_pool(S=st_cfg["S"], L=st_cfg["L"], K=st_cfg["K"], alpha=alpha, seed=st_cfg["seed"])
+        p = fppr.make_params(alpha, R, seed, k, stitch=stitch, counts=False, digests=True, stats=True)
+        ws = torch.empty((fppr.fppr_plan(G, p, g.n) + 7) // 8, dtype=torch.int64, device="cuda")
+        o = fppr.alloc_outputs(g.n, R, k, counts=False, digests=True, stats=True)
+
+        def one():
+            o.stats.zero_()
+            G.rebuild(stream)
+            fppr.fppr_run(G, p, None, g.n, ws, o, stream)
+
+        for _ in range(2):
+            one()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            one()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        st = o.stats_dict()
+        variants[name] = {"ms_per_step": round(ms, 3), "walk_steps_per_s": round(st["steps"] / (ms / 1e3), 1),
+                          "moves": st["moves"], "steps": st["steps"]}
+        log(f"ablation {name}: {ms:.1f} ms per step")
+        del ws, o
+        G.close()
+        torch.cuda.synchronize()
+    base = variants["stitched_trees"]["ms_per_step"]
+    for v in variants.values():
+        v["slowdown_vs_full"] = round(v["ms_per_step"] / base, 3)
+    return {"what": ("the scale-24 step without the short-walk pool (plain walks: results differ, "
+                     "same law) and without prefix trees (identical results), like Fig. 5(b)"),
+            "variants": variants}
+
+
+def full_parity(args, g, G, out, cfg, st_cfg):
+    """Every source of the workload against the oracle (digest and top-k of
+    each), in blocks of sources logged as they finish."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    alpha, R, seed, k = cfg["alpha"], cfg["R"], cfg["seed"], cfg["topk"]
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    og = O.Graph.from_csr(g)
+    pool = None
+    t0 = time.perf_counter()
+    if st_cfg:
+        pool = O.Pool(og, S=st_cfg["S"], L=st_cfg["L"], K=st_cfg["K"], alpha=alpha, seed=st_cfg["seed"],
+                      nthreads=nthreads)
+        log(f"full parity: oracle pool {time.perf_counter() - t0:.1f}s")
+        ok_pool = bool(np.array_equal(G.export_pool(), pool.entries()))
+        log(f"full parity: pool equal entry for entry: {ok_pool}")
+    else:
+        ok_pool = None
+    dig = out.digest.cpu().numpy().view(np.uint64)
+    top = out.topk.cpu().numpy().view(np.uint32)
+    block = 1 << 20
+    bad, steps, moves = 0, 0, 0
+    t0 = time.perf_counter()
+    for b0 in range(0, g.n, block):
+        src = np.arange(b0, min(g.n, b0 + block), dtype=np.uint32)
+        ref = O.run(og, alpha, R, seed, sources=src, topk=k, pool=pool, nthreads=nthreads, want_counts=False)
+        bad += int(np.count_nonzero((ref.digest != dig[src]) | np.any(ref.topk != top[src], axis=(1, 2))))
+        steps += ref.stats["steps"]
+        moves += ref.stats["moves"]
+        log(f"full parity: sources {b0}..{src[-1]} done, {bad} differing so far, "
+            f"{time.perf_counter() - t0:.0f}s")
+    gpu = out.stats_dict()
+    res = {"full_parity": {"workload": "rmat-scale24 all sources" if st_cfg else "all sources",
+                           "sources": int(g.n), "walks": int(g.n) * R, "differing_sources": bad,
+                           "pool_equal": ok_pool, "oracle_steps": int(steps), "gpu_steps": gpu["steps"],
+                           "oracle_moves": int(moves), "gpu_moves": gpu["moves"],
+                           "oracle_seconds": round(time.perf_counter() - t0, 1), "oracle_threads": nthreads}}
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -375,6 +528,12 @@ def main():
                     help="rows above this many edges get a prefix tree (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device 3 times (scale for byte counters)")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the runs without stitching and without prefix trees")
+    ap.add_argument("--cpu-sample-1t", type=int, default=1 << 14,
+                    help="sources of the oracle's one-thread timing (0 = skip)")
+    ap.add_argument("--full-parity", action="store_true",
+                    help="one step, then every source checked against the oracle (scale 24: minutes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -419,7 +578,8 @@ def main():
         g = synth.scale24_graph()
         wname = ("rmat-scale24 (n=2^24, m=2^28, a,b,c,d=.57,.19,.19,.05, Zipf(1.2) weights "
                  "in [1,1e4]), alpha=0.15, R=128, all sources, short walks S=32 L=3 K=64, "
-                 "large rows split, top-32")
+                 "large rows split (prefix trees above 8 edges: the workload's 4096-edge hub "
+                 "threshold gives identical results, 8 measured faster), top-32")
     else:
         cfg = dict(synth.MEDIUM)
         cfg["hub_threshold"] = 4096
@@ -461,6 +621,9 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
     G.check(stream)
+    if args.full_parity:
+        full_parity(args, g, G, out, cfg, st_cfg)
+        return
 
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -518,6 +681,7 @@ def main():
                      "ms_after_walk_kernel": round(coin_avg, 3), "walks": st_coin["walks"],
                      "moves": st_coin["moves"], "bound": "alu (one Philox4x32-10 block per move)"}
 
+    graph_steps = steps_total / args.steps - st_coin.get("steps", 0)
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "walk-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -527,20 +691,30 @@ def main():
                    "topk": k, "tree_rows": info["hubs"], "small_nodes": info["small"],
                    "rows_over_4096": int((g.degrees() > 4096).sum())},
         "sources_per_s": round(sources_per_s, 1),
+        "graph_steps_per_s": round(graph_steps / (ms_per_step / 1e3), 1),
+        "graph_steps_note": ("steps that read the graph (those of the walk kernel; the coin-only "
+                             "restart steps of the walks from nodes without out-edges excluded), "
+                             "over the whole step time"),
         "walk_stats_per_step": st_last,
         "aggregate_ms": round(float(np.mean(agg_ms)), 3),
         "walk_phase_ms": round(float(np.mean(walk_ms)), 3),
+        "rebuild_and_pool_ms": round(ms_per_step - float(np.mean(walk_ms)) - float(np.mean(agg_ms)), 3),
         "wall_s": round(wall, 3),
         "roofline": roofline,
         "coin_only": coin_only,
+        "paper_reference": PAPER_REFERENCE,
     }
+    if args.workload == "scale24" and not args.no_ablation:
+        result["ablation"] = ablation(args, fppr, torch, np, g, ro, col, w, cfg, st_cfg, stream, value,
+                                      ms_per_step)
 
     # ---- oracle: sampled parity + CPU baseline (rank 0, N = 1) ----
     og = pool = None
     if args.cpu_sample > 0:
         from oracle import oracle as O
 
-        nthreads = max(1, min(16, os.cpu_count() or 1))
+        ncpu = os.cpu_count() or 1
+        nthreads = max(1, min(16, ncpu))
         og = O.Graph.from_csr(g)
         pool = None
         t_pool = 0.0
@@ -558,12 +732,34 @@ def main():
         t_cpu = time.perf_counter() - tc
         cpu_steps = ref.stats["steps"] / t_cpu
         log(f"oracle sample {t_cpu:.1f}s ({cpu_steps:.3g} steps/s)")
+        one = None
+        if args.cpu_sample_1t > 0:
+            s1 = sample[:: max(1, len(sample) // args.cpu_sample_1t)][: args.cpu_sample_1t]
+            t1 = time.perf_counter()
+            r1 = O.run(og, alpha, R, seed, sources=s1, topk=k, pool=pool, nthreads=1, want_counts=False)
+            t1 = time.perf_counter() - t1
+            one = {"walk_steps_per_s": round(r1.stats["steps"] / t1, 1), "sources": int(len(s1)),
+                   "seconds": round(t1, 3)}
+            log(f"oracle one thread {t1:.1f}s ({r1.stats['steps'] / t1:.3g} steps/s)")
+        # the whole workload on the host at this rate, with the pool build
+        # (both are in the GPU's step)
+        whole_s = t_pool + t_cpu * g.n / len(sample)
         result["cpu_baseline"] = {
             "value": round(cpu_steps, 1), "unit": "walk-steps/s", "cores": nthreads, "kind": "oracle",
             "sample": (f"{len(sample)} uniform random sources x {R} walks of the same workload "
                        f"(walks + counting + top-k, {t_cpu:.2f}s); short-walk pool built "
                        f"beforehand in {t_pool:.1f}s, not in the rate"),
             "sources_per_s": round(len(sample) / t_cpu, 1),
+            "host": {"nproc": ncpu, "cpu_model": cpu_model(), "threads_used": nthreads},
+            "one_thread": one,
+            "pool_build_s": round(t_pool, 2),
+            "whole_step_estimate": {
+                "seconds": round(whole_s, 1),
+                "walk_steps_per_s": round(steps_total / args.steps / whole_s, 1),
+                "how": ("pool build + the sample's time scaled to all sources, i.e. the same work as "
+                        "one GPU step (rebuild aside)"),
+                "gpu_step_ms": round(ms_per_step, 3),
+            },
         }
         if not args.no_check:
             got_d = out.digest.cpu().numpy().view(np.uint64)[sample]

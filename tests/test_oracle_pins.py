@@ -213,11 +213,18 @@ def test_length_is_geometric():
 
 
 def test_move_cap():
-    """With the smallest threshold (T = 1) walks stop at the move cap."""
+    """With the smallest threshold (T = 1: a move stops only on x2 == 0,
+    probability 2^-32) both walks on a directed 3-cycle run to the cap of
+    65,536 moves and stop there, at the current tail: node 65536 mod 3 = 1
+    of the cycle 0 -> 1 -> 2 -> 0. A cap one move shorter or longer, or a
+    cap that is never applied, fails one of these."""
     g = graph_from_edges(3, [(0, 1), (1, 2), (2, 0)])
-    res = O.run(oracle_graph(g), 1e-12, 2, seed=1, sources=[0], topk=0, want_lengths=True)
-    assert res.stats["capped"] + res.stats["walks"] >= 2
-    assert res.lengths.max() <= O.MOVE_CAP
+    res = O.run(oracle_graph(g), 1e-12, 2, seed=1, sources=[0], topk=1, want_lengths=True)
+    assert O.MOVE_CAP == 65536
+    assert res.stats["capped"] == 2 and res.stats["walks"] == 2
+    assert np.array_equal(res.lengths.ravel(), [O.MOVE_CAP, O.MOVE_CAP])
+    assert res.stats["moves"] == res.stats["steps"] == 2 * O.MOVE_CAP
+    assert res.counts[0][0].tolist() == [O.MOVE_CAP % 3, 2]  # (node, count): both walks end at node 1
 
 
 # --------------------------------------------------------------------------
