@@ -33,25 +33,47 @@ def transition(n, row_offsets, col, w):
     return P, dangling
 
 
+def _spmm(M, X, threads=None):
+    """M @ X for a sparse M and a dense X of many columns, the columns split
+    over host threads (scipy's product releases the interpreter lock)."""
+    import concurrent.futures as cf
+    import os
+
+    ns = X.shape[1]
+    t = threads or min(16, os.cpu_count() or 1)
+    if ns < 16 or t < 2:
+        return M @ X
+    step = -(-ns // t)
+    parts = [np.ascontiguousarray(X[:, i:i + step]) for i in range(0, ns, step)]
+    with cf.ThreadPoolExecutor(len(parts)) as ex:
+        return np.hstack(list(ex.map(lambda c: M @ c, parts)))
+
+
 def _series(n, sources, Q, A, dangling, alpha, tol=1e-17, max_iter=100000):
     """pi = sum_k X_k A + alpha (X_k d) e_s, X_{k+1} = X_k Q + (1-alpha)(X_k d) e_s,
     X_0 = e_s. Q, A sparse (continue / absorb), d the dangling indicator."""
     src = np.asarray(sources, dtype=np.int64)
     ns = src.shape[0]
-    X = np.zeros((ns, n))
-    X[np.arange(ns), src] = 1.0
-    pi = np.zeros((ns, n))
+    cols = np.arange(ns)
+    # one column per source (nodes x sources); sum_k X_k A = (sum_k X_k) A,
+    # so the absorbing part is applied once, to the running sum
+    X = np.zeros((n, ns))
+    X[src, cols] = 1.0
+    Xsum = np.zeros((n, ns))
+    back_sum = np.zeros(ns)
     QT = Q.T.tocsr()
     AT = A.T.tocsr()
     for _ in range(max_iter):
-        back = X @ dangling  # mass at dangling nodes, returns to the source
-        pi += (AT @ X.T).T
-        pi[np.arange(ns), src] += alpha * back
-        Xn = (QT @ X.T).T
-        Xn[np.arange(ns), src] += (1.0 - alpha) * back
+        back = dangling @ X  # mass at dangling nodes, returns to the source
+        Xsum += X
+        back_sum += back
+        Xn = _spmm(QT, X)
+        Xn[src, cols] += (1.0 - alpha) * back
         X = Xn
         if X.sum() < tol:
             break
+    pi = np.ascontiguousarray(_spmm(AT, Xsum).T)
+    pi[cols, src] += alpha * back_sum
     return pi
 
 
@@ -64,23 +86,22 @@ def chain_exact(n, row_offsets, col, w, alpha, sources, small_nodes, pool_entrie
     """Pool-conditioned chain. small_nodes: ids in increasing order; pool_entries
     uint64[len(small_nodes)*K] encoded end | steps<<32 | mark<<48 (mark 1 = stop)."""
     P, d = transition(n, row_offsets, col, w)
-    P = P.tolil()
-    Q = ((1.0 - alpha) * P).tolil()
-    A = (alpha * P).tolil()
-    ent = np.asarray(pool_entries, dtype=np.uint64).reshape(len(small_nodes), K)
-    for r, v in enumerate(small_nodes):
-        Q.rows[v] = []
-        Q.data[v] = []
-        A.rows[v] = []
-        A.data[v] = []
-        ends = (ent[r] & np.uint64(0xFFFFFFFF)).astype(np.int64)
-        term = ((ent[r] >> np.uint64(48)) & np.uint64(1)).astype(bool)
-        for e, t in zip(ends, term):
-            if t:
-                A[v, e] = A[v, e] + 1.0 / K
-            else:
-                Q[v, e] = Q[v, e] + 1.0 / K
-    return _series(n, sources, Q.tocsr(), A.tocsr(), d, alpha)
+    small = np.asarray(small_nodes, dtype=np.int64)
+    keep = np.ones(n, dtype=bool)
+    keep[small] = False
+    Pc = P.tocoo()
+    m = keep[Pc.row]  # rows of nodes that are not small keep their edges
+    ent = np.asarray(pool_entries, dtype=np.uint64).reshape(small.shape[0], K)
+    ends = (ent & np.uint64(0xFFFFFFFF)).astype(np.int64).ravel()
+    term = ((ent >> np.uint64(48)) & np.uint64(1)).astype(bool).ravel()
+    rows = np.repeat(small, K)  # a small node jumps to each of its K entries with weight 1/K
+    Q = sp.coo_matrix((np.concatenate([(1.0 - alpha) * Pc.data[m], np.full(int((~term).sum()), 1.0 / K)]),
+                       (np.concatenate([Pc.row[m], rows[~term]]), np.concatenate([Pc.col[m], ends[~term]]))),
+                      shape=(n, n)).tocsr()  # duplicates add
+    A = sp.coo_matrix((np.concatenate([alpha * Pc.data[m], np.full(int(term.sum()), 1.0 / K)]),
+                       (np.concatenate([Pc.row[m], rows[term]]), np.concatenate([Pc.col[m], ends[term]]))),
+                      shape=(n, n)).tocsr()
+    return _series(n, sources, Q, A, d, alpha)
 
 
 def ppr_networkx(n, row_offsets, col, w, alpha, s):

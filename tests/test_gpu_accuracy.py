@@ -90,3 +90,66 @@ def test_topk_accuracy_against_exact_ppr(fp):
                 f"   vs exact: NDCG@{K}={nd_e:.4f} MAP@{K}={mp_e:.4f}")
         assert vs_chain[0] < vs_chain[1] < vs_chain[2] and vs_chain[2] > 0.95
     assert last_exact[64] > last_exact[16], "a larger pool must bring stitched walks closer to exact PPR"
+
+
+def test_topk_accuracy_at_depth(fp):
+    """The paper's accuracy axis at its depth (Sec. 5.2: NDCG and MAP of the
+    top-1000) and defaults (epsilon = delta = alpha = 0.5, p_f = 1/n), on
+    R-MAT scale 17 (131,072 nodes, 2.1M edges, the scale-24 workload's
+    skew and weight law): 64 sampled sources with out-edges, exact PPR in
+    FP64, GPU top-k lists at R_g, 4 R_g and 16 R_g walks (R_g from
+    Definition 1's guarantee), plain walks against exact PPR and stitched
+    walks (S = 32, L = 3, K = 64) against their pool's chain and against
+    exact PPR, at k = 16, 64 and 1000."""
+    import torch
+
+    from exact_ppr import chain_exact
+
+    alpha = 0.5
+    g = synth.rmat(17, 16, 0.57, 0.19, 0.19, wmax=10000, seed=1017, weight_law="zipf", zipf_s=1.2)
+    rng = np.random.default_rng(5)
+    src = np.sort(rng.choice(np.flatnonzero(g.degrees() > 0), 64, replace=False)).astype(np.uint32)
+    R_g = fp.fppr_walks_for_guarantee(0.5, 0.5, 1.0 / g.n)
+    say(f"case: accuracy at depth, n={g.n}, m={g.m}, alpha={alpha}, guaranteed R={R_g}, 64 sources")
+    pi = ppr_exact(g.n, g.row_offsets, g.col, g.w, alpha, src)
+    say("  exact PPR done")
+    G = fp.Graph(g)
+    G.build_pool(S=32, L=3, K=64, alpha=alpha, seed=7)
+    small = np.flatnonzero((g.degrees() >= 1) & (g.degrees() <= 32))
+    chain = chain_exact(g.n, g.row_offsets, g.col, g.w, alpha, src, small, G.export_pool(), 64)
+    say("  pool chain done")
+
+    def scores(ref, topk, k):
+        nd, ap = [], []
+        for r in range(ref.shape[0]):
+            est = topk[r, :, 0]
+            est = est[est < g.n]
+            nd.append(ndcg_at_k(ref[r], est, k))
+            ap.append(ap_at_k(ref[r], est, k))
+        return float(np.mean(nd)), float(np.mean(ap))
+
+    table = {}
+    for stitch in (False, True):
+        for R in (R_g, 4 * R_g, 16 * R_g):
+            kk = min(1000, R)
+            out = fp.run(G, alpha, R, 41, sources=src, topk=kk, stitch=stitch, counts=False, stats=False)
+            torch.cuda.synchronize()
+            tk = out.topk.cpu().numpy().view(np.uint32).reshape(src.size, kk, 2)
+            for k in (16, 64, 1000):
+                table[(stitch, R, k, "exact")] = scores(pi, tk, k)
+                if stitch:
+                    table[(stitch, R, k, "chain")] = scores(chain, tk, k)
+            line = "  ".join(f"@{k} NDCG {table[(stitch, R, k, 'exact')][0]:.4f} MAP {table[(stitch, R, k, 'exact')][1]:.4f}"
+                             for k in (16, 64, 1000))
+            say(f"  {'stitched' if stitch else 'plain   '} R={R:5d} vs exact: {line}")
+            if stitch:
+                line = "  ".join(f"@{k} NDCG {table[(stitch, R, k, 'chain')][0]:.4f} MAP {table[(stitch, R, k, 'chain')][1]:.4f}"
+                                 for k in (16, 64, 1000))
+                say(f"           R={R:5d} vs chain: {line}")
+    for k in (16, 64, 1000):
+        nd = [table[(False, R, k, "exact")][0] for R in (R_g, 4 * R_g, 16 * R_g)]
+        assert nd[0] < nd[1] < nd[2], (k, nd)
+        ndc = [table[(True, R, k, "chain")][0] for R in (R_g, 4 * R_g, 16 * R_g)]
+        assert ndc[0] < ndc[1] < ndc[2], (k, ndc)
+    assert table[(False, 16 * R_g, 16, "exact")][0] > 0.95
+    assert table[(True, 16 * R_g, 16, "chain")][0] > 0.95
