@@ -113,6 +113,26 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t x) {
 
 __device__ __forceinline__ uint32_t sread(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Loads through global-address-space pointers: addresses handed around as
+// integers (through LDS) would otherwise become flat loads, which also count
+// against the LDS counter.
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+typedef const U32x4 __attribute__((address_space(1)))* GlobalV4;
+typedef const uint64_t __attribute__((address_space(1)))* GlobalU64;
+typedef const uint32_t __attribute__((address_space(1)))* GlobalU32;
+// 16 bytes at addr + 16 k
+__device__ __forceinline__ uint4 gload16(uint64_t addr, uint32_t k) {
+  const U32x4 v = ((GlobalV4)addr)[k];
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// word j (0..3) of v, without branches
+__device__ __forceinline__ uint32_t word_of(uint4 v, uint32_t j) {
+  const uint32_t a = (j & 1u) ? v.y : v.x;
+  const uint32_t b = (j & 1u) ? v.w : v.z;
+  return (j & 2u) ? b : a;
+}
+
 // keys of q that are <= X: two u64 keys (wide layout) or four u32 keys
 // (narrow layout, where X < 2^32); `nar` is wave-uniform
 __device__ __forceinline__ uint32_t count_q(uint4 q, uint64_t X, bool nar) {
@@ -270,10 +290,11 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
     const bool rec_line = (ph == kSrcRec || ph == kRec);
     uint64_t v0 = 0, v1 = 0;
     if (ph == kBsearch) {
-      const Block& lb = blocks[L.off + L.lo + ((L.hi - L.lo) >> 1)];
-      v0 = nar ? lb.w32[kNarrowLeafEdges - 1] : lb.lf.p[kLeafEdges - 1];
+      const uint64_t lb = reinterpret_cast<uint64_t>(blocks + L.off + L.lo + ((L.hi - L.lo) >> 1));
+      v0 = nar ? static_cast<uint64_t>(((GlobalU32)lb)[kNarrowLeafEdges - 1])
+               : ((GlobalU64)lb)[kLeafEdges - 1];
     } else if (ph == kPool) {
-      v0 = *reinterpret_cast<const uint64_t*>(L.X);
+      v0 = *(GlobalU64)L.X;
     }
     const bool want_line = rec_line || ph == kTree || ph == kLeaf;
     const uint64_t line_mask = __ballot(want_line);
@@ -299,9 +320,9 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) q[r][k] = make_uint4(0, 0, 0, 0);
         if ((line_mask >> owner) & 1ull) {
-          const uint4* src = reinterpret_cast<const uint4*>(sh_line[wv][owner]) + half * 4;
+          const uint64_t src = sh_line[wv][owner] + half * 64;
 #pragma unroll
-          for (uint32_t k = 0; k < 4; ++k) q[r][k] = src[k];
+          for (uint32_t k = 0; k < 4; ++k) q[r][k] = gload16(src, k);
         }
       }
 #pragma unroll
@@ -335,18 +356,13 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
         if (leaf) {  // destination j = cnt: word j of the odd lane's 8 (16) ids
           if (half == 1) {  // selects of values (an indexed pick would put q in scratch)
             const uint32_t jw = cnt & 3u, qi = cnt >> 2;
+            const uint32_t w0 = word_of(q[r][0], jw), w1 = word_of(q[r][1], jw);
             if (!nar) {
-              const uint4 w = qi == 0 ? q[r][0] : q[r][1];
-              sh_res[wv][owner] = jw == 0 ? w.x : (jw == 1 ? w.y : (jw == 2 ? w.z : w.w));
+              sh_res[wv][owner] = (qi & 1u) ? w1 : w0;
             } else {
-              uint32_t wq[4];
-#pragma unroll
-              for (uint32_t t = 0; t < 4; ++t) {
-                const uint4 v = q[r][t];
-                wq[t] = jw == 0 ? v.x : (jw == 1 ? v.y : (jw == 2 ? v.z : v.w));
-              }
-              const uint32_t lo2 = (qi & 1u) ? wq[1] : wq[0];
-              const uint32_t hi2 = (qi & 1u) ? wq[3] : wq[2];
+              const uint32_t w2 = word_of(q[r][2], jw), w3 = word_of(q[r][3], jw);
+              const uint32_t lo2 = (qi & 1u) ? w1 : w0;
+              const uint32_t hi2 = (qi & 1u) ? w3 : w2;
               sh_res[wv][owner] = (qi & 2u) ? hi2 : lo2;
             }
           }
