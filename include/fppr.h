@@ -366,6 +366,22 @@ typedef struct {
   fppr_profile* profile;
 } fppr_out;
 
+/* Counting and top-k alone (Algorithm 2's last phase: group the walks by
+ * (head, tail) and count them; Sec. 1: keep the endpoints some walk
+ * reached) over endpoints the caller already has, e.g. those of
+ * fppr_run_alias or fppr_run_big_moves: source row j (source id
+ * sources[j], or j when sources is NULL, which the digest uses) owns the R
+ * walks endpoints[j * R .. j * R + R) (device u32; FPPR_NO_NODE entries are
+ * not counted). p gives R, topk and the output flags FPPR_COUNTS /
+ * FPPR_DIGESTS (alpha, seed, FPPR_STITCH and FPPR_STATS are not used);
+ * outputs as for fppr_run. workspace: device, at least fppr_aggregate_plan
+ * bytes (the hash tables of R > 256 without counts). Identical to the
+ * counting of fppr_run over the same endpoints. Asynchronous on `stream`. */
+FPPR_API fppr_status fppr_aggregate_plan(const fppr_params* p, uint64_t n_sources, uint64_t* workspace_bytes);
+FPPR_API fppr_status fppr_aggregate(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
+                                    uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
+                                    const fppr_out* out, void* stream);
+
 /* Workspace size (bytes, 256-byte aligned device memory) for a run of
  * n_sources sources. Pure host computation. */
 FPPR_API fppr_status fppr_plan(const fppr_graph* g, const fppr_params* p, uint64_t n_sources,

@@ -698,6 +698,45 @@ FPPR_API fppr_status fppr_run_static(fppr_graph* g, const fppr_params* p, const 
   return fppr_run(g, p, sources, n_sources, ws, FPPR_STATIC_SCRATCH_BYTES, out, stream);
 }
 
+namespace {
+// the parameters counting uses (no graph): R, k and the output flags
+fppr_status check_count_params(const fppr_params* p) {
+  if (!p) return invalid("params is NULL");
+  if (p->R < 1 || p->R > kMaxR) return invalid("R must be in [1, 2^20]");
+  if ((p->flags & FPPR_COUNTS) && p->R > kAggMaxR) return invalid("FPPR_COUNTS needs R <= 4096");
+  if (p->topk > p->R || p->topk > 1024) return invalid("topk must be <= R and <= 1024");
+  if (p->flags & ~(FPPR_STITCH | FPPR_COUNTS | FPPR_DIGESTS | FPPR_STATS)) return invalid("unknown flag bits");
+  return FPPR_OK;
+}
+}  // namespace
+
+FPPR_API fppr_status fppr_aggregate_plan(const fppr_params* p, uint64_t n_sources, uint64_t* workspace_bytes) {
+  fppr_status st = check_count_params(p);
+  if (st != FPPR_OK) return st;
+  if (!workspace_bytes) return invalid("workspace_bytes is NULL");
+  *workspace_bytes = std::max<uint64_t>(kAlign, agg_table_bytes(n_sources, p->R, (p->flags & FPPR_COUNTS) != 0));
+  return FPPR_OK;
+}
+
+FPPR_API fppr_status fppr_aggregate(const fppr_params* p, const uint32_t* endpoints, const uint32_t* sources,
+                                    uint64_t n_sources, void* workspace, uint64_t workspace_bytes,
+                                    const fppr_out* out, void* stream) {
+  fppr_status st = check_count_params(p);
+  if (st != FPPR_OK) return st;
+  if ((st = check_outputs(p, out)) != FPPR_OK) return st;
+  if (n_sources == 0) return FPPR_OK;
+  if (!endpoints) return invalid("endpoints is NULL");
+  if (n_sources > (1ull << 40) / p->R) return invalid("n_sources * R too large");
+  uint64_t need = 0;
+  fppr_aggregate_plan(p, n_sources, &need);
+  if (!workspace || workspace_bytes < need) return invalid("workspace missing or smaller than fppr_aggregate_plan");
+  AggLaunch a = make_agg(p, endpoints, sources, n_sources, out);
+  a.table = static_cast<uint64_t*>(workspace);
+  if (!(a.topk || a.counts || a.digest)) return FPPR_OK;
+  const hipError_t e = launch_aggregate(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FPPR_OK : hip_fail(e, "aggregate kernel");
+}
+
 FPPR_API fppr_status fppr_profile_create(fppr_profile** out) {
   if (!out) return invalid("out is NULL");
   auto* p = new fppr_profile();

@@ -171,6 +171,10 @@ _SIGS = [
     ("fppr_run", ctypes.c_int, [P, ctypes.POINTER(fppr_params), P, ctypes.c_uint64, P, ctypes.c_uint64,
                                 ctypes.POINTER(fppr_out), P]),
     ("fppr_run_check", ctypes.c_int, [P, P]),
+    ("fppr_aggregate_plan", ctypes.c_int, [ctypes.POINTER(fppr_params), ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+    ("fppr_aggregate", ctypes.c_int, [ctypes.POINTER(fppr_params), P, P, ctypes.c_uint64, P, ctypes.c_uint64,
+                                      ctypes.POINTER(fppr_out), P]),
     ("fppr_run_static", ctypes.c_int, [P, ctypes.POINTER(fppr_params), P, ctypes.c_uint64,
                                        ctypes.POINTER(fppr_out), P]),
     ("fppr_profile_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
@@ -542,6 +546,30 @@ def fppr_run_static(graph: Graph, params: fppr_params, sources, n_sources: int, 
                  out.profile.handle if out.profile is not None else None)
     _check(lib().fppr_run_static(graph.handle, ctypes.byref(params), _dptr(sources), n_sources,
                                  ctypes.byref(o), _stream_ptr(stream)))
+
+
+def count(endpoints, R, topk, sources=None, n_sources=None, counts=True, digests=True, stream=None) -> Outputs:
+    """fppr_aggregate over device endpoints (int32 tensor, n_sources * R):
+    counting, top-k and digests as fppr_run computes them. sources: None
+    (row j is node j) or a device int32 tensor / int sequence of source ids."""
+    import torch
+
+    src = None
+    if sources is not None:
+        src = sources if isinstance(sources, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(sources, dtype=np.uint32).view(np.int32)).cuda()
+        n_sources = int(src.numel())
+    n_sources = int(n_sources if n_sources is not None else endpoints.numel() // R)
+    p = make_params(0.5, R, 0, topk, False, counts, digests, False)
+    ws_bytes = ctypes.c_uint64()
+    _check(lib().fppr_aggregate_plan(ctypes.byref(p), n_sources, ctypes.byref(ws_bytes)))
+    ws = torch.empty((ws_bytes.value + 7) // 8, dtype=torch.int64, device="cuda")
+    out = alloc_outputs(n_sources, R, topk, counts, digests, stats=False)
+    o = fppr_out(_dptr(out.topk), _dptr(out.counts), _dptr(out.n_distinct), _dptr(out.digest), None, None, None)
+    _check(lib().fppr_aggregate(ctypes.byref(p), _dptr(endpoints), _dptr(src), n_sources, _dptr(ws),
+                                ws.numel() * 8, ctypes.byref(o), _stream_ptr(stream)))
+    out._workspace = ws
+    return out
 
 
 class Profile:

@@ -217,7 +217,7 @@ def test_alias_walks_scale24_ab(fp):
     """R-MAT scale 24 (the benchmark graph), R = 16 from every node, no
     stitching: alias walks against the prefix-tree path on the same walks
     (equal step counts, since coins do not depend on the picks), both timed;
-    16 sampled walks recomputed by the oracle."""
+    288 sampled walks (hub sources included) recomputed by the oracle."""
     import torch
 
     g = synth.scale24_graph()
@@ -252,8 +252,98 @@ def test_alias_walks_scale24_ab(fp):
     say(f"  prefix-tree path: {cdf_steps} steps, walk phase {walk_ms:.2f} ms (walk kernel {kern_ms:.2f} ms): "
         f"{cdf_steps / walk_ms * 1e3:.3e} walk-steps/s")
     assert cdf_steps == steps
-    src = np.array([5, 77777, 4_000_000, 16_000_000], dtype=np.uint32)
-    e = ep.cpu().numpy().view(np.uint32).reshape(g.n, 16)[src, :4]
-    s_ = st.cpu().numpy().view(np.uint32).reshape(g.n, 16)[src, :4]
-    ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.15), 3, 4, src)
+    # 288 walks recomputed by the oracle: 6 walks from each of the 8 largest
+    # rows (hubs of up to 370,930 edges) and of 40 random nodes with out-edges
+    deg = g.degrees()
+    rng = np.random.default_rng(24)
+    src = np.unique(np.concatenate([np.argsort(deg)[-8:],
+                                    rng.choice(np.flatnonzero(deg > 0), 40, replace=False)])).astype(np.uint32)
+    e = ep.cpu().numpy().view(np.uint32).reshape(g.n, 16)[src, :6]
+    s_ = st.cpu().numpy().view(np.uint32).reshape(g.n, 16)[src, :6]
+    ref_ep, ref_st = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.15), 3, 6, src)
     assert np.array_equal(e, ref_ep) and np.array_equal(s_, ref_st)
+
+
+def count_reference(ep, sources, k):
+    """Algorithm 2's last phase written out: per source the (t, count) pairs
+    of its walks' endpoints, the top-k by count descending then t ascending
+    (padded with (FPPR_NO_NODE, 0)), and the digest as the oracle defines it."""
+    from oracle import oracle as O
+
+    topk = np.zeros((len(sources), k, 2), dtype=np.uint32)
+    topk[:, :, 0] = 0xFFFFFFFF
+    digest = np.zeros(len(sources), dtype=np.uint64)
+    for r, s in enumerate(sources):
+        t, c = np.unique(ep[r][ep[r] != 0xFFFFFFFF], return_counts=True)
+        order = np.lexsort((t, -c))[:k]
+        topk[r, :order.size, 0] = t[order]
+        topk[r, :order.size, 1] = c[order]
+        d = 0
+        for tt, cc in zip(t, c):
+            d = (d + O.digest_term(int(s), int(tt), int(cc))) % 2**64
+        digest[r] = d
+    return topk, digest
+
+
+def test_aggregate_equals_run_counting(fp):
+    """fppr_aggregate over fppr_run's own endpoints gives fppr_run's counts,
+    top-k and digests (sort path with counts, and the hash path of R > 256)."""
+    import torch
+
+    g = CASES["chung-lu hubs"]()
+    say("case: fppr_aggregate over fppr_run's endpoints")
+    G = fp.Graph(g)
+    src = np.arange(0, g.n, 11, dtype=np.uint32)
+    for R, k, counts in ((100, 16, True), (5000, 32, False)):
+        o = fp.run(G, 0.15, R, 77, sources=src, topk=k, counts=counts, endpoints=True)
+        a = fp.count(o.endpoints.reshape(-1), R, k, sources=src, counts=counts)
+        torch.cuda.synchronize()
+        assert torch.equal(a.topk, o.topk) and torch.equal(a.digest, o.digest)
+        if counts:
+            assert torch.equal(a.counts, o.counts) and torch.equal(a.n_distinct, o.n_distinct)
+
+
+def test_alias_walks_counted(fp):
+    """Alias walks (the paper's picks) through counting and top-k: the top-k
+    lists and digests of the oracle walker's endpoints."""
+    import torch
+
+    g = CASES["r-mat scale 12"]()
+    say("case: alias walks counted")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
+    P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
+    nd = G.alias_nodes()
+    src = np.arange(0, g.n, 29, dtype=np.uint32)
+    ep, _ = fp.run_alias(G, nd, sl, 0.15, 64, 5, sources=src, steps=False)
+    o = fp.count(ep, 64, 16, sources=src, counts=False)
+    torch.cuda.synchronize()
+    ref_ep, _ = A.run(g.row_offsets, g.col, g.w, fp.fppr_alpha_threshold(0.15), 5, 64, src)
+    tk, dg = count_reference(ref_ep, src, 16)
+    assert np.array_equal(o.topk.cpu().numpy().view(np.uint32), tk)
+    assert np.array_equal(o.digest.cpu().numpy().view(np.uint64), dg)
+
+
+def test_alias_slots_of_long_rows_scale20(fp):
+    """Packed slots (threshold, own destination, alias's destination) of the
+    64 largest rows of R-MAT scale 20 (up to 69,306 edges: lanes loop over
+    the row) and 4,000 sampled rows, against the oracle's tables."""
+    import torch
+
+    g = synth.medium_graph()
+    deg = g.degrees()
+    say("case: alias slots of long rows, R-MAT scale 20")
+    G = fp.Graph(g)
+    Pt, alt = G.alias_tables()
+    sl = G.alias_slots(Pt, alt)
+    torch.cuda.synchronize()
+    sl = sl.cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(19)
+    rows = np.concatenate([np.argsort(deg)[-64:], rng.choice(np.flatnonzero(deg > 0), 4000, replace=False)])
+    for v in rows:
+        a, b = int(g.row_offsets[v]), int(g.row_offsets[v + 1])
+        Po, alo, _ = A.alias_table(g.w[a:b])
+        want = g.col[a:b].astype(np.uint64) | (g.col[a + np.asarray(alo, dtype=np.int64)].astype(np.uint64)
+                                                << np.uint64(32))
+        assert np.array_equal(sl[a:b, 0], np.asarray(Po, dtype=np.uint64)), v
+        assert np.array_equal(sl[a:b, 1], want), v

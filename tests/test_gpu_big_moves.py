@@ -171,3 +171,28 @@ def test_paper_design_walks_scale20(fp):
     ref_ep, ref_st = BM.run_with_alias(g.row_offsets, g.col, g.w, S, d, cap,
                                        fp.fppr_alpha_threshold(alpha), 3, 16, sample)
     assert np.array_equal(e, ref_ep) and np.array_equal(s_, ref_st)
+
+
+def test_paper_design_walks_counted(fp):
+    """Walks of the paper's design (alias picks, one exact big move at each
+    small node) through counting and top-k (fppr_aggregate): the top-k lists
+    and digests of the oracle walker's endpoints."""
+    import torch
+
+    from test_gpu_alias import count_reference
+
+    name, make, S, d, cap, alpha = CASES[0]
+    g = make()
+    say(f"case: big-move walks counted, {name}")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_NARROW)
+    P, al = G.alias_tables()
+    sl = G.alias_slots(P, al)
+    bm = G.big_moves(S, d, cap, alpha)
+    src = np.arange(0, g.n, 7, dtype=np.uint32)
+    ep, _ = fp.run_big_moves(G, sl, bm, S, alpha, 48, 31, sources=src, steps=False)
+    o = fp.count(ep, 48, 12, sources=src, counts=False)
+    torch.cuda.synchronize()
+    ref_ep, _ = BM.run_with_alias(g.row_offsets, g.col, g.w, S, d, cap, fp.fppr_alpha_threshold(alpha), 31, 48, src)
+    tk, dg = count_reference(ref_ep, src, 12)
+    assert np.array_equal(o.topk.cpu().numpy().view(np.uint32), tk)
+    assert np.array_equal(o.digest.cpu().numpy().view(np.uint64), dg)
