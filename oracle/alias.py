@@ -4,14 +4,15 @@ Algorithm 3, Examples 3-4, Lemma 1): CPU oracle, test infrastructure only.
 Only the test suite may import this module; it shares nothing with the GPU
 library.
 
-Integer form. For a set S of n items with integer weights w (all >= 1) and
-total W, Algorithm 1's switch probability p(e) = n r(e) is kept as the
-integer P(e) = n w(e) in units of 1/W, so "1" is W and every update
-P(y) <- P(y) - (W - P(x)) is exact: the loop ends with every P in [0, W]
-and no item stranded by rounding. "Select any x in S^s and y in S^l" takes
-the first of each in insertion order (both are FIFO queues, seeded in item
-order; an item that drops below W joins the back of S^s); Example 2's
-printed result follows from that choice.
+Integer form. For n items with integer weights w (all >= 1) and total W,
+Algorithm 1's switch probability p(e) = n r(e) is kept as the integer
+P(e) = n w(e) in units of 1/W, so "1" is W and every transfer is exact: the
+table ends with every P in [0, W] and no item stranded by rounding. Slot i
+holds W units: P[i] for item i itself and W - P[i] for alias[i]. Algorithm
+1 leaves the order of its transfers free; here the items below W are
+filled oldest first by the earliest item still above W (item order), and
+an item that falls below W while giving joins the end of the fill order.
+Example 2's printed result follows from that order.
 
 A pick maps one 64-bit uniform D to X = floor(D n W / 2^64) in [0, n W):
 slot i = X div W (uniform over the n items) and U = X mod W (uniform over
@@ -30,29 +31,37 @@ pick descends from the root with one 64-bit draw per level.
 """
 from __future__ import annotations
 
-from collections import deque
-
 
 def alias_table(w):
-    """Algorithm 1 on integer weights: returns (P, alias, W) with P[i] in
-    [0, W] the switch threshold of item i in units of 1/W."""
+    """Integer alias table (Sec. 2.2, Algorithm 1): returns (P, alias, W)
+    with P[i] in [0, W] the units of slot i kept by item i, in units of
+    1/W; the rest of the slot goes to alias[i]. One sweep over the donors
+    (items above W, in item order): each fills the oldest unfilled slots
+    until it is down to W or below; a donor that ends below W becomes a
+    slot to fill itself, after all those already waiting."""
     w = [int(x) for x in w]
     if not w or min(w) < 1:
         raise ValueError("alias table needs at least one item, all weights >= 1")
     n, W = len(w), sum(w)
     P = [n * x for x in w]
     alias = list(range(n))
-    small = deque(i for i in range(n) if P[i] < W)
-    large = deque(i for i in range(n) if P[i] > W)
-    while large:
-        x = small.popleft()
-        y = large[0]
-        alias[x] = y
-        P[y] -= W - P[x]
-        if P[y] <= W:
-            large.popleft()
-            if P[y] < W:
-                small.append(y)
+    to_fill = [i for i in range(n) if P[i] < W]  # grows at the end while donors give
+    donors = [i for i in range(n) if P[i] > W]
+    nxt = 0
+    for y in donors:
+        while P[y] > W:  # deficits and surpluses balance exactly, so a slot is always waiting
+            x = to_fill[nxt]
+            nxt += 1
+            alias[x] = y
+            P[y] -= W - P[x]
+        if P[y] < W:
+            to_fill.append(y)
+    # every item owns exactly n w(e) units over all slots
+    own = list(P)
+    for i in range(n):
+        if alias[i] != i:
+            own[alias[i]] += W - P[i]
+    assert own == [n * x for x in w] and all(0 <= p <= W for p in P)
     return P, alias, W
 
 

@@ -3,12 +3,13 @@
 //
 // For a row of n edges with integer weights w and total W the switch
 // probability p(e) = n r(e) is kept as the integer P(e) = n w(e) in units of
-// 1/W, so every update of Algorithm 1 is exact and no edge is left over by
-// rounding. "Select any x in S^s and y in S^l" takes the first of each in
-// insertion order: both sets are FIFO queues seeded in edge order, and an
-// edge whose P drops below W joins the back of S^s (Example 2's printed
-// tables follow from this choice). A pick keeps slot i iff U < P(i), else
-// takes alias(i).
+// 1/W, so every transfer of Algorithm 1 is exact and no edge is left over
+// by rounding. Algorithm 1 leaves the order of its transfers free; here the
+// edges below W are filled oldest first by the earliest edge still above W
+// (both kept as FIFO queues in edge order), and an edge that falls below W
+// while giving joins the back of the fill queue (Example 2's printed tables
+// follow from this order). A pick keeps slot i iff U < P(i), else takes
+// alias(i).
 //
 // One thread per row: the loop is a dependent chain (each step may move the
 // head of S^l), so a row cannot be split across lanes without changing the
