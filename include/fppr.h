@@ -85,13 +85,24 @@ typedef struct {
                                   fppr_graph_destroy */
 } fppr_csr;
 
-/* Graph layouts (fppr_graph_opts.layout). Both give identical results; the
- * narrow layout reads fewer lines per weighted pick (it was faster or equal
- * on every workload measured). */
+/* Graph layouts (fppr_graph_opts.layout). All give identical results (the
+ * same edge for every draw). The narrow layout reads fewer lines per
+ * weighted pick than the wide one. The guide layout reads one 64-byte entry
+ * for almost every pick, whatever the degree: each row gets a table indexed
+ * by the top bits of the pick's 64-bit draw D, whose entries hold the
+ * thresholds ceil(P[j] 2^64 / W) that separate the edges meeting it (the
+ * first edge with P[j] > floor(D W / 2^64) is the first with D < that
+ * threshold), with child tables over the next bits of D where more than
+ * three edges meet one entry; every entry carries the record of the nodes it
+ * leads to, so a walk never reads a node's own line. It takes about 64 bytes
+ * x (0.7 to 2) per edge plus 8 bytes per edge of thresholds, and 16-byte
+ * pool entries; it needs n <= 2^30. The alias and big-move calls need the
+ * narrow layout. */
 #define FPPR_LAYOUT_AUTO 0u   /* narrow when it fits (max out-degree x max weight
                                  < 2^32), else wide */
 #define FPPR_LAYOUT_WIDE 1u   /* always wide */
 #define FPPR_LAYOUT_NARROW 2u /* narrow; INVALID_ARGUMENT when it does not fit */
+#define FPPR_LAYOUT_GUIDE 3u  /* guide tables; INVALID_ARGUMENT when n > 2^30 */
 
 typedef struct {
   /* Rows with more than hub_threshold out-edges (the large nodes of Sec. 4.1)
@@ -108,9 +119,12 @@ typedef struct {
    * measured); values below 8 act as 8; UINT32_MAX disables trees (rows of
    * more than E edges are then binary-searched over their blocks). */
   uint32_t hub_threshold;
-  /* FPPR_LAYOUT_AUTO, _WIDE or _NARROW. A narrow graph keeps its layout:
-   * a rebuild whose weights push a row total past 2^32 - 1 fails its check
-   * (fppr_graph_check) and the graph must be created again. */
+  /* FPPR_LAYOUT_AUTO, _WIDE, _NARROW or _GUIDE. A narrow graph keeps its
+   * layout: a rebuild whose weights push a row total past 2^32 - 1 fails its
+   * check (fppr_graph_check) and the graph must be created again. A guide
+   * graph is created with room for its child tables plus slack; a rebuild
+   * whose new weights need more fails its check the same way. Prefix trees
+   * (hub_threshold) do not apply to the guide layout. */
   uint32_t layout;
 } fppr_graph_opts;
 
@@ -146,8 +160,8 @@ FPPR_API fppr_status fppr_graph_check(fppr_graph* g, void* stream);
  * (0 without a pool), device_bytes = bytes the library allocated. */
 FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t* m,
                                      uint32_t* n_hubs, uint64_t* n_small, uint64_t* device_bytes);
-/* The layout chosen at creation (host output): FPPR_LAYOUT_WIDE or
- * FPPR_LAYOUT_NARROW. */
+/* The layout chosen at creation (host output): FPPR_LAYOUT_WIDE,
+ * FPPR_LAYOUT_NARROW or FPPR_LAYOUT_GUIDE. */
 FPPR_API fppr_status fppr_graph_layout(const fppr_graph* g, uint32_t* layout);
 
 typedef struct {

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfppr.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["build.hip", "pool.hip", "walk.hip", "aggregate.hip", "alias.hip", "big_moves.hip", "fppr.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
+SOURCES = ["build.hip", "pool.hip", "walk.hip", "guide.hip", "walk_guide.hip", "aggregate.hip", "alias.hip", "big_moves.hip", "fppr.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
 ARCH = os.environ.get("FPPR_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fvisibility=hidden",

@@ -331,6 +331,7 @@ FPPR_API fppr_status fppr_batch_check(fppr_batch* b, void* stream) {
   unsigned long long ctl[2];
   e = hipMemcpy(ctl, b->ctl, sizeof ctl, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "read batch status");
+  if (ctl[1] & 2) return invalid("a walk met guide tables that did not resolve its pick (rebuild the graph)");
   if (ctl[1]) return invalid("a source id was >= n (its walks were skipped)");
   if (b->opts.flags & FPPR_BATCH_REBUILD) {
     for (size_t k = 0; k < b->graphs.size(); ++k) {

@@ -65,6 +65,12 @@ void free_graph(fppr_graph* g) {
   dfree(g->cls);
   dfree(g->live);
   dfree(g->dang);
+  dfree(g->ghead);
+  dfree(g->gent);
+  dfree(g->gT);
+  dfree(g->gtab[0]);
+  dfree(g->gtab[1]);
+  dfree(g->gctl);
   if (g->side) (void)hipStreamDestroy(g->side);
   if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
   if (g->join_ev) (void)hipEventDestroy(g->join_ev);
@@ -80,6 +86,7 @@ std::string err_bits(uint32_t e) {
   if (e & kErrDegree) s += " a row has 2^27 or more edges;";
   if (e & kErrCapacity) s += " pool table overflow (graph changed shape);";
   if (e & kErrNarrow) s += " a row's total weight exceeds 2^32 - 1 in a graph created with 32-bit prefixes (recreate it);";
+  if (e & kErrGuide) s += " the guide tables need more room than the graph was created with (recreate it);";
   return s;
 }
 
@@ -125,8 +132,80 @@ hipError_t zero_ctl(fppr_graph* g, hipStream_t s) {
 // are unchanged, and the kernels refuse to write past it otherwise)
 hipError_t derive(fppr_graph* g, hipStream_t s) {
   hipError_t e;
+  if (g->guide) {
+    // levels beyond the first build's depth + 2 are refused (and reported)
+    const uint32_t levels = std::min<uint32_t>(g->g_levels + 2, kGuideLevels);
+    if ((e = launch_guide_build(g, false, levels, s)) != hipSuccess) return e;
+    for (uint32_t l = 2; l <= levels; ++l)
+      if ((e = launch_guide_level(g, l, levels, s)) != hipSuccess) return e;
+    return hipSuccess;
+  }
   if ((e = launch_region_sizes(g, s)) != hipSuccess) return e;
   return launch_leaves(g, s, false);  // the tree-row count is unchanged
+}
+
+// Guide tables at creation: sizes and bases, then the build level by level,
+// reading back each level's table count; when entries or table lists run out
+// the build starts again with room for what the counters asked for.
+fppr_status create_guide(fppr_graph* g, hipStream_t s);
+
+fppr_status create_guide(fppr_graph* g, hipStream_t s) {
+  using guide::Entry;
+  using guide::Pending;
+  uint64_t* acc = &g->device_bytes;
+  hipError_t e;
+  if ((e = launch_guide_sizes(g, s)) != hipSuccess) return hip_fail(e, "guide table sizes");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+  uint64_t e1 = 0;
+  if ((e = hipMemcpy(&e1, g->d_err + 4, 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read sizes");
+  if (e1 >= (1ull << 32)) return invalid("layout GUIDE needs fewer than 2^32 row-table entries");
+  g->g_entries1 = e1;
+  if ((e = dmalloc(&g->ghead, g->n, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide heads)");
+  if ((e = dmalloc(&g->gT, g->m, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide thresholds)");
+  if ((e = dmalloc(&g->gctl, 1, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide counters)");
+  const uint64_t kMaxCap = (1ull << 32) - 1;  // entry indices are 32-bit
+  uint64_t cap = std::min(kMaxCap, e1 + std::max<uint64_t>(e1 * 3 / 2, 1u << 16));
+  uint64_t tcap = std::max<uint64_t>(e1 / 8, 1u << 14);
+  for (int attempt = 0;; ++attempt) {
+    if (attempt == 6) return invalid("guide tables did not fit after several attempts");
+    if ((e = dmalloc(&g->gent, cap, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide entries)");
+    if ((e = dmalloc(&g->gtab[0], tcap, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide tables)");
+    if ((e = dmalloc(&g->gtab[1], tcap, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide tables)");
+    g->g_cap = cap;
+    g->g_tcap = static_cast<uint32_t>(tcap);
+    if ((e = zero_ctl(g, s)) != hipSuccess) return hip_fail(e, "zero control words");
+    if ((e = launch_guide_build(g, true, kGuideLevels, s)) != hipSuccess) return hip_fail(e, "guide tables");
+    uint32_t depth = 1;
+    GuideCtl h{};
+    for (uint32_t l = 2; l <= kGuideLevels; ++l) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+      if ((e = hipMemcpy(&h, g->gctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read");
+      if (h.tables[l] == 0 || h.tables[l] > tcap || h.next_entry > cap) break;
+      if ((e = launch_guide_level(g, l, kGuideLevels, s)) != hipSuccess) return hip_fail(e, "guide level");
+      depth = l;
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
+    if ((e = hipMemcpy(&h, g->gctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read");
+    uint32_t err = 0;
+    if ((e = hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read");
+    uint64_t most = 0;
+    for (uint32_t l = 0; l < kGuideLevels + 2; ++l) most = std::max<uint64_t>(most, h.tables[l]);
+    const bool full = h.next_entry > cap || most > tcap;
+    if (!full) {
+      if (err & kErrGuide) return invalid("guide tables need more than 64 levels");
+      if (err) return invalid("graph build failed:" + err_bits(err));
+      g->g_levels = depth;
+      return FPPR_OK;
+    }
+    g->device_bytes -= align_up(cap * sizeof(Entry)) + 2 * align_up(tcap * sizeof(Pending));
+    dfree(g->gent);
+    dfree(g->gtab[0]);
+    dfree(g->gtab[1]);
+    if (cap == kMaxCap && h.next_entry > cap) return invalid("layout GUIDE needs fewer than 2^32 table entries");
+    const uint64_t asked = h.next_entry + h.next_entry / 4;
+    cap = std::min(kMaxCap, std::max<uint64_t>(cap * 2, asked));
+    tcap = std::max(tcap * 2, most + most / 4);
+  }
 }
 
 uint32_t log2_exact(uint32_t v) {
@@ -164,6 +243,9 @@ WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* so
   WalkDesc D{};
   D.rec = g->rec;
   D.blocks = g->blocks;
+  D.ghead = g->ghead;
+  D.gent = g->gent;
+  D.g_cap = g->g_cap;
   D.pool = stitch ? g->pool : nullptr;
   D.S_small = stitch ? g->pool_opts.S : 0u;
   D.sources = sources;
@@ -179,7 +261,7 @@ WalkDesc make_desc(const fppr_graph* g, const fppr_params* p, const uint32_t* so
   D.T = fppr_alpha_threshold(p->alpha);
   D.tree_min = g->tree_min;
   D.K_log2 = stitch ? g->K_log2 : 0;
-  D.flags = (g->narrow ? kDescNarrow : 0u) | (g->tagged ? kDescTagged : 0u);
+  D.flags = (g->narrow ? kDescNarrow : 0u) | (g->tagged ? kDescTagged : 0u) | (g->guide ? kDescGuide : 0u);
   return D;
 }
 
@@ -250,8 +332,10 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
   if (opts && opts->hub_threshold) H = opts->hub_threshold;
   if (H < kLeafEdges) H = kLeafEdges;
   const uint32_t layout = opts ? opts->layout : FPPR_LAYOUT_AUTO;
-  if (layout != FPPR_LAYOUT_AUTO && layout != FPPR_LAYOUT_WIDE && layout != FPPR_LAYOUT_NARROW)
-    return invalid("layout must be AUTO, WIDE or NARROW");
+  if (layout != FPPR_LAYOUT_AUTO && layout != FPPR_LAYOUT_WIDE && layout != FPPR_LAYOUT_NARROW &&
+      layout != FPPR_LAYOUT_GUIDE)
+    return invalid("layout must be AUTO, WIDE, NARROW or GUIDE");
+  if (layout == FPPR_LAYOUT_GUIDE && csr->n > kMaxTaggedNodes) return invalid("layout GUIDE needs n <= 2^30");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   fppr_graph* g = new fppr_graph();
@@ -296,8 +380,10 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     g->col = csr->col;
     g->w = csr->w;
   }
-  FPPR_TRY(dmalloc(&g->rec, n, acc), "hipMalloc(rec)");
-  FPPR_TRY(dmalloc(&g->region, n, acc), "hipMalloc(region)");
+  if (layout != FPPR_LAYOUT_GUIDE) {
+    FPPR_TRY(dmalloc(&g->rec, n, acc), "hipMalloc(rec)");
+    FPPR_TRY(dmalloc(&g->region, n, acc), "hipMalloc(region)");
+  }
   FPPR_TRY(dmalloc(&g->flag, n, acc), "hipMalloc(flag)");
   FPPR_TRY(dmalloc(&g->scan, n, acc), "hipMalloc(scan)");
   FPPR_TRY(dmalloc(&g->rows, n, acc), "hipMalloc(rows)");
@@ -320,10 +406,11 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     return invalid("layout NARROW needs max out-degree x max weight < 2^32");
   }
   g->narrow = layout == FPPR_LAYOUT_NARROW || (layout == FPPR_LAYOUT_AUTO && fits);
+  g->guide = layout == FPPR_LAYOUT_GUIDE;
   FPPR_TRY(dmalloc(&g->live, n, acc), "hipMalloc(live nodes)");
   FPPR_TRY(dmalloc(&g->dang, n, acc), "hipMalloc(dangling nodes)");
   FPPR_TRY(launch_split_nodes(g, s), "split nodes");
-  FPPR_TRY(launch_region_sizes(g, s), "region sizes");
+  if (!g->guide) FPPR_TRY(launch_region_sizes(g, s), "region sizes");
   FPPR_TRY(read_ctl(g, s, &c), "read region sizes");
   g->n_live = c.live;
   g->n_dang = n - c.live;
@@ -332,13 +419,21 @@ FPPR_API fppr_status fppr_graph_create(const fppr_csr* csr, const fppr_graph_opt
     FPPR_TRY(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming), "hipEventCreate(fork)");
     FPPR_TRY(hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming), "hipEventCreate(join)");
   }
-  g->n_blocks = c.blocks;
-  FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
   if (g->tagged) {
     FPPR_TRY(dmalloc(&g->cls, n, acc), "hipMalloc(node classes)");
     FPPR_TRY(launch_node_class(g, 0, s), "node classes");
   }
-  FPPR_TRY(launch_leaves(g, s, true), "leaf blocks");
+  if (g->guide) {
+    const fppr_status st = create_guide(g, s);
+    if (st != FPPR_OK) {
+      free_graph(g);
+      return st;
+    }
+  } else {
+    g->n_blocks = c.blocks;
+    FPPR_TRY(dmalloc(&g->blocks, g->n_blocks, acc), "hipMalloc(blocks)");
+    FPPR_TRY(launch_leaves(g, s, true), "leaf blocks");
+  }
   FPPR_TRY(read_ctl(g, s, &c), "read build status");
   if (c.err) {
     std::string msg = "graph build failed:" + err_bits(c.err);
@@ -371,7 +466,7 @@ FPPR_API fppr_status fppr_graph_info(const fppr_graph* g, uint32_t* n, uint64_t*
 
 FPPR_API fppr_status fppr_graph_layout(const fppr_graph* g, uint32_t* layout) {
   if (!g || !layout) return invalid("graph or layout is NULL");
-  *layout = g->narrow ? FPPR_LAYOUT_NARROW : FPPR_LAYOUT_WIDE;
+  *layout = g->guide ? FPPR_LAYOUT_GUIDE : (g->narrow ? FPPR_LAYOUT_NARROW : FPPR_LAYOUT_WIDE);
   return FPPR_OK;
 }
 
@@ -379,7 +474,7 @@ static fppr_status pool_kernels(fppr_graph* g, hipStream_t s) {
   hipError_t e;
   if ((e = launch_small_flags(g, g->pool_opts.S, s)) != hipSuccess) return hip_fail(e, "small flags");
   if ((e = launch_small_compact(g, g->pool_opts.S, s)) != hipSuccess) return hip_fail(e, "small compact");
-  if ((e = launch_pool(g, s)) != hipSuccess) return hip_fail(e, "pool");
+  if ((e = g->guide ? launch_pool_guide(g, s) : launch_pool(g, s)) != hipSuccess) return hip_fail(e, "pool");
   return FPPR_OK;
 }
 
@@ -403,7 +498,8 @@ FPPR_API fppr_status fppr_graph_build_pool(fppr_graph* g, const fppr_pool_opts* 
   }
   // node-indexed: node v's K entries at v * K, so a walk that arrives at a
   // small node over a tagged edge finds its entry without the node's line
-  const uint64_t need = static_cast<uint64_t>(g->n) * o->K;
+  // (entries of 16 bytes with guide tables: the end node's record rides along)
+  const uint64_t need = static_cast<uint64_t>(g->n) * o->K * (g->guide ? 2u : 1u);
   if (!g->small_nodes) {
     if ((e = dmalloc(&g->small_nodes, g->n, &g->device_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(small nodes)");
   }
@@ -441,7 +537,7 @@ FPPR_API fppr_status fppr_graph_export_pool(const fppr_graph* g, uint64_t* entri
   uint64_t* tmp = nullptr;  // the canonical order, gathered from the node-indexed pool
   hipError_t e = hipMalloc(&tmp, total * 8);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(pool export)");
-  e = launch_pool_export(g, tmp, s);
+  e = g->guide ? launch_pool_guide_export(g, tmp, s) : launch_pool_export(g, tmp, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipMemcpy(entries, tmp, total * 8, hipMemcpyDeviceToHost);
   (void)hipFree(tmp);
@@ -465,6 +561,10 @@ FPPR_API fppr_status fppr_graph_set_hub_threshold(fppr_graph* g, uint32_t hub_th
   uint32_t H = hub_threshold ? hub_threshold : kLeafEdges;
   if (H < kLeafEdges) H = kLeafEdges;
   if (H == g->tree_min) return FPPR_OK;
+  if (g->guide) {  // guide tables have no prefix trees: nothing to lay out again
+    g->tree_min = H;
+    return FPPR_OK;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
@@ -790,6 +890,7 @@ FPPR_API fppr_status fppr_run_check(const void* workspace, void* stream) {
   unsigned long long ctl[2];
   e = hipMemcpy(ctl, workspace, sizeof ctl, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "read run status");
+  if (ctl[1] & 2) return invalid("a walk met guide tables that did not resolve its pick (rebuild the graph)");
   if (ctl[1]) return invalid("a source id was >= n (its walks were skipped)");
   return FPPR_OK;
 }

@@ -10,6 +10,7 @@
 #include "../../include/fppr.h"
 #include "agg_hash.hpp"
 #include "fppr_device.hpp"
+#include "guide.hpp"
 
 namespace fppr {
 
@@ -21,6 +22,15 @@ enum : uint32_t {
   kErrDegree = 16u,
   kErrCapacity = 32u,
   kErrNarrow = 64u,  // a row total above 2^32 - 1 in a graph with the narrow layout
+  kErrGuide = 128u,  // guide tables: more child entries, tables or levels than the graph holds
+};
+
+// Child levels of the guide tables are built one pass each, at most this many.
+constexpr uint32_t kGuideLevels = 64;
+// Allocation counters of a guide-table build (device memory).
+struct GuideCtl {
+  unsigned long long next_entry;       // first free entry
+  uint32_t tables[kGuideLevels + 2];   // child tables pushed per level
 };
 
 }  // namespace fppr
@@ -68,7 +78,16 @@ struct fppr_graph {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::mutex side_mu;  // keeps each event record and its wait together across host threads
-  uint64_t pool_cap = 0;             // entries allocated
+  // guide-table layout (guide.hpp): instead of node lines and row regions
+  bool guide = false;
+  fppr::guide::Head* ghead = nullptr;      // [n] first entry of each node's table, lg | class << 8
+  fppr::guide::Entry* gent = nullptr;      // [g_cap] row tables [0, g_entries1), then child tables
+  uint64_t* gT = nullptr;                  // [m] draw thresholds of every edge but a row's last
+  fppr::guide::Pending* gtab[2] = {nullptr, nullptr};  // child tables of alternate levels, g_tcap each
+  fppr::GuideCtl* gctl = nullptr;
+  uint64_t g_entries1 = 0, g_cap = 0;
+  uint32_t g_tcap = 0, g_levels = 1;       // deepest level of the last full build
+  uint64_t pool_cap = 0;             // u64 words allocated
   uint32_t* small_nodes = nullptr;   // [n] rank -> node
   uint64_t device_bytes = 0;
 };
@@ -103,6 +122,17 @@ hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t n, uint64
                            uint64_t* total_dev, hipStream_t s);
 uint64_t scan_block_count(uint64_t n);
 
+// guide.hip
+// table sizes of every node + scan -> g->scan, total at d_err[4..5]
+hipError_t launch_guide_sizes(fppr_graph* g, hipStream_t s);
+// heads (bases from g->scan when `bases`, else kept), row tables and the
+// first child level's list; children deeper than `levels` are refused
+hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStream_t s);
+// the child tables of one level (2 <= level <= levels)
+hipError_t launch_guide_level(fppr_graph* g, uint32_t level, uint32_t levels, hipStream_t s);
+hipError_t launch_pool_guide(fppr_graph* g, hipStream_t s);
+hipError_t launch_pool_guide_export(const fppr_graph* g, uint64_t* out, hipStream_t s);
+
 // pool.hip
 hipError_t launch_small_flags(fppr_graph* g, uint32_t S, hipStream_t s);
 hipError_t launch_small_compact(fppr_graph* g, uint32_t S, hipStream_t s);
@@ -121,7 +151,11 @@ constexpr uint32_t kSrcBuf = kWalkChunk + 2;  // source ids of one chunk in LDS 
 struct WalkDesc {
   const Block* rec;          // node lines
   const Block* blocks;       // row regions
-  const uint64_t* pool;      // stitched runs: the graph's pool (node v's entries at v << K_log2)
+  const uint64_t* pool;      // stitched runs: the graph's pool (node v's entries at v << K_log2;
+                             // 16-byte entries in graphs with guide tables)
+  const fppr::guide::Head* ghead;   // guide-table graphs: node heads
+  const fppr::guide::Entry* gent;   // guide-table graphs: table entries
+  uint64_t g_cap;                   // guide-table graphs: entries allocated
   const uint32_t* sources;   // source ids by row, or null for row = node id
   uint32_t* endpoints;
   uint64_t first;
@@ -139,12 +173,17 @@ constexpr uint32_t kDescEpBySource = 1;
 constexpr uint32_t kDescNarrow = 2;
 // the graph's leaf destinations and pool entries carry class tags
 constexpr uint32_t kDescTagged = 4;
+// the graph has the guide-table layout (every descriptor of a table must)
+constexpr uint32_t kDescGuide = 8;
 // lane_keys: the per-lane-key form of the kernel (for tables whose
 // descriptors all read one graph; see same_graph_table)
 // descs: the table on the device; host: the same table in host memory (it
 // selects the kernel's form: layouts, per-lane keys, inline restarts)
 hipError_t launch_walk(const WalkDesc* descs, const WalkDesc* host, uint32_t ndesc, uint64_t total,
                        unsigned long long* ctl, fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s);
+// walk_guide.hip: the walk kernel of tables whose descriptors all have kDescGuide
+hipError_t launch_walk_guide(const WalkDesc* descs, const WalkDesc* host, uint32_t ndesc, uint64_t total,
+                             unsigned long long* ctl, fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s);
 // 0 when every descriptor's graph is wide, 1 when every one is narrow, 2 mixed
 int table_layout(const WalkDesc* h, uint32_t ndesc);
 // true when a table (host copy) has more than one descriptor and all of them

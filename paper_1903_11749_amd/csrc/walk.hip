@@ -726,6 +726,10 @@ hipError_t launch_plain(const WalkTable& t, bool stats, uint32_t b, hipStream_t 
 hipError_t launch_walk(const WalkDesc* descs, const WalkDesc* host, uint32_t ndesc, uint64_t total,
                        unsigned long long* ctl, fppr_stats* stats, uint32_t blocks_per_cu, hipStream_t s) {
   if (total == 0 || ndesc == 0) return hipSuccess;
+  uint32_t guides = 0;
+  for (uint32_t k = 0; k < ndesc; ++k) guides += (host[k].flags & kDescGuide) ? 1u : 0u;
+  if (guides == ndesc) return launch_walk_guide(descs, host, ndesc, total, ctl, stats, blocks_per_cu, s);
+  if (guides) return hipErrorInvalidValue;  // one table cannot mix guide tables with the tree layouts
   WalkTable t{descs, ndesc, total, ctl, stats};
   const uint32_t b = blocks_per_cu;
   const int layout = table_layout(host, ndesc);
@@ -749,7 +753,8 @@ hipError_t launch_walk(const WalkDesc* descs, const WalkDesc* host, uint32_t nde
 bool same_graph_table(const WalkDesc* h, uint32_t ndesc) {
   for (uint32_t k = 1; k < ndesc; ++k)
     if (h[k].rec != h[0].rec || h[k].blocks != h[0].blocks || h[k].tree_min != h[0].tree_min ||
-        h[k].K_log2 != h[0].K_log2 || h[k].pool != h[0].pool || h[k].S_small != h[0].S_small)
+        h[k].K_log2 != h[0].K_log2 || h[k].pool != h[0].pool || h[k].S_small != h[0].S_small ||
+        h[k].ghead != h[0].ghead || h[k].gent != h[0].gent)
       return false;
   return ndesc > 1;
 }

@@ -53,6 +53,7 @@ class fppr_csr(ctypes.Structure):
 FPPR_LAYOUT_AUTO = 0
 FPPR_LAYOUT_WIDE = 1
 FPPR_LAYOUT_NARROW = 2
+FPPR_LAYOUT_GUIDE = 3
 
 
 class fppr_graph_opts(ctypes.Structure):
@@ -351,7 +352,7 @@ class Graph:
         return dict(n=n.value, m=m.value, hubs=hubs.value, small=small.value, device_bytes=by.value)
 
     def layout(self) -> int:
-        """FPPR_LAYOUT_WIDE or FPPR_LAYOUT_NARROW."""
+        """FPPR_LAYOUT_WIDE, FPPR_LAYOUT_NARROW or FPPR_LAYOUT_GUIDE."""
         v = ctypes.c_uint32()
         _check(lib().fppr_graph_layout(self._h, ctypes.byref(v)))
         return int(v.value)

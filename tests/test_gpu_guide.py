@@ -1,0 +1,256 @@
+"""The guide-table layout (FPPR_LAYOUT_GUIDE): the same edge for every draw as
+the flat search of Sec. 2.1, so every run is bit-identical to the oracle and
+to the tree layouts: plain and stitched walks, pools, statistics (including
+the sum of ceil(log2 deg) over picks), rows of every weight shape (child
+tables several levels deep), row totals above 2^32, rebuilds of a borrowed
+CSR, source lists, the per-lane-key form (many descriptors on one graph)
+and the scale-24 workload in the benchmark's launch configuration."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import torch
+
+    from paper_1903_11749_amd import fppr
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fppr.lib()
+    return fppr
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def compare(out, ref, k, counts=True, sample=None):
+    import torch
+
+    torch.cuda.synchronize()
+    rows = slice(None) if sample is None else np.asarray(sample)
+    if counts and ref.counts is not None:
+        assert np.array_equal(u32(out.n_distinct)[rows], ref.n_distinct)
+        assert np.array_equal(u32(out.counts)[rows], ref.counts)
+    if k:
+        assert np.array_equal(u32(out.topk)[rows], ref.topk)
+    assert np.array_equal(u64(out.digest)[rows], ref.digest)
+
+
+def stats_equal(out, ref_stats):
+    st = out.stats_dict()
+    for key in ("walks", "moves", "steps", "capped", "dangling_moves", "plain_moves",
+                "stitched_moves", "probe_log_sum"):
+        assert st[key] == ref_stats[key], (key, st[key], ref_stats[key])
+
+
+def check_all(fp, g, alpha, R, seed, k, pool_opts=None, narrow_too=True):
+    """Every source, plain and (with pool_opts) stitched: guide = oracle
+    (counts, top-k, digests, statistics, pool) = narrow layout."""
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_GUIDE)
+    assert G.layout() == fp.FPPR_LAYOUT_GUIDE
+    og = O.Graph.from_csr(g)
+    Gn = fp.Graph(g) if narrow_too else None
+    for stitch in ((False, True) if pool_opts else (False,)):
+        pool = None
+        if stitch:
+            G.build_pool(alpha=alpha, **pool_opts)
+            pool = O.Pool(og, alpha=alpha, **pool_opts)
+            assert np.array_equal(G.export_pool(), pool.entries())
+            if Gn is not None:
+                Gn.build_pool(alpha=alpha, **pool_opts)
+        out = fp.run(G, alpha, R, seed, topk=k, stitch=stitch, counts=True, stats=True)
+        ref = O.run(og, alpha, R, seed, topk=k, pool=pool)
+        compare(out, ref, k)
+        stats_equal(out, ref.stats)
+        if Gn is not None:
+            outn = fp.run(Gn, alpha, R, seed, topk=k, stitch=stitch, counts=True, stats=True)
+            compare(outn, ref, k)
+    G.close()
+    if Gn is not None:
+        Gn.close()
+
+
+def test_small_all_sources(fp):
+    say("case: guide layout, small graph, plain and stitched")
+    check_all(fp, synth.small_graph(), 0.2, 100, 1, 16, pool_opts=dict(S=8, L=3, K=16, seed=4))
+
+
+def test_long_rows(fp):
+    """Rows of thousands of edges (row tables of up to 2^11 entries)."""
+    g = synth.chung_lu(6000, 90000, 2.05, 200, seed=2071)
+    say(f"case: guide layout, long rows, max out-degree {g.degrees().max()}")
+    check_all(fp, g, 0.15, 80, 19, 12, pool_opts=dict(S=24, L=3, K=32, seed=77))
+
+
+def test_row_totals_above_32_bits(fp):
+    g = synth.chung_lu(3000, 40000, 2.1, 2_000_000_000, seed=2072)
+    say(f"case: guide layout, weights up to {g.w.max()}")
+    check_all(fp, g, 0.15, 60, 5, 8, pool_opts=dict(S=16, L=2, K=8, seed=3), narrow_too=False)
+
+
+def shaped_graph():
+    """Rows whose thresholds crowd into a few entries: tiny edges between
+    giants, doubling weights, one giant among ones, equal weights."""
+    rng = np.random.default_rng(2090)
+    n = 400
+    rows = []
+    big = 0xFFFFFFFF
+    for u in range(n):
+        kind = u % 8
+        if kind == 0:
+            w = np.r_[[big], np.ones(int(rng.integers(3, 900))), [big]]
+        elif kind == 1:
+            w = 2 ** (np.arange(int(rng.integers(2, 33))) % 32)
+        elif kind == 2:
+            d = int(rng.integers(2, 3000))
+            w = np.ones(d)
+            w[rng.integers(0, d)] = big
+        elif kind == 3:
+            w = np.ones(int(rng.integers(1, 70)))
+        elif kind == 4:
+            w = np.minimum(rng.zipf(1.1, int(rng.integers(1, 5000))), big)
+        elif kind == 5:
+            w = np.r_[np.ones(200), [big] * 3, np.ones(300), [big], np.ones(5)]
+        elif kind == 6:
+            w = np.zeros(0)  # no out-edges
+        else:
+            w = rng.integers(1, 1 << 32, int(rng.integers(1, 200)), dtype=np.uint64)
+        rows.append(np.asarray(w, np.uint64))
+    src = np.concatenate([np.full(r.size, u, np.uint32) for u, r in enumerate(rows)])
+    dst = rng.integers(0, n, src.size).astype(np.uint32)
+    w = np.concatenate(rows).astype(np.uint32)
+    return synth.csr_from_edges(n, src, dst, w)
+
+
+def test_crowded_thresholds(fp):
+    g = shaped_graph()
+    say(f"case: guide layout, crowded thresholds, m {g.m}")
+    check_all(fp, g, 0.1, 300, 23, 10, pool_opts=dict(S=32, L=3, K=64, seed=9), narrow_too=False)
+
+
+def test_borrowed_csr_rebuild(fp):
+    """New weights written into a borrowed CSR, then a rebuild: the oracle's
+    result for the new weights (or, when they need more child tables than
+    the graph was made with, a failed check)."""
+    import torch
+
+    say("case: guide layout, borrowed CSR + rebuild")
+    small = synth.small_graph()
+    ro = torch.from_numpy(small.row_offsets.view(np.int64)).cuda()
+    col = torch.from_numpy(small.col.view(np.int32)).cuda()
+    w = torch.from_numpy(small.w.view(np.int32)).cuda()
+    G = fp.Graph(n=small.n, row_offsets=ro, col=col, w=w, layout=fp.FPPR_LAYOUT_GUIDE)
+    G.build_pool(S=8, L=3, K=16, alpha=0.2, seed=4)
+    for k, w2 in enumerate([(small.w.astype(np.uint64) * 7 % 1000 + 1).astype(np.uint32), small.w.copy()]):
+        w.copy_(torch.from_numpy(w2.view(np.int32)).cuda())
+        G.rebuild()
+        G.check()
+        g2 = synth.CSRGraph(small.n, small.row_offsets, small.col, w2)
+        og = O.Graph.from_csr(g2)
+        pool = O.Pool(og, S=8, L=3, K=16, alpha=0.2, seed=4)
+        assert np.array_equal(G.export_pool(), pool.entries())
+        out = fp.run(G, 0.2, 50, 8 + k, topk=5, stitch=True, stats=True)
+        ref = O.run(og, 0.2, 50, 8 + k, topk=5, pool=pool)
+        compare(out, ref, 5)
+        stats_equal(out, ref.stats)
+    G.close()
+
+
+def test_source_lists_and_lane_keys(fp):
+    """A source list with duplicates and nodes of every class, then a server
+    (many descriptors on one graph: the per-lane-key form) whose every query
+    equals its run alone and the oracle."""
+    g = synth.chung_lu(5000, 60000, 2.2, 255, seed=2091)
+    say("case: guide layout, source lists, server")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_GUIDE)
+    G.build_pool(S=16, L=3, K=32, alpha=0.15, seed=6)
+    og = O.Graph.from_csr(g)
+    pool = O.Pool(og, S=16, L=3, K=32, alpha=0.15, seed=6)
+    rng = np.random.default_rng(2092)
+    deg = g.degrees()
+    src = np.r_[np.nonzero(deg == 0)[0][:5], np.nonzero((deg > 0) & (deg <= 16))[0][:5],
+                np.argsort(deg)[-5:], rng.integers(0, g.n, 40), [7, 7, 7]].astype(np.uint32)
+    for stitch in (False, True):
+        out = fp.run(G, 0.15, 333, 12, sources=src, topk=20, stitch=stitch, stats=True)
+        ref = O.run(og, 0.15, 333, 12, sources=src, topk=20, pool=pool if stitch else None)
+        compare(out, ref, 20)
+        stats_equal(out, ref.stats)
+    S = fp.Server(G, mode="continuous", max_requests=8, slice_walks=1 << 16)
+    qs = [dict(sources=rng.integers(0, g.n, int(rng.integers(1, 40))).astype(np.uint32),
+               R=int(rng.choice([100, 1000, 3000])), seed=100 + i, topk=16, stitch=bool(i % 2)) for i in range(12)]
+    ids = [S.submit(q["sources"], q["R"], 0.15, q["seed"], q["topk"], q["stitch"]) for q in qs]
+    outs = [S.wait(i) for i in ids]
+    S.close()
+    for q, (topk, digest, _) in zip(qs, outs):
+        ref = O.run(og, 0.15, q["R"], q["seed"], sources=q["sources"], topk=q["topk"],
+                    pool=pool if q["stitch"] else None, want_counts=False)
+        assert np.array_equal(topk, ref.topk) and np.array_equal(digest, ref.digest)
+    G.close()
+
+
+def test_medium_rmat_all_sources(fp):
+    """R-MAT scale 20, every source: digests, distinct counts, top-k and
+    statistics of all 2^20 sources against the oracle."""
+    import torch
+
+    say("case: guide layout, R-MAT scale 20, all sources")
+    g = synth.medium_graph()
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_GUIDE)
+    out = fp.run(G, 0.15, 200, 2, topk=32, counts=True, stats=True)
+    og = O.Graph.from_csr(g)
+    ref = O.run(og, 0.15, 200, 2, topk=32, want_counts=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(out.n_distinct), ref.n_distinct)
+    assert np.array_equal(u32(out.topk), ref.topk)
+    assert np.array_equal(u64(out.digest), ref.digest)
+    stats_equal(out, ref.stats)
+    G.close()
+
+
+def test_scale24_stitched_sampled(fp):
+    """R-MAT scale 24 with the pool (S=32, L=3, K=64): the whole pool and a
+    stratified sample of 8192 sources (hubs, small, dangling, random)
+    against the oracle, from a run over all 2^24 sources in the benchmark's
+    launch configuration."""
+    import torch
+
+    say("case: guide layout, scale-24 generate")
+    g = synth.scale24_graph()
+    cfg = synth.SCALE24
+    st = cfg["stitch"]
+    say("case: guide layout, scale-24 GPU graph + pool")
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_GUIDE)
+    G.build_pool(S=st["S"], L=st["L"], K=st["K"], alpha=cfg["alpha"], seed=st["seed"])
+    say("case: guide layout, scale-24 GPU run, all sources")
+    out = fp.run(G, cfg["alpha"], cfg["R"], cfg["seed"], topk=cfg["topk"], stitch=True, counts=False, stats=True)
+    torch.cuda.synchronize()
+    say("case: guide layout, scale-24 oracle pool")
+    og = O.Graph.from_csr(g)
+    pool = O.Pool(og, S=st["S"], L=st["L"], K=st["K"], alpha=cfg["alpha"], seed=st["seed"])
+    assert np.array_equal(G.export_pool(), pool.entries())
+    sample = synth.stratified_sources(g, 8192, seed=12, hub_threshold=cfg["hub_threshold"], small_max=st["S"])
+    say("case: guide layout, scale-24 oracle sample")
+    ref = O.run(og, cfg["alpha"], cfg["R"], cfg["seed"], sources=sample, topk=cfg["topk"], pool=pool)
+    compare(out, ref, cfg["topk"], counts=False, sample=sample)
+    out_s = fp.run(G, cfg["alpha"], cfg["R"], cfg["seed"], sources=sample, topk=cfg["topk"], stitch=True)
+    compare(out_s, ref, cfg["topk"])
+    stats_equal(out_s, ref.stats)
+    assert out.stats_dict()["walks"] == g.n * cfg["R"]
+    G.close()
