@@ -1,9 +1,13 @@
 """Benchmark: one step = the whole hot path on the R-MAT scale-24 workload.
 
 Step (all on one HIP stream, CSR already resident in HBM):
-  rebuild   validation, per-row uint64 weight prefixes, node records, and
-            the 8-ary prefix trees of every row above 8 out-edges (the
-            split of large nodes; it never changes results)
+  rebuild   validation and the search structure of every row's weights:
+            by default the guide tables (per-edge draw thresholds of the
+            uint64 weight prefixes, row tables indexed by the draw's top bits
+            and their child tables; one 64-byte read per weighted pick for
+            almost every draw), or with --layout narrow/wide the node records
+            and the prefix trees of every row above 8 out-edges (the split of
+            large nodes); every layout gives the same edge for every draw
   pool      short walks of <= 3 steps for every node of out-degree <= 32
             (K = 64 per node)
   run       128 walks from every one of the 2^24 sources, alpha = 0.15,
@@ -11,7 +15,8 @@ Step (all on one HIP stream, CSR already resident in HBM):
 
 Prints one JSON line. `value` is walk-steps per second of the whole step
 (steps = edges traversed, restarts and every step of a stitched move
-included). The roofline object describes the walk kernel k_walk, timed with
+included). The roofline object describes the walk kernel (k_walk_guide, or
+k_walk for the tree layouts), timed with
 HIP events the library records on the stream it launches on; in all-nodes
 runs on graphs where a quarter or more of the nodes have no out-edges, the
 walks from those nodes run in a coin-only kernel (k_dangling) beside it on a
@@ -47,26 +52,38 @@ def alg_bytes(st: dict) -> int:
             + 8 * st["stitched_moves"] + 4 * st["walks"])
 
 
-WALK_SOURCES = ["paper_1903_11749_amd/csrc/walk.hip", "paper_1903_11749_amd/csrc/fppr_device.hpp",
-                "paper_1903_11749_amd/csrc/fppr_internal.hpp"]
-PMC_SUMMARY = "profiles/k_walk_rmat24_pmc.md"
+# the walk kernel of each layout: its sources and its committed counter summary
+WALK_KERNELS = {
+    "guide": ("k_walk_guide", ["paper_1903_11749_amd/csrc/walk_guide.hip", "paper_1903_11749_amd/csrc/guide.hpp",
+                               "paper_1903_11749_amd/csrc/fppr_device.hpp",
+                               "paper_1903_11749_amd/csrc/fppr_internal.hpp"],
+              "profiles/k_walk_guide_rmat24_pmc.md"),
+    "tree": ("k_walk", ["paper_1903_11749_amd/csrc/walk.hip", "paper_1903_11749_amd/csrc/fppr_device.hpp",
+                        "paper_1903_11749_amd/csrc/fppr_internal.hpp"],
+             "profiles/k_walk_rmat24_pmc.md"),
+}
+LAYOUT_NAMES = {"guide": 3, "narrow": 2, "wide": 1, "auto": 0}
 
 
-def walk_source_hash() -> str:
+def walk_kernel(layout: str):
+    return WALK_KERNELS["guide" if layout == "guide" else "tree"]
+
+
+def walk_source_hash(layout: str = "guide") -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in WALK_SOURCES:
+    for f in walk_kernel(layout)[1]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def counted_traffic():
-    """HBM bytes of one k_walk launch from the committed counter summary, or
-    None when the walk kernel's sources changed since the counters were
-    taken."""
-    path = os.path.join(ROOT, PMC_SUMMARY)
+def counted_traffic(layout: str = "guide"):
+    """HBM bytes of one walk-kernel launch from the committed counter
+    summary, or None when the walk kernel's sources changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, walk_kernel(layout)[2])
     if not os.path.exists(path):
         return None
     vals = {}
@@ -76,7 +93,7 @@ def counted_traffic():
                                                      "walk_traffic_bytes_per_launch"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
-    if vals.get("walk_kernel_source_sha256") != walk_source_hash():
+    if vals.get("walk_kernel_source_sha256") != walk_source_hash(layout):
         return None
     return int(vals["walk_traffic_bytes_per_launch"])
 
@@ -114,10 +131,12 @@ def _bench_batch(args, fppr, torch, np, stream):
         f"{sum(g.m for g in graphs)} edges in {time.time() - t0:.1f}s")
     Gs, manifest = [], []
     t0 = time.time()
+    guide = args.batch_layout == "guide"
     for sp, g in zip(specs, graphs):
-        G = fppr.Graph(g)
+        G = fppr.Graph(g, layout=LAYOUT_NAMES[args.batch_layout])
         pools = [dict(o, seed=6000 + sp["index"]) for o in BATCH_POOLS]
-        r = G.autotune(sp["alpha"], sp["R"], sp["walk_seed"], hub_thresholds=BATCH_HUB_THRESHOLDS,
+        r = G.autotune(sp["alpha"], sp["R"], sp["walk_seed"],
+                       hub_thresholds=[0] if guide else BATCH_HUB_THRESHOLDS,
                        blocks_per_cu=BATCH_BLOCKS_PER_CU, pools=pools, stream=stream)
         Gs.append(G)
         manifest.append(dict(graph=sp["index"], n=g.n, m=g.m, alpha=sp["alpha"], R=sp["R"],
@@ -421,14 +440,19 @@ def cpu_model() -> str:
 
 def ablation(args, fppr, torch, np, g, ro, col, w, cfg, st_cfg, stream, value, ms_per_step):
     """The paper's optimisation ablation (Fig. 5(b)) on this path: the same
-    step without the short-walk pool (plain walks) and without prefix trees
-    (every row binary-searched over its leaf blocks), each as a graph of
-    its own on the same borrowed CSR, timed like the main step."""
+    step without the short-walk pool (plain walks), and with the tree layout
+    in place of the guide tables, with and without prefix trees (rows then
+    binary-searched over their leaf blocks), each as a graph of its own on
+    the same borrowed CSR, timed like the main step."""
     alpha, R, seed, k = cfg["alpha"], cfg["R"], cfg["seed"], cfg["topk"]
-    variants = {"stitched_trees": {"ms_per_step": round(ms_per_step, 3), "walk_steps_per_s": round(value, 1)}}
-    for name, stitch, H in (("plain_trees", False, 0), ("stitched_no_trees", True, 0xFFFFFFFF),
-                            ("plain_no_trees", False, 0xFFFFFFFF)):
-        G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=H)
+    head = f"stitched_{args.layout}"
+    variants = {head: {"ms_per_step": round(ms_per_step, 3), "walk_steps_per_s": round(value, 1)}}
+    runs = [(f"plain_{args.layout}", False, args.layout, 0)] if args.layout == "guide" else []
+    runs += [("stitched_trees", True, "narrow", 0), ("plain_trees", False, "narrow", 0),
+             ("stitched_no_trees", True, "narrow", 0xFFFFFFFF), ("plain_no_trees", False, "narrow", 0xFFFFFFFF)]
+    runs = [r for r in runs if r[0] not in variants]
+    for name, stitch, layout, H in runs:
+        G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=H, layout=LAYOUT_NAMES[layout])
         if stitch:
             G.build_pool(S=st_cfg["S"], L=st_cfg["L"], K=st_cfg["K"], alpha=alpha, seed=st_cfg["seed"])
         p = fppr.make_params(alpha, R, seed, k, stitch=stitch, counts=False, digests=True, stats=True)
@@ -457,11 +481,12 @@ def ablation(args, fppr, torch, np, g, ro, col, w, cfg, st_cfg, stream, value, m
         del ws, o
         G.close()
         torch.cuda.synchronize()
-    base = variants["stitched_trees"]["ms_per_step"]
+    base = variants[head]["ms_per_step"]
     for v in variants.values():
         v["slowdown_vs_full"] = round(v["ms_per_step"] / base, 3)
     return {"what": ("the scale-24 step without the short-walk pool (plain walks: results differ, "
-                     "same law) and without prefix trees (identical results), like Fig. 5(b)"),
+                     "same law), with prefix trees in place of guide tables and without either "
+                     "(identical results), like Fig. 5(b)"),
             "variants": variants}
 
 
@@ -532,6 +557,9 @@ def main():
                     help="skip the runs without stitching and without prefix trees")
     ap.add_argument("--cpu-sample-1t", type=int, default=1 << 14,
                     help="sources of the oracle's one-thread timing (0 = skip)")
+    ap.add_argument("--layout", choices=sorted(LAYOUT_NAMES), default="guide",
+                    help="search structure of the weighted pick (every layout gives identical results)")
+    ap.add_argument("--batch-layout", choices=sorted(LAYOUT_NAMES), default="guide")
     ap.add_argument("--full-parity", action="store_true",
                     help="one step, then every source checked against the oracle (scale 24: minutes)")
     args = ap.parse_args()
@@ -576,10 +604,15 @@ def main():
         cfg = dict(synth.SCALE24)
         t0 = time.time()
         g = synth.scale24_graph()
+        picks = ("weighted picks through guide tables (row tables indexed by the draw, child "
+                 "tables where edges crowd; the workload's 4096-edge hub split is subsumed: every "
+                 "row costs about one 64-byte read per pick, results identical)"
+                 if args.layout == "guide" else
+                 "large rows split (prefix trees above 8 edges: the workload's 4096-edge hub "
+                 "threshold gives identical results, 8 measured faster)")
         wname = ("rmat-scale24 (n=2^24, m=2^28, a,b,c,d=.57,.19,.19,.05, Zipf(1.2) weights "
                  "in [1,1e4]), alpha=0.15, R=128, all sources, short walks S=32 L=3 K=64, "
-                 "large rows split (prefix trees above 8 edges: the workload's 4096-edge hub "
-                 "threshold gives identical results, 8 measured faster), top-32")
+                 f"{picks}, top-32")
     else:
         cfg = dict(synth.MEDIUM)
         cfg["hub_threshold"] = 4096
@@ -596,7 +629,8 @@ def main():
     col = torch.from_numpy(g.col.view(np.int32)).cuda()
     w = torch.from_numpy(g.w.view(np.int32)).cuda()
     torch.cuda.synchronize()
-    G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=args.hub_threshold)
+    G = fppr.Graph(n=g.n, row_offsets=ro, col=col, w=w, hub_threshold=args.hub_threshold,
+                   layout=LAYOUT_NAMES[args.layout])
     if st_cfg:
         G.build_pool(S=st_cfg["S"], L=st_cfg["L"], K=st_cfg["K"], alpha=alpha, seed=st_cfg["seed"])
     info = G.info()
@@ -668,16 +702,17 @@ def main():
         st_walk[key] -= st_coin.get(key, 0)
     ab = alg_bytes(st_walk)
     achieved = ab / (kern_avg / 1e3) / 1e9
-    traffic = counted_traffic() if args.workload in ("scale24", "serve") else None
+    traffic = counted_traffic(args.layout) if args.workload in ("scale24", "serve") else None
+    kname = walk_kernel(args.layout)[0]
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
-                "kernel": "k_walk", "kernel_ms": round(kern_avg, 3), "alg_bytes_per_launch": ab,
+                "kernel": kname, "kernel_ms": round(kern_avg, 3), "alg_bytes_per_launch": ab,
                 "traffic_GBps": round(traffic / (kern_avg / 1e3) / 1e9, 1) if traffic else None,
                 "walk_steps_per_s_kernel": round(st_walk["steps"] / (kern_avg / 1e3), 1),
                 "moves_per_s_kernel": round(st_walk["moves"] / (kern_avg / 1e3), 1)}
     coin_only = None
     if split:
-        coin_only = {"kernel": "k_dangling", "stream": "the graph's side stream, beside k_walk",
+        coin_only = {"kernel": "k_dangling", "stream": f"the graph's side stream, beside {kname}",
                      "ms_after_walk_kernel": round(coin_avg, 3), "walks": st_coin["walks"],
                      "moves": st_coin["moves"], "bound": "alu (one Philox4x32-10 block per move)"}
 
@@ -688,7 +723,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64 integer",
         "data": "synthetic (seeded R-MAT; stands in for the paper's SNAP graphs)",
         "config": {"workload": wname, "n": g.n, "m": g.m, "R": R, "alpha": alpha, "seed": seed,
-                   "topk": k, "tree_rows": info["hubs"], "small_nodes": info["small"],
+                   "topk": k, "layout": args.layout, "tree_rows": info["hubs"], "small_nodes": info["small"],
                    "rows_over_4096": int((g.degrees() > 4096).sum())},
         "sources_per_s": round(sources_per_s, 1),
         "graph_steps_per_s": round(graph_steps / (ms_per_step / 1e3), 1),

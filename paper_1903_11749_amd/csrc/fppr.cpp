@@ -68,6 +68,8 @@ void free_graph(fppr_graph* g) {
   dfree(g->ghead);
   dfree(g->gent);
   dfree(g->gT);
+  dfree(g->gerec);
+  dfree(g->gclass);
   dfree(g->gtab[0]);
   dfree(g->gtab[1]);
   dfree(g->gctl);
@@ -162,7 +164,31 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
   g->g_entries1 = e1;
   if ((e = dmalloc(&g->ghead, g->n, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide heads)");
   if ((e = dmalloc(&g->gT, g->m, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide thresholds)");
+  if ((e = dmalloc(&g->gerec, g->m, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(edge records)");
   if ((e = dmalloc(&g->gctl, 1, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide counters)");
+  // rows by size class (degrees never change: built once). The table bases
+  // sit in g->scan until the build below reads them, so the class lists are
+  // made first, in a scratch list of their own.
+  if ((e = dmalloc(&g->gclass, g->n, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(row classes)");
+  {
+    uint64_t* bases = nullptr;  // the table bases, kept while the class scans reuse g->scan
+    if ((e = dmalloc(&bases, g->n, nullptr)) != hipSuccess) return hip_fail(e, "hipMalloc(scratch)");
+    e = hipMemcpyAsync(bases, g->scan, g->n * 8, hipMemcpyDeviceToDevice, s);
+    uint64_t at = 0;
+    for (uint32_t c = 0; c < 8 && e == hipSuccess; ++c) {
+      g->gclass_off[c] = at;
+      e = launch_guide_class(g, c, at, s);
+      uint64_t cnt = 0;
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess) e = hipMemcpy(&cnt, g->d_err + 14, 8, hipMemcpyDeviceToHost);
+      at += cnt;
+    }
+    g->gclass_off[8] = at;
+    if (e == hipSuccess) e = hipMemcpyAsync(g->scan, bases, g->n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(bases);
+    if (e != hipSuccess) return hip_fail(e, "row classes");
+  }
   const uint64_t kMaxCap = (1ull << 32) - 1;  // entry indices are 32-bit
   uint64_t cap = std::min(kMaxCap, e1 + std::max<uint64_t>(e1 * 3 / 2, 1u << 16));
   uint64_t tcap = std::max<uint64_t>(e1 / 8, 1u << 14);

@@ -30,7 +30,8 @@ constexpr uint32_t kGuideLevels = 64;
 // Allocation counters of a guide-table build (device memory).
 struct GuideCtl {
   unsigned long long next_entry;       // first free entry
-  uint32_t tables[kGuideLevels + 2];   // child tables pushed per level
+  uint32_t pad[30];                    // the two counters in lines of their own
+  uint32_t tables[kGuideLevels + 2];   // child-table slots taken per level
 };
 
 }  // namespace fppr
@@ -82,7 +83,10 @@ struct fppr_graph {
   bool guide = false;
   fppr::guide::Head* ghead = nullptr;      // [n] first entry of each node's table, lg | class << 8
   fppr::guide::Entry* gent = nullptr;      // [g_cap] row tables [0, g_entries1), then child tables
-  uint64_t* gT = nullptr;                  // [m] draw thresholds of every edge but a row's last
+  uint64_t* gT = nullptr;                  // [m] draw thresholds of every edge but a row's last (~0 there)
+  uint4* gerec = nullptr;                  // [m] record of every edge's destination: id | tag, base, lg
+  uint32_t* gclass = nullptr;              // [n_live] rows by size class (1, 2, 3-4, ..., 33-64, > 64 edges)
+  uint64_t gclass_off[9] = {0};            // class c's rows at gclass[gclass_off[c] .. gclass_off[c + 1])
   fppr::guide::Pending* gtab[2] = {nullptr, nullptr};  // child tables of alternate levels, g_tcap each
   fppr::GuideCtl* gctl = nullptr;
   uint64_t g_entries1 = 0, g_cap = 0;
@@ -125,6 +129,8 @@ uint64_t scan_block_count(uint64_t n);
 // guide.hip
 // table sizes of every node + scan -> g->scan, total at d_err[4..5]
 hipError_t launch_guide_sizes(fppr_graph* g, hipStream_t s);
+// the rows of size class c (see gclass) to gclass + at; their count at d_err[14..15]
+hipError_t launch_guide_class(fppr_graph* g, uint32_t c, uint64_t at, hipStream_t s);
 // heads (bases from g->scan when `bases`, else kept), row tables and the
 // first child level's list; children deeper than `levels` are refused
 hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStream_t s);

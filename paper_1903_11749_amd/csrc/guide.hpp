@@ -163,24 +163,25 @@ FPPR_GUIDE_FN void row_bucket(uint32_t kb, uint32_t b, uint64_t* blo, uint64_t* 
   *bhi = *blo + ((1ull << (64 - kb)) - 1);
 }
 
-// Thresholds and shape of the entry whose draws meet candidates c0 .. c1:
-// returns the number of middle candidates that go to a child table (0 when
-// the entry resolves every draw itself).
-template <class Th>
-FPPR_GUIDE_FN uint32_t entry_shape(const Th& T, uint32_t c0, uint32_t c1, uint64_t* lo, uint64_t* hi) {
+// Thresholds of the entry whose draws meet candidates c0 .. c1, from
+// t0 = T(c0) and t1 = T(c1 - 1) (read only when the entry has more than one
+// candidate): returns the number of middle candidates that go to a child
+// table (0 when the entry resolves every draw itself).
+FPPR_GUIDE_FN uint32_t entry_bounds(uint32_t c0, uint32_t c1, uint64_t t0, uint64_t t1, uint64_t* lo, uint64_t* hi) {
   const uint32_t count = c1 - c0 + 1;
   if (count == 1) {  // every draw to R
     *lo = 0;
     *hi = 0;
     return 0;
   }
-  if (count == 2) {
-    *lo = *hi = T(c0);
-    return 0;
-  }
-  *lo = T(c0);
-  *hi = T(c1 - 1);
-  return count == 3 ? 0u : count - 2;
+  *lo = t0;
+  *hi = count == 2 ? t0 : t1;
+  return count <= 3 ? 0u : count - 2;
+}
+template <class Th>
+FPPR_GUIDE_FN uint32_t entry_shape(const Th& T, uint32_t c0, uint32_t c1, uint64_t* lo, uint64_t* hi) {
+  if (c1 == c0) return entry_bounds(c0, c1, 0, 0, lo, hi);
+  return entry_bounds(c0, c1, T(c0), T(c1 - 1), lo, hi);
 }
 
 // A candidate's record: destination id (with its class tag), the first
@@ -189,18 +190,14 @@ struct Cand {
   uint32_t id, base, lg;
 };
 
-// Fills entry e whose draws meet candidates c0 .. c1 (c0 <= c1) of a row
-// with thresholds T(j); rec(c) is candidate c's record. With more than three
-// candidates the middle ones go to a child table: push(lo, hi, first, last,
-// nbk, sh) lays it out and returns its first entry, or ~0u when there is no
-// room (the entry then sends the middle draws to the first middle candidate,
-// and the caller reports the graph as failed).
-template <class Th, class Rec, class Push>
-FPPR_GUIDE_FN void fill_entry(Entry* e, const Th& T, const Rec& rec, uint32_t c0, uint32_t c1, Push&& push) {
-  uint64_t lo = 0, hi = 0;
-  const uint32_t mc = entry_shape(T, c0, c1, &lo, &hi);
-  const Cand L = rec(c0), R = rec(c1);
-  const Cand M = c1 - c0 >= 2 ? rec(c0 + 1) : L;
+// Writes entry e whose draws meet candidates c0 .. c1 (c0 <= c1): bounds lo,
+// hi and mc from entry_bounds, L = candidate c0, M = c0 + 1 (when there is
+// one), R = c1. With mc > 0 the middle candidates go to the child table at
+// entry `child` with shift sh (child_shape); child = ~0u when no room was
+// found for it: the entry then sends the middle draws to the first middle
+// candidate, and the caller reports the graph as failed.
+FPPR_GUIDE_FN void put_entry(Entry* e, uint64_t lo, uint64_t hi, uint32_t mc, const Cand& L, const Cand& M,
+                             const Cand& R, uint32_t child, uint32_t sh) {
   Entry x{};
   x.lo = lo;
   x.hi = hi;
@@ -211,17 +208,30 @@ FPPR_GUIDE_FN void fill_entry(Entry* e, const Th& T, const Rec& rec, uint32_t c0
   x.m_id = M.id;
   x.m_base = M.base;
   x.meta = L.lg | (M.lg << 8) | (R.lg << 16);
-  if (mc) {
-    uint32_t sh = 0;
-    const uint32_t nbk = child_shape(lo, hi, mc, &sh);
-    const uint32_t base = push(lo, hi, c0 + 1, c1 - 1, nbk, sh);
-    if (base != ~0u) {
-      x.m_id = 0;
-      x.m_base = base;
-      x.meta = L.lg | (sh << 8) | (R.lg << 16) | kChild;
-    }
+  if (mc && child != ~0u) {
+    x.m_id = 0;
+    x.m_base = child;
+    x.meta = L.lg | (sh << 8) | (R.lg << 16) | kChild;
   }
   *e = x;
+}
+
+// An entry from thresholds T(j) and candidate records rec(c) read through
+// accessors; push(lo, hi, first, last, nbk, sh) lays out the child table of
+// the middle candidates first..last when there is one and returns its first
+// entry (or ~0u).
+template <class Th, class Rec, class Push>
+FPPR_GUIDE_FN void fill_entry(Entry* e, const Th& T, const Rec& rec, uint32_t c0, uint32_t c1, Push&& push) {
+  uint64_t lo = 0, hi = 0;
+  const uint32_t mc = entry_shape(T, c0, c1, &lo, &hi);
+  const Cand L = rec(c0), R = rec(c1);
+  const Cand M = c1 - c0 >= 2 ? rec(c0 + 1) : L;
+  uint32_t sh = 0, child = ~0u;
+  if (mc) {
+    const uint32_t nbk = child_shape(lo, hi, mc, &sh);
+    child = push(lo, hi, c0 + 1, c1 - 1, nbk, sh);
+  }
+  put_entry(e, lo, hi, mc, L, M, R, child, sh);
 }
 
 // Candidates c0 .. c1 of every entry of a row table (2^kb entries, d >= 1
