@@ -70,6 +70,7 @@ void free_graph(fppr_graph* g) {
   dfree(g->gT);
   dfree(g->gerec);
   dfree(g->gclass);
+  dfree(g->gruns);
   dfree(g->gtab[0]);
   dfree(g->gtab[1]);
   dfree(g->gctl);
@@ -175,7 +176,7 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     if ((e = dmalloc(&bases, g->n, nullptr)) != hipSuccess) return hip_fail(e, "hipMalloc(scratch)");
     e = hipMemcpyAsync(bases, g->scan, g->n * 8, hipMemcpyDeviceToDevice, s);
     uint64_t at = 0;
-    for (uint32_t c = 0; c < 8 && e == hipSuccess; ++c) {
+    for (uint32_t c = 0; c < 9 && e == hipSuccess; ++c) {
       g->gclass_off[c] = at;
       e = launch_guide_class(g, c, at, s);
       uint64_t cnt = 0;
@@ -183,7 +184,16 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
       if (e == hipSuccess) e = hipMemcpy(&cnt, g->d_err + 14, 8, hipMemcpyDeviceToHost);
       at += cnt;
     }
-    g->gclass_off[8] = at;
+    g->gclass_off[9] = at;
+    // runs of entries of the longest rows
+    uint64_t runs = 0;
+    if (e == hipSuccess) e = launch_guide_runs_count(g, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && g->gclass_off[9] > g->gclass_off[8])
+      e = hipMemcpy(&runs, g->d_err + 14, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = dmalloc(&g->gruns, runs ? runs : 1, acc);
+    if (e == hipSuccess) e = launch_guide_runs_fill(g, s);
+    g->n_runs = runs;
     if (e == hipSuccess) e = hipMemcpyAsync(g->scan, bases, g->n * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dfree(bases);

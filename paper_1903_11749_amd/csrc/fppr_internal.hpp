@@ -85,8 +85,10 @@ struct fppr_graph {
   fppr::guide::Entry* gent = nullptr;      // [g_cap] row tables [0, g_entries1), then child tables
   uint64_t* gT = nullptr;                  // [m] draw thresholds of every edge but a row's last (~0 there)
   uint4* gerec = nullptr;                  // [m] record of every edge's destination: id | tag, base, lg
-  uint32_t* gclass = nullptr;              // [n_live] rows by size class (1, 2, 3-4, ..., 33-64, > 64 edges)
-  uint64_t gclass_off[9] = {0};            // class c's rows at gclass[gclass_off[c] .. gclass_off[c + 1])
+  uint32_t* gclass = nullptr;              // [n_live] rows by size class (1, 2, 3-4, ..., 33-64, 65-1024, more edges)
+  uint64_t gclass_off[10] = {0};           // class c's rows at gclass[gclass_off[c] .. gclass_off[c + 1])
+  uint2* gruns = nullptr;                  // [n_runs] (row, first entry) of each run of 16 entries of the longest rows
+  uint64_t n_runs = 0;
   fppr::guide::Pending* gtab[2] = {nullptr, nullptr};  // child tables of alternate levels, g_tcap each
   fppr::GuideCtl* gctl = nullptr;
   uint64_t g_entries1 = 0, g_cap = 0;
@@ -131,6 +133,9 @@ uint64_t scan_block_count(uint64_t n);
 hipError_t launch_guide_sizes(fppr_graph* g, hipStream_t s);
 // the rows of size class c (see gclass) to gclass + at; their count at d_err[14..15]
 hipError_t launch_guide_class(fppr_graph* g, uint32_t c, uint64_t at, hipStream_t s);
+// entry runs of the longest rows: counts and scan (total at d_err[14..15]), then the list
+hipError_t launch_guide_runs_count(fppr_graph* g, hipStream_t s);
+hipError_t launch_guide_runs_fill(fppr_graph* g, hipStream_t s);
 // heads (bases from g->scan when `bases`, else kept), row tables and the
 // first child level's list; children deeper than `levels` are refused
 hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStream_t s);

@@ -143,9 +143,11 @@ __global__ void k_guide_sizes(const uint64_t* __restrict__ off, uint32_t n, uint
   }
 }
 
-// size class of a row: ceil(log2 d) for 1 <= d <= 64 (0..6), 7 above, none without edges
+// size class of a row: ceil(log2 d) for 1 <= d <= 64 (0..6), 7 up to kMidMax
+// edges, 8 above, none without edges
+constexpr uint32_t kMidMax = 1024;
 __device__ __forceinline__ uint32_t row_class(uint64_t d) {
-  return d == 0 ? ~0u : (d <= 64 ? guide::ceil_log2(d) : 7u);
+  return d == 0 ? ~0u : (d <= 64 ? guide::ceil_log2(d) : (d <= kMidMax ? 7u : 8u));
 }
 __global__ void k_class_flags(const uint64_t* __restrict__ off, uint32_t n, uint32_t c, uint32_t* __restrict__ flag) {
   for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < n;
@@ -254,26 +256,93 @@ __global__ void __launch_bounds__(kThreads) k_guide_rows(const uint32_t* __restr
   alloc.flush();
 }
 
-// Long rows (more than 64 edges): one block per row. The row's total, then
-// its prefixes, thresholds and edge records in tiles of kThreads * 4 edges
-// (thresholds also staged in LDS for rows of up to kStaged edges), then its
-// table entries: each thread takes a run of consecutive entries, finds the
-// first one's candidates by binary search and the rest by merging bucket
-// edges with thresholds.
-constexpr uint32_t kStaged = 4096;
+// Orders this wave's LDS and global writes before its later reads by
+// other lanes of the workgroup (here: of the wave itself).
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Rows of 65 to kMidMax edges: one wave per row. The row's total, then its
+// prefixes, thresholds and edge records 64 edges at a time (thresholds also
+// staged in the wave's LDS), then its 64 to 512 entries, each lane taking a
+// run of consecutive ones: the first by binary search over the staged
+// thresholds, the rest by merging.
+__global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restrict__ rows, uint64_t count,
+                                                        const uint64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ col,
+                                                        const uint32_t* __restrict__ w, const Head* __restrict__ head,
+                                                        uint32_t n, uint64_t* T, uint4* erec, Entry* __restrict__ ent,
+                                                        Alloc alloc) {
+  __shared__ uint64_t sT[kThreads / 64][kMidMax];
+  const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
+  uint64_t* st = sT[wv];
+  const uint64_t waves = static_cast<uint64_t>(gridDim.x) * (kThreads / 64);
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(kThreads / 64) + wv; r < count; r += waves) {  // wave-uniform
+    const uint32_t u = rows[r];
+    const uint64_t a = off[u];
+    const uint32_t d = static_cast<uint32_t>(off[u + 1] - a);  // 65 .. kMidMax
+    uint64_t part = 0;
+    for (uint32_t j = lane; j < d; j += 64) part += w[a + j];
+    const uint64_t W = wave_sum_u64(part);
+    uint64_t carry = 0;
+    for (uint32_t j0 = 0; j0 < d; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      const uint64_t x = j < d ? w[a + j] : 0u;
+      const uint64_t inc = wave_inclusive_scan_u64(x);
+      const uint64_t P = carry + inc;
+      carry += __shfl(static_cast<unsigned long long>(inc), 63, 64);
+      if (j < d) {
+        const uint64_t t = j + 1 < d && P < W ? guide::threshold(P, W) : ~0ull;
+        T[a + j] = t;
+        st[j] = t;
+        erec[a + j] = edge_record(head, n, col[a + j], u);
+      }
+    }
+    group_sync();  // the staged thresholds and the row's records, visible to the wave
+    if (W != 0) {  // wave-uniform
+      auto th = [&](uint32_t j) -> uint64_t { return st[j]; };
+      const ERec rec{erec + a};
+      Entry* row_ent = ent + head[u].base;
+      const uint32_t kb = guide::table_bits(guide::ceil_log2(d));
+      const uint32_t last = d - 1, nb = 1u << kb, run = nb >> 6;  // nb = 64 .. 512
+      uint32_t c = 0;
+      for (uint32_t k = 0; k < run; ++k) {
+        const uint32_t b = lane * run + k;
+        uint64_t blo, bhi;
+        guide::row_bucket(kb, b, &blo, &bhi);
+        if (k == 0) c = guide::containing(th, 0u, last, blo);
+        while (c < last && th(c) <= blo) ++c;
+        const uint32_t c0 = c;
+        uint32_t c1 = c0;
+        while (c1 < last && th(c1) <= bhi) ++c1;
+        const uint64_t t0 = c1 > c0 ? th(c0) : 0, t1 = c1 > c0 ? th(c1 - 1) : 0;
+        const Cand L = rec(c0), R = rec(c1);
+        const Cand M = c1 > c0 + 1 ? rec(c0 + 1) : L;
+        c = c1;
+        write_entry(alloc, true, row_ent + b, c0, c1, t0, t1, L, M, R, a, u);
+      }
+    }
+    group_sync();  // the next row's staging reuses the LDS words
+  }
+  alloc.flush();
+}
+
+// Long rows (more than kMidMax edges): one block per row for the row's
+// total, then its prefixes, thresholds and edge records in tiles of
+// kThreads * 4 edges. Their entries come after, from k_guide_runs.
 __global__ void __launch_bounds__(kThreads) k_guide_long(const uint32_t* __restrict__ rows, uint64_t count,
                                                          const uint64_t* __restrict__ off,
                                                          const uint32_t* __restrict__ col,
                                                          const uint32_t* __restrict__ w,
                                                          const Head* __restrict__ head, uint32_t n, uint64_t* T,
-                                                         uint4* erec, Entry* __restrict__ ent, Alloc alloc) {
+                                                         uint4* erec) {
   __shared__ uint64_t lds[kThreads / 64];
-  __shared__ uint64_t sT[kStaged];
   for (uint64_t r = blockIdx.x; r < count; r += gridDim.x) {
     const uint32_t u = rows[r];
     const uint64_t a = off[u];
     const uint64_t d = off[u + 1] - a;
-    const bool staged = d <= kStaged;  // block-uniform
     uint64_t part = 0;
     for (uint64_t j = threadIdx.x; j < d; j += kThreads) part += w[a + j];
     uint64_t W = 0;
@@ -296,90 +365,52 @@ __global__ void __launch_bounds__(kThreads) k_guide_long(const uint32_t* __restr
         const uint64_t j = j0 + k;
         if (j < d) {
           const uint64_t P = carry + excl + v[k];
-          const uint64_t t = j + 1 < d && P < W ? guide::threshold(P, W) : ~0ull;
-          T[a + j] = t;
-          if (staged) sT[j] = t;
+          T[a + j] = j + 1 < d && P < W ? guide::threshold(P, W) : ~0ull;
           erec[a + j] = edge_record(head, n, col[a + j], u);
         }
       }
       carry += total;
     }
-    __syncthreads();  // the row's thresholds and records, visible to the whole block
-    if (W != 0) {  // block-uniform
-      const uint64_t* Tg = T + a;
-      auto th = [&](uint32_t j) -> uint64_t { return staged ? sT[j] : Tg[j]; };
-      const ERec rec{erec + a};
-      Entry* row_ent = ent + head[u].base;
-      const uint32_t kb = guide::table_bits(guide::ceil_log2(d));
-      const uint32_t last = static_cast<uint32_t>(d - 1), nb = 1u << kb;
-      const uint32_t run = (nb + kThreads - 1) / kThreads;
-      uint32_t c = 0;
-      for (uint32_t k = 0; k < run; ++k) {  // block-uniform
-        const uint32_t b = threadIdx.x * run + k;
-        const bool act = b < nb;
-        uint32_t c0 = 0, c1 = 0;
-        uint64_t t0 = 0, t1 = 0;
-        Cand L{}, M{}, R{};
-        if (act) {
-          uint64_t blo, bhi;
-          guide::row_bucket(kb, b, &blo, &bhi);
-          if (k == 0) c = guide::containing(th, 0u, last, blo);
-          while (c < last && th(c) <= blo) ++c;
-          c0 = c;
-          c1 = c0;
-          while (c1 < last && th(c1) <= bhi) ++c1;
-          if (c1 > c0) {
-            t0 = th(c0);
-            t1 = th(c1 - 1);
-          }
-          L = rec(c0);
-          R = rec(c1);
-          M = c1 > c0 + 1 ? rec(c0 + 1) : L;
-          c = c1;
-        }
-        write_entry(alloc, act, row_ent + (act ? b : 0u), c0, c1, t0, t1, L, M, R, a, u);
-      }
-    }
-    __syncthreads();  // the next row's scans and staging reuse the LDS words
   }
-  alloc.flush();
 }
 
-// The child tables of one level, one lane per table: its entries in order,
-// their candidates by merging bucket edges with the row's thresholds;
-// tables of the next level go to the other list. A wave runs until the
-// largest table among its lanes is done.
-__global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __restrict__ T,
-                                                          const uint4* __restrict__ erec, Entry* __restrict__ ent,
-                                                          const Pending* __restrict__ in, uint32_t level, Alloc alloc) {
-  uint32_t count = alloc.ctl->tables[level];
-  if (count > alloc.tcap) count = alloc.tcap;
+// Entries of the long rows: one thread per run of kRun consecutive entries
+// of one row (runs listed at creation: (row, first entry)), the first run
+// entry's candidates by binary search over the row's thresholds, the rest by
+// merging.
+constexpr uint32_t kRun = 16;
+__global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict__ runs, uint64_t count,
+                                                         const uint64_t* __restrict__ off, const Head* __restrict__ head,
+                                                         const uint64_t* __restrict__ T, const uint4* __restrict__ erec,
+                                                         Entry* __restrict__ ent, Alloc alloc) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; __ballot(t < count) != 0;
-       t += stride) {  // wave-uniform loop
-    Pending p{};
-    if (t < count) p = in[t];  // tables that found no room have no buckets
-    uint32_t most = p.nbk;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint32_t x = static_cast<uint32_t>(__shfl_xor(static_cast<int>(most), o, 64));
-      most = x > most ? x : most;
-    }
-    const Thr th{T + p.off};
-    const ERec rec{erec + p.off};
-    uint32_t c = p.a;
-    for (uint32_t i = 0; i < most; ++i) {  // wave-uniform
-      const bool act = i < p.nbk;
+  for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; __ballot(q < count) != 0;
+       q += stride) {  // wave-uniform loop
+    bool act = q < count;
+    const uint2 rb = act ? runs[q] : make_uint2(0, 0);
+    const uint32_t u = rb.x;
+    const uint64_t a = act ? off[u] : 0;
+    const uint32_t d = act ? static_cast<uint32_t>(off[u + 1] - a) : 1u;
+    act = act && d > 1;
+    const uint32_t kb = guide::table_bits(guide::ceil_log2(d));
+    const uint32_t last = d - 1;
+    const Thr th{T + a};
+    const ERec rec{erec + a};
+    Entry* row_ent = ent + (act ? head[u].base : 0u);
+    uint32_t c = 0;
+    for (uint32_t k = 0; k < kRun; ++k) {  // wave-uniform
+      const uint32_t b = rb.y + k;
       uint32_t c0 = 0, c1 = 0;
       uint64_t t0 = 0, t1 = 0;
       Cand L{}, M{}, R{};
       if (act) {
         uint64_t blo, bhi;
-        guide::child_bucket(p.origin, p.end, p.sh, i, &blo, &bhi);
-        while (c < p.b && th(c) <= blo) ++c;
+        guide::row_bucket(kb, b, &blo, &bhi);
+        if (k == 0) c = guide::containing(th, 0u, last, blo);
+        while (c < last && th(c) <= blo) ++c;
         c0 = c;
         c1 = c0;
-        while (c1 < p.b && th(c1) <= bhi) ++c1;
+        while (c1 < last && th(c1) <= bhi) ++c1;
         if (c1 > c0) {
           t0 = th(c0);
           t1 = th(c1 - 1);
@@ -388,6 +419,99 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
         R = rec(c1);
         M = c1 > c0 + 1 ? rec(c0 + 1) : L;
         c = c1;
+      }
+      write_entry(alloc, act, row_ent + (act ? b : 0u), c0, c1, t0, t1, L, M, R, a, u);
+    }
+  }
+  alloc.flush();
+}
+
+// runs of each long row (2^kb / kRun: kb >= 10 there)
+__global__ void k_run_counts(const uint32_t* __restrict__ rows, uint64_t count, const uint64_t* __restrict__ off,
+                             uint32_t* __restrict__ flag) {
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < count;
+       r += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t u = rows[r];
+    const uint64_t d = off[u + 1] - off[u];
+    flag[r] = (1u << guide::table_bits(guide::ceil_log2(d))) / kRun;
+  }
+}
+__global__ void k_run_fill(const uint32_t* __restrict__ rows, uint64_t count, const uint32_t* __restrict__ flag,
+                           const uint64_t* __restrict__ scan, uint2* __restrict__ runs) {
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < count;
+       r += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    for (uint32_t i = 0; i < flag[r]; ++i) runs[scan[r] + i] = make_uint2(rows[r], i * kRun);
+}
+
+// The child tables of one level, a group of kLevelGroup lanes per table.
+// The group holds the table's thresholds in its lanes when there are at
+// most kLevelGroup of them (almost every table: a child's middle holds a
+// few candidates), and each lane fills one entry at a time: candidates by
+// binary search over the group's thresholds through lane shuffles (over the
+// row's thresholds in memory for larger tables), records from the edge
+// records. Tables of the next level go to the other list.
+constexpr uint32_t kLevelGroup = 8;
+__global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __restrict__ T,
+                                                          const uint4* __restrict__ erec, Entry* __restrict__ ent,
+                                                          const Pending* __restrict__ in, uint32_t level, Alloc alloc) {
+  constexpr uint32_t GL = kLevelGroup;
+  uint32_t count = alloc.ctl->tables[level];
+  if (count > alloc.tcap) count = alloc.tcap;
+  const uint32_t gi = __lane_id() & (GL - 1);
+  const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * kThreads) / GL;
+  for (uint64_t t = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) / GL; __ballot(t < count) != 0;
+       t += groups) {  // wave-uniform loop
+    Pending p{};
+    if (t < count) p = in[t];  // tables that found no room have no buckets
+    const uint32_t nthr = p.b - p.a;  // thresholds between the candidates
+    const bool small = nthr <= GL;
+    const uint64_t Tv = gi < nthr && small ? T[p.off + p.a + gi] : ~0ull;
+    uint32_t most = (p.nbk + GL - 1) / GL;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t x = static_cast<uint32_t>(__shfl_xor(static_cast<int>(most), o, 64));
+      most = x > most ? x : most;
+    }
+    const Thr th{T + p.off};
+    const ERec rec{erec + p.off};
+    for (uint32_t k = 0; k < most; ++k) {  // wave-uniform
+      const uint32_t i = k * GL + gi;
+      const bool act = i < p.nbk;
+      uint64_t blo = 0, bhi = 0;
+      if (act) guide::child_bucket(p.origin, p.end, p.sh, i, &blo, &bhi);
+      // thresholds <= blo and <= bhi among the group's (every lane shuffles)
+      uint32_t l0 = 0, h0 = small ? nthr : 0, l1 = 0, h1 = h0;
+#pragma unroll
+      for (uint32_t it = 0; it < 4; ++it) {  // ranges of at most GL + 1 = 9 positions
+        const uint32_t m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
+        const uint64_t x0 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(m0 & (GL - 1)), GL);
+        const uint64_t x1 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(m1 & (GL - 1)), GL);
+        if (l0 < h0) {
+          if (x0 <= blo) l0 = m0 + 1;
+          else h0 = m0;
+        }
+        if (l1 < h1) {
+          if (x1 <= bhi) l1 = m1 + 1;
+          else h1 = m1;
+        }
+      }
+      uint32_t c0 = p.a + l0, c1 = p.a + l1;
+      if (act && !small) {
+        c0 = guide::containing(th, p.a, p.b, blo);
+        c1 = guide::containing(th, p.a, p.b, bhi);
+      }
+      const uint64_t y0 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>((c0 - p.a) & (GL - 1)), GL);
+      const uint64_t y1 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>((c1 - p.a - 1) & (GL - 1)), GL);
+      uint64_t t0 = 0, t1 = 0;
+      Cand L{}, M{}, R{};
+      if (act) {
+        if (c1 > c0) {
+          t0 = small ? y0 : th(c0);
+          t1 = small ? y1 : th(c1 - 1);
+        }
+        L = rec(c0);
+        R = rec(c1);
+        M = c1 > c0 + 1 ? rec(c0 + 1) : L;
       }
       write_entry(alloc, act, ent + (act ? p.base + i : 0u), c0, c1, t0, t1, L, M, R, p.off, p.row);
     }
@@ -493,6 +617,22 @@ hipError_t launch_guide_sizes(fppr_graph* g, hipStream_t s) {
   return launch_scan_u32(g->flag, g->scan, g->n, g->scan_blocks, reinterpret_cast<uint64_t*>(g->d_err + 4), s);
 }
 
+hipError_t launch_guide_runs_count(fppr_graph* g, hipStream_t s) {
+  const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
+  if (!nlong) return hipSuccess;
+  hipLaunchKernelGGL(k_run_counts, dim3(grid_for(nlong)), dim3(kThreads), 0, s, g->gclass + g->gclass_off[8], nlong,
+                     g->off, g->flag);
+  return launch_scan_u32(g->flag, g->scan, nlong, g->scan_blocks, reinterpret_cast<uint64_t*>(g->d_err + 14), s);
+}
+
+hipError_t launch_guide_runs_fill(fppr_graph* g, hipStream_t s) {
+  const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
+  if (!nlong) return hipSuccess;
+  hipLaunchKernelGGL(k_run_fill, dim3(grid_for(nlong)), dim3(kThreads), 0, s, g->gclass + g->gclass_off[8], nlong,
+                     g->flag, g->scan, g->gruns);
+  return hipGetLastError();
+}
+
 hipError_t launch_guide_class(fppr_graph* g, uint32_t c, uint64_t at, hipStream_t s) {
   hipLaunchKernelGGL(k_class_flags, dim3(grid_for(g->n)), dim3(kThreads), 0, s, g->off, g->n, c, g->flag);
   hipError_t e = launch_scan_u32(g->flag, g->scan, g->n, g->scan_blocks, reinterpret_cast<uint64_t*>(g->d_err + 14), s);
@@ -538,17 +678,24 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
   launch_rows<4>(g, p, s);
   launch_rows<5>(g, p, s);
   launch_rows<6>(g, p, s);
-  const uint64_t nlong = g->gclass_off[8] - g->gclass_off[7];
-  if (nlong)
-    hipLaunchKernelGGL(k_guide_long, dim3(static_cast<uint32_t>(nlong < 2048 ? nlong : 2048)), dim3(kThreads), 0, s,
-                       g->gclass + g->gclass_off[7], nlong, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec,
+  const uint64_t nmid = g->gclass_off[8] - g->gclass_off[7];
+  if (nmid)
+    hipLaunchKernelGGL(k_guide_mid, dim3(std::min<uint32_t>(grid_for(nmid * 64), 2048u)), dim3(kThreads), 0, s,
+                       g->gclass + g->gclass_off[7], nmid, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec,
                        g->gent, p);
+  const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
+  if (nlong) {
+    hipLaunchKernelGGL(k_guide_long, dim3(static_cast<uint32_t>(nlong < 2048 ? nlong : 2048)), dim3(kThreads), 0, s,
+                       g->gclass + g->gclass_off[8], nlong, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec);
+    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs), 2048u)), dim3(kThreads), 0, s,
+                       g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_guide_level(fppr_graph* g, uint32_t level, uint32_t levels, hipStream_t s) {
   const guide::Pending* in = g->gtab[level & 1u ? 1 : 0];
-  hipLaunchKernelGGL(k_guide_level, dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
+  hipLaunchKernelGGL(k_guide_level, dim3(4096), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
                      allocator(g, level + 1, levels));
   return hipGetLastError();
 }
