@@ -450,7 +450,7 @@ __global__ void k_run_fill(const uint32_t* __restrict__ rows, uint64_t count, co
 // binary search over the group's thresholds through lane shuffles (over the
 // row's thresholds in memory for larger tables), records from the edge
 // records. Tables of the next level go to the other list.
-constexpr uint32_t kLevelGroup = 8;
+constexpr uint32_t kLevelGroup = 16;
 __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __restrict__ T,
                                                           const uint4* __restrict__ erec, Entry* __restrict__ ent,
                                                           const Pending* __restrict__ in, uint32_t level, Alloc alloc) {
@@ -464,8 +464,10 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
     Pending p{};
     if (t < count) p = in[t];  // tables that found no room have no buckets
     const uint32_t nthr = p.b - p.a;  // thresholds between the candidates
-    const bool small = nthr <= GL;
+    // small tables: lane j holds threshold a + j and the record of candidate a + j
+    const bool small = nthr < GL;
     const uint64_t Tv = gi < nthr && small ? T[p.off + p.a + gi] : ~0ull;
+    const uint4 Rv = gi <= nthr && small ? erec[p.off + p.a + gi] : make_uint4(0, 0, 0, 0);
     uint32_t most = (p.nbk + GL - 1) / GL;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -482,7 +484,7 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
       // thresholds <= blo and <= bhi among the group's (every lane shuffles)
       uint32_t l0 = 0, h0 = small ? nthr : 0, l1 = 0, h1 = h0;
 #pragma unroll
-      for (uint32_t it = 0; it < 4; ++it) {  // ranges of at most GL + 1 = 9 positions
+      for (uint32_t it = 0; it < 4; ++it) {  // ranges of at most GL = 16 positions
         const uint32_t m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
         const uint64_t x0 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(m0 & (GL - 1)), GL);
         const uint64_t x1 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(m1 & (GL - 1)), GL);
@@ -495,23 +497,32 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
           else h1 = m1;
         }
       }
-      uint32_t c0 = p.a + l0, c1 = p.a + l1;
+      uint32_t j0 = l0, j1 = l1;  // candidates relative to a
       if (act && !small) {
-        c0 = guide::containing(th, p.a, p.b, blo);
-        c1 = guide::containing(th, p.a, p.b, bhi);
+        j0 = guide::containing(th, p.a, p.b, blo) - p.a;
+        j1 = guide::containing(th, p.a, p.b, bhi) - p.a;
       }
-      const uint64_t y0 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>((c0 - p.a) & (GL - 1)), GL);
-      const uint64_t y1 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>((c1 - p.a - 1) & (GL - 1)), GL);
+      const uint32_t jm = j1 > j0 + 1 ? j0 + 1 : j0;
+      const uint64_t y0 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(j0 & (GL - 1)), GL);
+      const uint64_t y1 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>((j1 - 1) & (GL - 1)), GL);
+      Cand L{__shfl(Rv.x, static_cast<int>(j0 & (GL - 1)), GL), __shfl(Rv.y, static_cast<int>(j0 & (GL - 1)), GL),
+             __shfl(Rv.z, static_cast<int>(j0 & (GL - 1)), GL)};
+      Cand M{__shfl(Rv.x, static_cast<int>(jm & (GL - 1)), GL), __shfl(Rv.y, static_cast<int>(jm & (GL - 1)), GL),
+             __shfl(Rv.z, static_cast<int>(jm & (GL - 1)), GL)};
+      Cand R{__shfl(Rv.x, static_cast<int>(j1 & (GL - 1)), GL), __shfl(Rv.y, static_cast<int>(j1 & (GL - 1)), GL),
+             __shfl(Rv.z, static_cast<int>(j1 & (GL - 1)), GL)};
+      const uint32_t c0 = p.a + j0, c1 = p.a + j1;
       uint64_t t0 = 0, t1 = 0;
-      Cand L{}, M{}, R{};
       if (act) {
         if (c1 > c0) {
           t0 = small ? y0 : th(c0);
           t1 = small ? y1 : th(c1 - 1);
         }
-        L = rec(c0);
-        R = rec(c1);
-        M = c1 > c0 + 1 ? rec(c0 + 1) : L;
+        if (!small) {
+          L = rec(c0);
+          R = rec(c1);
+          M = c1 > c0 + 1 ? rec(c0 + 1) : L;
+        }
       }
       write_entry(alloc, act, ent + (act ? p.base + i : 0u), c0, c1, t0, t1, L, M, R, p.off, p.row);
     }
@@ -695,7 +706,7 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
 
 hipError_t launch_guide_level(fppr_graph* g, uint32_t level, uint32_t levels, hipStream_t s) {
   const guide::Pending* in = g->gtab[level & 1u ? 1 : 0];
-  hipLaunchKernelGGL(k_guide_level, dim3(4096), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
+  hipLaunchKernelGGL(k_guide_level, dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
                      allocator(g, level + 1, levels));
   return hipGetLastError();
 }
