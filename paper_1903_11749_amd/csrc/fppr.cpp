@@ -247,7 +247,7 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
       tcap = std::max(tcap * 2, most + most / 4);
       cap = std::min(kMaxCap, std::max<uint64_t>(cap, h.next_entry + h.next_entry / 4));
     } else {
-      cap = std::min(kMaxCap, h.next_entry + h.next_entry / 8 + (1u << 20));
+      cap = std::min<uint64_t>(kMaxCap, h.next_entry + h.next_entry / 8 + (1u << 20));
     }
   }
 }
