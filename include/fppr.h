@@ -487,7 +487,9 @@ FPPR_API fppr_status fppr_batch_plan(const fppr_batch_item* items, uint32_t coun
 
 /* Validates every item as fppr_run would, lays out `workspace` (device,
  * >= fppr_batch_plan bytes) and uploads the walk table (synchronous); opts
- * may be NULL (no rebuild, full width). Items
+ * may be NULL (no rebuild, full width). The items' graphs either all have
+ * the guide layout or none does (INVALID_ARGUMENT otherwise: one launch runs
+ * one walk kernel). Items
  * are ordered by decreasing walk count in the table. The batch keeps a copy
  * of `items`; graphs, sources, outputs and the workspace must outlive it. */
 FPPR_API fppr_status fppr_batch_create(const fppr_batch_item* items, uint32_t count,

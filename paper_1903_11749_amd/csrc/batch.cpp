@@ -65,6 +65,10 @@ fppr_status check_items(const fppr_batch_item* items, uint32_t count) {
   for (uint32_t k = 0; k < count; ++k) {
     const fppr_batch_item& it = items[k];
     if (!it.graph) return invalid("batch item " + std::to_string(k) + ": graph is NULL");
+    // one walk launch serves the whole table, with one kernel per layout family
+    if (it.graph->guide != items[0].graph->guide)
+      return invalid("batch item " + std::to_string(k) +
+                     ": a batch cannot mix graphs with guide tables and graphs with the tree layouts");
     fppr_status st = check_params(it.graph, &it.params);
     if (st != FPPR_OK) return st;
     if (!it.sources && it.n_sources != it.graph->n && it.n_sources != 0)
@@ -369,7 +373,7 @@ FPPR_API fppr_status fppr_batch_manifest(const fppr_batch* b, char* json, size_t
              ", \"alpha\": " + dbl(g->pool_opts.alpha) + ", \"small_nodes\": " + std::to_string(g->n_small) + "}";
     j += std::string(k ? ", " : "") + "{\"item\": " + std::to_string(k) + ", \"graph\": {\"n\": " +
          std::to_string(g->n) + ", \"m\": " + std::to_string(g->m) + ", \"layout\": \"" +
-         (g->narrow ? "narrow" : "wide") + "\", \"hub_threshold\": " + std::to_string(g->tree_min) +
+         (g->guide ? "guide" : (g->narrow ? "narrow" : "wide")) + "\", \"hub_threshold\": " + std::to_string(g->tree_min) +
          ", \"tree_rows\": " + std::to_string(g->n_tree) + ", \"pool\": " + pool +
          "}, \"alpha\": " + dbl(p.alpha) + ", \"R\": " + std::to_string(p.R) +
          ", \"seed\": " + std::to_string(p.seed) + ", \"topk\": " + std::to_string(p.topk) +

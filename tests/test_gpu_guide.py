@@ -254,3 +254,87 @@ def test_scale24_stitched_sampled(fp):
     stats_equal(out_s, ref.stats)
     assert out.stats_dict()["walks"] == g.n * cfg["R"]
     G.close()
+
+
+def test_batch_capture_and_mixed_layouts(fp):
+    """Guide-table graphs in one batch (plain and stitched, all nodes and a
+    source list): every item equals its plain run and the oracle, captured
+    replays equal the eager run; a batch that mixes guide tables with the
+    tree layouts is refused at creation."""
+    import torch
+
+    say("case: guide layout, batch + capture")
+    specs = [(synth.chung_lu(3000, 30000, 2.1, 255, seed=2101), 0.1, 64, 11, 8, None, False),
+             (synth.chung_lu(500, 4000, 2.5, 255, seed=2102), 0.2, 256, 12, 16, None, True),
+             (synth.chung_lu(8000, 120000, 2.2, 255, seed=2103), 0.15, 64, 13, 32,
+              np.arange(0, 8000, 5, dtype=np.uint32), True)]
+    items = []
+    for g, alpha, R, seed, k, src, stitch in specs:
+        G = fp.Graph(g, layout=fp.FPPR_LAYOUT_GUIDE)
+        if stitch:
+            G.build_pool(S=16, L=3, K=32, alpha=alpha, seed=seed + 100)
+        items.append(dict(csr=g, graph=G, alpha=alpha, R=R, seed=seed, topk=k, sources=src, stitch=stitch))
+    B = fp.Batch(items, rebuild=True)
+    B.run()
+    B.check()
+    torch.cuda.synchronize()
+    want = []
+    for it, ob in zip(items, B.outputs):
+        og = O.Graph.from_csr(it["csr"])
+        pool = O.Pool(og, S=16, L=3, K=32, alpha=it["alpha"], seed=it["seed"] + 100) if it["stitch"] else None
+        ref = O.run(og, it["alpha"], it["R"], it["seed"], sources=it["sources"], topk=it["topk"], pool=pool)
+        assert np.array_equal(u32(ob.counts), ref.counts)
+        assert np.array_equal(u32(ob.topk), ref.topk)
+        assert np.array_equal(u64(ob.digest), ref.digest)
+        want.append((u32(ob.counts).copy(), u64(ob.digest).copy()))
+    stream = torch.cuda.Stream()
+    B.capture(stream)
+    for rep in range(2):
+        for o in B.outputs:
+            o.counts.fill_(-1)
+            o.digest.fill_(-1)
+        torch.cuda.synchronize()
+        B.launch(stream)
+        stream.synchronize()
+        for (c, d), o in zip(want, B.outputs):
+            assert np.array_equal(u32(o.counts), c) and np.array_equal(u64(o.digest), d), rep
+    B.close()
+    Gn = fp.Graph(specs[0][0], layout=fp.FPPR_LAYOUT_NARROW)
+    mixed = [dict(items[0]), dict(items[0], graph=Gn)]
+    with pytest.raises(fp.FpprError):
+        fp.Batch(mixed)
+    Gn.close()
+    for it in items:
+        it["graph"].close()
+
+
+def test_static_entry_and_autotune(fp):
+    """The entry point that allocates nothing gives fppr_run's results on a
+    guide graph; the autotuner (whose hub thresholds mean nothing here)
+    leaves a configuration whose run equals the oracle."""
+    import torch
+
+    say("case: guide layout, static entry + autotune")
+    g = synth.chung_lu(20000, 240000, 2.2, 255, seed=2111)
+    G = fp.Graph(g, layout=fp.FPPR_LAYOUT_GUIDE)
+    p = fp.make_params(0.15, 64, 41, 8, False, True, True, True)
+    out_s = fp.alloc_outputs(g.n, 64, 8, True, True, True)
+    fp.fppr_run_static(G, p, None, g.n, out_s)
+    ref_run = fp.run(G, 0.15, 64, 41, topk=8)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(out_s.counts), u32(ref_run.counts))
+    assert np.array_equal(u64(out_s.digest), u64(ref_run.digest))
+    pools = [dict(S=16, L=2, K=32, seed=31), dict(S=32, L=3, K=64, seed=32)]
+    r = G.autotune(0.15, 64, 41, hub_thresholds=[0], blocks_per_cu=[0, 2], pools=pools, sample=4096, reps=1)
+    stitch = r["pool"] >= 0
+    o = fp.run(G, 0.15, 64, 41, topk=8, stitch=stitch, blocks_per_cu=r["blocks_per_cu"])
+    torch.cuda.synchronize()
+    og = O.Graph.from_csr(g)
+    pool = None
+    if stitch:
+        po = pools[r["pool"]]
+        pool = O.Pool(og, S=po["S"], L=po["L"], K=po["K"], alpha=0.15, seed=po["seed"])
+    ref = O.run(og, 0.15, 64, 41, topk=8, pool=pool)
+    assert np.array_equal(u32(o.counts), ref.counts)
+    assert np.array_equal(u64(o.digest), ref.digest)
+    G.close()
