@@ -71,6 +71,11 @@ void free_graph(fppr_graph* g) {
   dfree(g->gerec);
   dfree(g->gclass);
   dfree(g->gruns);
+  dfree(g->gtiles);
+  dfree(g->gtile_first);
+  dfree(g->gtsum);
+  dfree(g->gtoff);
+  dfree(g->gttot);
   dfree(g->gtab[0]);
   dfree(g->gtab[1]);
   dfree(g->gctl);
@@ -194,6 +199,19 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     if (e == hipSuccess) e = dmalloc(&g->gruns, runs ? runs : 1, acc);
     if (e == hipSuccess) e = launch_guide_runs_fill(g, s);
     g->n_runs = runs;
+    // tiles of the longest rows
+    uint64_t tiles = 0;
+    const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
+    if (e == hipSuccess) e = launch_guide_tiles_count(g, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && nlong) e = hipMemcpy(&tiles, g->d_err + 14, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = dmalloc(&g->gtiles, tiles ? tiles : 1, acc);
+    if (e == hipSuccess) e = dmalloc(&g->gtile_first, nlong ? nlong : 1, acc);
+    if (e == hipSuccess) e = dmalloc(&g->gtsum, tiles ? tiles : 1, acc);
+    if (e == hipSuccess) e = dmalloc(&g->gtoff, tiles ? tiles : 1, acc);
+    if (e == hipSuccess) e = dmalloc(&g->gttot, tiles ? tiles : 1, acc);
+    if (e == hipSuccess) e = launch_guide_tiles_fill(g, s);
+    g->n_tiles = tiles;
     if (e == hipSuccess) e = hipMemcpyAsync(g->scan, bases, g->n * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dfree(bases);

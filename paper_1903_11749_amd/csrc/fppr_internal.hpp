@@ -89,6 +89,12 @@ struct fppr_graph {
   uint64_t gclass_off[10] = {0};           // class c's rows at gclass[gclass_off[c] .. gclass_off[c + 1])
   uint2* gruns = nullptr;                  // [n_runs] (row, first entry) of each run of 16 entries of the longest rows
   uint64_t n_runs = 0;
+  uint2* gtiles = nullptr;                 // [n_tiles] (row, tile) of each 1024-edge tile of the longest rows
+  uint64_t n_tiles = 0;
+  uint64_t* gtile_first = nullptr;         // [rows of that class] first tile of each
+  uint64_t* gtsum = nullptr;               // [n_tiles] weight sum, offset within the row, row total
+  uint64_t* gtoff = nullptr;
+  uint64_t* gttot = nullptr;
   fppr::guide::Pending* gtab[2] = {nullptr, nullptr};  // child tables of alternate levels, g_tcap each
   fppr::GuideCtl* gctl = nullptr;
   uint64_t g_entries1 = 0, g_cap = 0;
@@ -135,6 +141,9 @@ hipError_t launch_guide_sizes(fppr_graph* g, hipStream_t s);
 hipError_t launch_guide_class(fppr_graph* g, uint32_t c, uint64_t at, hipStream_t s);
 // entry runs of the longest rows: counts and scan (total at d_err[14..15]), then the list
 hipError_t launch_guide_runs_count(fppr_graph* g, hipStream_t s);
+// 1024-edge tiles of the longest rows: counts and scan (total at d_err[14..15]), then the list
+hipError_t launch_guide_tiles_count(fppr_graph* g, hipStream_t s);
+hipError_t launch_guide_tiles_fill(fppr_graph* g, hipStream_t s);
 hipError_t launch_guide_runs_fill(fppr_graph* g, hipStream_t s);
 // heads (bases from g->scan when `bases`, else kept), row tables and the
 // first child level's list; children deeper than `levels` are refused

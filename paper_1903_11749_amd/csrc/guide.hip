@@ -329,47 +329,86 @@ __global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restri
   alloc.flush();
 }
 
-// Long rows (more than kMidMax edges): one block per row for the row's
-// total, then its prefixes, thresholds and edge records in tiles of
-// kThreads * 4 edges. Their entries come after, from k_guide_runs.
-__global__ void __launch_bounds__(kThreads) k_guide_long(const uint32_t* __restrict__ rows, uint64_t count,
-                                                         const uint64_t* __restrict__ off,
-                                                         const uint32_t* __restrict__ col,
-                                                         const uint32_t* __restrict__ w,
-                                                         const Head* __restrict__ head, uint32_t n, uint64_t* T,
-                                                         uint4* erec) {
+// Long rows (more than kMidMax edges) are cut into tiles of kTile edges
+// (listed at creation: (row, tile)), so that a hub's thresholds spread over
+// many blocks: the tiles' weight sums, then each row's running offsets and
+// total over its tiles, then each tile's prefixes, thresholds and edge
+// records. Their entries come after, from k_guide_runs.
+constexpr uint32_t kTile = kThreads * 4;
+__device__ __forceinline__ void tile_span(const uint64_t* __restrict__ off, uint2 rt, uint64_t* a, uint64_t* d,
+                                          uint64_t* j0, uint64_t* len) {
+  *a = off[rt.x];
+  *d = off[rt.x + 1] - *a;
+  *j0 = static_cast<uint64_t>(rt.y) * kTile;
+  *len = *d - *j0 < kTile ? *d - *j0 : kTile;
+}
+
+__global__ void __launch_bounds__(kThreads) k_tile_sums(const uint2* __restrict__ tiles, uint64_t count,
+                                                        const uint64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ w, uint64_t* __restrict__ tsum) {
   __shared__ uint64_t lds[kThreads / 64];
-  for (uint64_t r = blockIdx.x; r < count; r += gridDim.x) {
-    const uint32_t u = rows[r];
-    const uint64_t a = off[u];
-    const uint64_t d = off[u + 1] - a;
+  for (uint64_t q = blockIdx.x; q < count; q += gridDim.x) {  // block-uniform
+    uint64_t a, d, j0, len;
+    tile_span(off, tiles[q], &a, &d, &j0, &len);
     uint64_t part = 0;
-    for (uint64_t j = threadIdx.x; j < d; j += kThreads) part += w[a + j];
-    uint64_t W = 0;
-    block_exclusive_scan_u64<kThreads>(part, lds, &W);
-    uint64_t carry = 0;
-    for (uint64_t t0 = 0; t0 < d; t0 += kThreads * 4) {
-      const uint64_t j0 = t0 + threadIdx.x * 4ull;
-      uint64_t v[4];
-      uint64_t local = 0;
+    for (uint64_t j = threadIdx.x; j < len; j += kThreads) part += w[a + j0 + j];
+    uint64_t total = 0;
+    block_exclusive_scan_u64<kThreads>(part, lds, &total);
+    if (threadIdx.x == 0) tsum[q] = total;
+  }
+}
+
+// one thread per long row: its tiles' offsets within the row, and the total
+__global__ void k_tile_offsets(const uint32_t* __restrict__ rows, uint64_t count, const uint64_t* __restrict__ off,
+                               const uint64_t* __restrict__ first, const uint64_t* __restrict__ tsum,
+                               uint64_t* __restrict__ toff, uint64_t* __restrict__ ttot) {
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < count;
+       r += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t u = rows[r];
+    const uint64_t d = off[u + 1] - off[u];
+    const uint64_t n = (d + kTile - 1) / kTile, f = first[r];
+    uint64_t acc = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+      toff[f + k] = acc;
+      acc += tsum[f + k];
+    }
+    for (uint64_t k = 0; k < n; ++k) ttot[f + k] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_tile_thresholds(const uint2* __restrict__ tiles, uint64_t count,
+                                                              const uint64_t* __restrict__ off,
+                                                              const uint32_t* __restrict__ col,
+                                                              const uint32_t* __restrict__ w,
+                                                              const Head* __restrict__ head, uint32_t n,
+                                                              const uint64_t* __restrict__ toff,
+                                                              const uint64_t* __restrict__ ttot, uint64_t* T,
+                                                              uint4* erec) {
+  __shared__ uint64_t lds[kThreads / 64];
+  for (uint64_t q = blockIdx.x; q < count; q += gridDim.x) {  // block-uniform
+    const uint2 rt = tiles[q];
+    uint64_t a, d, j0, len;
+    tile_span(off, rt, &a, &d, &j0, &len);
+    const uint64_t W = ttot[q];
+    const uint64_t base = j0 + threadIdx.x * 4ull;
+    uint64_t v[4];
+    uint64_t local = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint64_t j = j0 + k;
-        local += j < d ? w[a + j] : 0u;
-        v[k] = local;
-      }
-      uint64_t total;
-      const uint64_t excl = block_exclusive_scan_u64<kThreads>(local, lds, &total);
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t j = base + k;
+      local += j < j0 + len ? w[a + j] : 0u;
+      v[k] = local;
+    }
+    uint64_t total;
+    const uint64_t excl = block_exclusive_scan_u64<kThreads>(local, lds, &total);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint64_t j = j0 + k;
-        if (j < d) {
-          const uint64_t P = carry + excl + v[k];
-          T[a + j] = j + 1 < d && P < W ? guide::threshold(P, W) : ~0ull;
-          erec[a + j] = edge_record(head, n, col[a + j], u);
-        }
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t j = base + k;
+      if (j < j0 + len) {
+        const uint64_t P = toff[q] + excl + v[k];
+        T[a + j] = j + 1 < d && P < W ? guide::threshold(P, W) : ~0ull;
+        erec[a + j] = edge_record(head, n, col[a + j], rt.x);
       }
-      carry += total;
     }
   }
 }
@@ -424,6 +463,25 @@ __global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict
     }
   }
   alloc.flush();
+}
+
+// tiles of each long row, and their list (each row's tiles together; the
+// first tile of row r at first[r])
+__global__ void k_tile_counts(const uint32_t* __restrict__ rows, uint64_t count, const uint64_t* __restrict__ off,
+                              uint32_t* __restrict__ flag) {
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < count;
+       r += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t u = rows[r];
+    flag[r] = static_cast<uint32_t>((off[u + 1] - off[u] + kTile - 1) / kTile);
+  }
+}
+__global__ void k_tile_fill(const uint32_t* __restrict__ rows, uint64_t count, const uint32_t* __restrict__ flag,
+                            const uint64_t* __restrict__ scan, uint2* __restrict__ tiles, uint64_t* __restrict__ first) {
+  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; r < count;
+       r += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    first[r] = scan[r];
+    for (uint32_t i = 0; i < flag[r]; ++i) tiles[scan[r] + i] = make_uint2(rows[r], i);
+  }
 }
 
 // runs of each long row (2^kb / kRun: kb >= 10 there)
@@ -636,6 +694,22 @@ hipError_t launch_guide_runs_count(fppr_graph* g, hipStream_t s) {
   return launch_scan_u32(g->flag, g->scan, nlong, g->scan_blocks, reinterpret_cast<uint64_t*>(g->d_err + 14), s);
 }
 
+hipError_t launch_guide_tiles_count(fppr_graph* g, hipStream_t s) {
+  const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
+  if (!nlong) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_counts, dim3(grid_for(nlong)), dim3(kThreads), 0, s, g->gclass + g->gclass_off[8], nlong,
+                     g->off, g->flag);
+  return launch_scan_u32(g->flag, g->scan, nlong, g->scan_blocks, reinterpret_cast<uint64_t*>(g->d_err + 14), s);
+}
+
+hipError_t launch_guide_tiles_fill(fppr_graph* g, hipStream_t s) {
+  const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
+  if (!nlong) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_fill, dim3(grid_for(nlong)), dim3(kThreads), 0, s, g->gclass + g->gclass_off[8], nlong,
+                     g->flag, g->scan, g->gtiles, g->gtile_first);
+  return hipGetLastError();
+}
+
 hipError_t launch_guide_runs_fill(fppr_graph* g, hipStream_t s) {
   const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
   if (!nlong) return hipSuccess;
@@ -696,8 +770,12 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                        g->gent, p);
   const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
   if (nlong) {
-    hipLaunchKernelGGL(k_guide_long, dim3(static_cast<uint32_t>(nlong < 2048 ? nlong : 2048)), dim3(kThreads), 0, s,
-                       g->gclass + g->gclass_off[8], nlong, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec);
+    const uint32_t tb = static_cast<uint32_t>(std::min<uint64_t>(g->n_tiles, 8192));
+    hipLaunchKernelGGL(k_tile_sums, dim3(tb), dim3(kThreads), 0, s, g->gtiles, g->n_tiles, g->off, g->w, g->gtsum);
+    hipLaunchKernelGGL(k_tile_offsets, dim3(grid_for(nlong)), dim3(kThreads), 0, s, g->gclass + g->gclass_off[8],
+                       nlong, g->off, g->gtile_first, g->gtsum, g->gtoff, g->gttot);
+    hipLaunchKernelGGL(k_tile_thresholds, dim3(tb), dim3(kThreads), 0, s, g->gtiles, g->n_tiles, g->off, g->col,
+                       g->w, g->ghead, g->n, g->gtoff, g->gttot, g->gT, g->gerec);
     hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs), 2048u)), dim3(kThreads), 0, s,
                        g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
   }
