@@ -218,9 +218,12 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "row classes");
   }
   const uint64_t kMaxCap = (1ull << 32) - 1;  // entry indices are 32-bit
-  // child tables take about as many entries again as the row tables on the
-  // skewed weights measured (1.3x at R-MAT scale 24), plus the wave chunks
-  uint64_t cap = std::min(kMaxCap, e1 * 3 + (1u << 20));
+  // The first pass has room for the row tables only: the child tables'
+  // entries are counted, not written, and the second pass allocates what
+  // was counted plus an eighth for rebuilds whose weights crowd more
+  // (child tables took 1.5x the row tables' entries at R-MAT scale 24).
+  // Graphs with no crowded entries are done in one pass.
+  uint64_t cap = std::min(kMaxCap, e1 + (1u << 20));
   uint64_t tcap = e1 / 4 + (1u << 16);  // 0.19 tables per row-table entry at scale 24
   for (int attempt = 0;; ++attempt) {
     if (attempt == 6) return invalid("guide tables did not fit after several attempts");
@@ -258,9 +261,10 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     dfree(g->gtab[0]);
     dfree(g->gtab[1]);
     if (cap == kMaxCap && h.next_entry > cap) return invalid("layout GUIDE needs fewer than 2^32 table entries");
-    // the counters ran on past the room: they give what this build needs
-    // (all of it when the lists did not overflow; then the entries are
-    // exact, and only the lists grow otherwise)
+    // the counters ran on past the room: every table that was asked for is
+    // counted, though the children of those that did not fit are not (a
+    // lower bound, so a deep graph may take another pass); lists that ran
+    // out grow as well
     if (most > tcap) {
       tcap = std::max(tcap * 2, most + most / 4);
       cap = std::min(kMaxCap, std::max<uint64_t>(cap, h.next_entry + h.next_entry / 4));
