@@ -413,18 +413,33 @@ __global__ void __launch_bounds__(kThreads) k_tile_thresholds(const uint2* __res
   }
 }
 
-// Entries of the long rows: one thread per run of kRun consecutive entries
-// of one row (runs listed at creation: (row, first entry)), the first run
-// entry's candidates by binary search over the row's thresholds, the rest by
-// merging.
+// Entries of the long rows: a group of kRun lanes per run of kRun
+// consecutive entries of one row (runs listed at creation: (row, first
+// entry)), lane k filling entry k, so that a group writes its run's entries
+// as one contiguous stretch. Each lane finds its bucket's first candidate by
+// binary search over the row's thresholds (the lanes of a group search
+// neighbouring draws, so they share the lines read) and its last by a
+// doubling search from there (a bucket of a long row holds few candidates,
+// except where light edges crowd).
 constexpr uint32_t kRun = 16;
+template <typename Th>
+__device__ __forceinline__ uint32_t containing_from(const Th& T, uint32_t a, uint32_t last, uint64_t x) {
+  uint32_t lo = a, hi = a, step = 1;
+  while (hi < last && T(hi) <= x) {  // every index below hi + 1 is at most x
+    lo = hi + 1;
+    hi = last - lo > step ? lo + step : last;
+    step <<= 1;
+  }
+  return guide::containing(T, lo, hi, x);
+}
 __global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict__ runs, uint64_t count,
                                                          const uint64_t* __restrict__ off, const Head* __restrict__ head,
                                                          const uint64_t* __restrict__ T, const uint4* __restrict__ erec,
                                                          Entry* __restrict__ ent, Alloc alloc) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t q = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; __ballot(q < count) != 0;
-       q += stride) {  // wave-uniform loop
+  const uint32_t gi = __lane_id() & (kRun - 1);
+  const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * kThreads) / kRun;
+  for (uint64_t q = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) / kRun; __ballot(q < count) != 0;
+       q += groups) {  // wave-uniform loop
     bool act = q < count;
     const uint2 rb = act ? runs[q] : make_uint2(0, 0);
     const uint32_t u = rb.x;
@@ -435,32 +450,24 @@ __global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict
     const uint32_t last = d - 1;
     const Thr th{T + a};
     const ERec rec{erec + a};
-    Entry* row_ent = ent + (act ? head[u].base : 0u);
-    uint32_t c = 0;
-    for (uint32_t k = 0; k < kRun; ++k) {  // wave-uniform
-      const uint32_t b = rb.y + k;
-      uint32_t c0 = 0, c1 = 0;
-      uint64_t t0 = 0, t1 = 0;
-      Cand L{}, M{}, R{};
-      if (act) {
-        uint64_t blo, bhi;
-        guide::row_bucket(kb, b, &blo, &bhi);
-        if (k == 0) c = guide::containing(th, 0u, last, blo);
-        while (c < last && th(c) <= blo) ++c;
-        c0 = c;
-        c1 = c0;
-        while (c1 < last && th(c1) <= bhi) ++c1;
-        if (c1 > c0) {
-          t0 = th(c0);
-          t1 = th(c1 - 1);
-        }
-        L = rec(c0);
-        R = rec(c1);
-        M = c1 > c0 + 1 ? rec(c0 + 1) : L;
-        c = c1;
+    const uint32_t b = rb.y + gi;  // < 2^kb: runs tile the table (2^kb >= 1024 here)
+    uint32_t c0 = 0, c1 = 0;
+    uint64_t t0 = 0, t1 = 0;
+    Cand L{}, M{}, R{};
+    if (act) {
+      uint64_t blo, bhi;
+      guide::row_bucket(kb, b, &blo, &bhi);
+      c0 = guide::containing(th, 0u, last, blo);
+      c1 = containing_from(th, c0, last, bhi);
+      if (c1 > c0) {
+        t0 = th(c0);
+        t1 = th(c1 - 1);
       }
-      write_entry(alloc, act, row_ent + (act ? b : 0u), c0, c1, t0, t1, L, M, R, a, u);
+      L = rec(c0);
+      R = rec(c1);
+      M = c1 > c0 + 1 ? rec(c0 + 1) : L;
     }
+    write_entry(alloc, act, ent + (act ? head[u].base + b : 0u), c0, c1, t0, t1, L, M, R, a, u);
   }
   alloc.flush();
 }
@@ -517,15 +524,33 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
   if (count > alloc.tcap) count = alloc.tcap;
   const uint32_t gi = __lane_id() & (GL - 1);
   const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * kThreads) / GL;
-  for (uint64_t t = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) / GL; __ballot(t < count) != 0;
-       t += groups) {  // wave-uniform loop
-    Pending p{};
-    if (t < count) p = in[t];  // tables that found no room have no buckets
+  if (count == 0) return;
+  // The group's next table is loaded one iteration ahead. Every load of an
+  // iteration is issued on every path (inactive lanes read index 0 and drop
+  // the value), so the wait for this table's values below leaves the
+  // prefetch in flight.
+  uint64_t t = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) / GL;
+  Pending pn = in[t < count ? t : 0];
+  bool pn_ok = t < count;
+  __builtin_amdgcn_s_waitcnt(0);
+  for (; __ballot(t < count) != 0; t += groups) {  // wave-uniform loop
+    const Pending p = pn_ok ? pn : Pending{};  // tables that found no room have no buckets
     const uint32_t nthr = p.b - p.a;  // thresholds between the candidates
     // small tables: lane j holds threshold a + j and the record of candidate a + j
     const bool small = nthr < GL;
-    const uint64_t Tv = gi < nthr && small ? T[p.off + p.a + gi] : ~0ull;
-    const uint4 Rv = gi <= nthr && small ? erec[p.off + p.a + gi] : make_uint4(0, 0, 0, 0);
+    const bool tv_ok = gi < nthr && small, rv_ok = gi <= nthr && small;
+    const uint64_t Tl = T[tv_ok ? p.off + p.a + gi : 0];
+    const uint4 Rl = erec[rv_ok ? p.off + p.a + gi : 0];
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch behind these loads
+    const uint64_t tn = t + groups;
+    pn = in[tn < count ? tn : 0];
+    pn_ok = tn < count;
+    __builtin_amdgcn_sched_barrier(0);
+    // this table's loads complete (vmcnt <= 4: the prefetch's loads may
+    // still be in flight; the compiler adds whatever more a use needs)
+    __builtin_amdgcn_s_waitcnt(0xF74);
+    const uint64_t Tv = tv_ok ? Tl : ~0ull;
+    const uint4 Rv = rv_ok ? Rl : make_uint4(0, 0, 0, 0);
     uint32_t most = (p.nbk + GL - 1) / GL;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -534,7 +559,11 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
     }
     const Thr th{T + p.off};
     const ERec rec{erec + p.off};
-    for (uint32_t k = 0; k < most; ++k) {  // wave-uniform
+    // at least one pass (with no active lane when the wave has no buckets),
+    // so that this table's loads are used on every path and stay ahead of
+    // the prefetch
+    uint32_t k = 0;
+    do {  // wave-uniform
       const uint32_t i = k * GL + gi;
       const bool act = i < p.nbk;
       uint64_t blo = 0, bhi = 0;
@@ -583,7 +612,7 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
         }
       }
       write_entry(alloc, act, ent + (act ? p.base + i : 0u), c0, c1, t0, t1, L, M, R, p.off, p.row);
-    }
+    } while (++k < most);
   }
   alloc.flush();
 }
@@ -776,7 +805,7 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                        nlong, g->off, g->gtile_first, g->gtsum, g->gtoff, g->gttot);
     hipLaunchKernelGGL(k_tile_thresholds, dim3(tb), dim3(kThreads), 0, s, g->gtiles, g->n_tiles, g->off, g->col,
                        g->w, g->ghead, g->n, g->gtoff, g->gttot, g->gT, g->gerec);
-    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs), 2048u)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs * kRun), 2048u)), dim3(kThreads), 0, s,
                        g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
   }
   return hipGetLastError();
