@@ -264,12 +264,25 @@ __device__ __forceinline__ void group_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Rows of 65 to kMidMax edges: one wave per row. The row's total, then its
-// prefixes, thresholds and edge records 64 edges at a time (thresholds also
-// staged in the wave's LDS), then its 64 to 512 entries, each lane taking a
-// run of consecutive ones: the first by binary search over the staged
-// thresholds, the rest by merging.
-__global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restrict__ rows, uint64_t count,
+// First candidate at or after a whose threshold is above x, by doubling
+// steps from a and then binary search (the answer is usually near a).
+template <typename Th>
+__device__ __forceinline__ uint32_t containing_from(const Th& T, uint32_t a, uint32_t last, uint64_t x) {
+  uint32_t lo = a, hi = a, step = 1;
+  while (hi < last && T(hi) <= x) {  // every index below hi + 1 is at most x
+    lo = hi + 1;
+    hi = last - lo > step ? lo + step : last;
+    step <<= 1;
+  }
+  return guide::containing(T, lo, hi, x);
+}
+// Rows of 65 to kMidMax edges: one wave per row. The row's total and its
+// edge records (several edges' loads in flight per lane), then its
+// prefixes and thresholds 64 edges at a time (the thresholds also staged in
+// the wave's LDS), then its 64 to 512 entries, lane k taking entries k,
+// k + 64, ... so that the wave's writes are contiguous: candidates by binary
+// search over the staged thresholds and a doubling search from there.
+__global__ void __launch_bounds__(kThreads, 5) k_guide_mid(const uint32_t* __restrict__ rows, uint64_t count,
                                                         const uint64_t* __restrict__ off,
                                                         const uint32_t* __restrict__ col,
                                                         const uint32_t* __restrict__ w, const Head* __restrict__ head,
@@ -284,7 +297,11 @@ __global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restri
     const uint64_t a = off[u];
     const uint32_t d = static_cast<uint32_t>(off[u + 1] - a);  // 65 .. kMidMax
     uint64_t part = 0;
-    for (uint32_t j = lane; j < d; j += 64) part += w[a + j];
+#pragma unroll 4
+    for (uint32_t j = lane; j < d; j += 64) {
+      part += w[a + j];
+      erec[a + j] = edge_record(head, n, col[a + j], u);
+    }
     const uint64_t W = wave_sum_u64(part);
     uint64_t carry = 0;
     for (uint32_t j0 = 0; j0 < d; j0 += 64) {
@@ -297,7 +314,6 @@ __global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restri
         const uint64_t t = j + 1 < d && P < W ? guide::threshold(P, W) : ~0ull;
         T[a + j] = t;
         st[j] = t;
-        erec[a + j] = edge_record(head, n, col[a + j], u);
       }
     }
     group_sync();  // the staged thresholds and the row's records, visible to the wave
@@ -306,21 +322,15 @@ __global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restri
       const ERec rec{erec + a};
       Entry* row_ent = ent + head[u].base;
       const uint32_t kb = guide::table_bits(guide::ceil_log2(d));
-      const uint32_t last = d - 1, nb = 1u << kb, run = nb >> 6;  // nb = 64 .. 512
-      uint32_t c = 0;
-      for (uint32_t k = 0; k < run; ++k) {
-        const uint32_t b = lane * run + k;
+      const uint32_t last = d - 1, nb = 1u << kb;  // nb = 64 .. 512
+      for (uint32_t b = lane; b < nb; b += 64) {  // wave-uniform: nb is a multiple of 64
         uint64_t blo, bhi;
         guide::row_bucket(kb, b, &blo, &bhi);
-        if (k == 0) c = guide::containing(th, 0u, last, blo);
-        while (c < last && th(c) <= blo) ++c;
-        const uint32_t c0 = c;
-        uint32_t c1 = c0;
-        while (c1 < last && th(c1) <= bhi) ++c1;
+        const uint32_t c0 = guide::containing(th, 0u, last, blo);
+        const uint32_t c1 = containing_from(th, c0, last, bhi);
         const uint64_t t0 = c1 > c0 ? th(c0) : 0, t1 = c1 > c0 ? th(c1 - 1) : 0;
         const Cand L = rec(c0), R = rec(c1);
         const Cand M = c1 > c0 + 1 ? rec(c0 + 1) : L;
-        c = c1;
         write_entry(alloc, true, row_ent + b, c0, c1, t0, t1, L, M, R, a, u);
       }
     }
@@ -422,16 +432,6 @@ __global__ void __launch_bounds__(kThreads) k_tile_thresholds(const uint2* __res
 // doubling search from there (a bucket of a long row holds few candidates,
 // except where light edges crowd).
 constexpr uint32_t kRun = 16;
-template <typename Th>
-__device__ __forceinline__ uint32_t containing_from(const Th& T, uint32_t a, uint32_t last, uint64_t x) {
-  uint32_t lo = a, hi = a, step = 1;
-  while (hi < last && T(hi) <= x) {  // every index below hi + 1 is at most x
-    lo = hi + 1;
-    hi = last - lo > step ? lo + step : last;
-    step <<= 1;
-  }
-  return guide::containing(T, lo, hi, x);
-}
 __global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict__ runs, uint64_t count,
                                                          const uint64_t* __restrict__ off, const Head* __restrict__ head,
                                                          const uint64_t* __restrict__ T, const uint4* __restrict__ erec,
