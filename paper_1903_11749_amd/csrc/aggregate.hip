@@ -321,7 +321,13 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
         const uint32_t idx = e * 64 + lane;
         kv[e] = idx < nd ? run_key[wv][idx] : 0xFFFFFFFFu;
       }
-      wave_bitonic<E>(kv);
+      if (E > 1 && nd <= 64) {  // wave-uniform: every key in the first register, the rest padding
+        uint32_t k1[1] = {kv[0]};
+        wave_bitonic<1>(k1);
+        kv[0] = k1[0];
+      } else {
+        wave_bitonic<E>(kv);
+      }
 #pragma unroll
       for (uint32_t e = 0; e < E; ++e) {
         const uint32_t q = e * 64 + lane;
