@@ -173,6 +173,45 @@ def test_borrowed_csr_rebuild(fp):
     G.close()
 
 
+def test_rebuild_beyond_room_fails_check(fp):
+    """A graph created with equal weights has no child tables, so it gets
+    room for its row tables plus the slack; new weights that crowd every
+    row (one giant edge among 63 light ones: a child table of about 64
+    entries per row, 4M in all) need more. The rebuild's check reports it
+    (recreate the graph), and a graph created from the new weights gives the
+    oracle's results."""
+    import torch
+
+    n, deg = 1 << 16, 64
+    rng = np.random.default_rng(2101)
+    src = np.repeat(np.arange(n, dtype=np.uint32), deg)
+    dst = rng.integers(0, n, src.size).astype(np.uint32)
+    g = synth.csr_from_edges(n, src, dst, np.ones(src.size, np.uint32))
+    say(f"case: guide layout, rebuild beyond the created room, m {g.m}")
+    ro = torch.from_numpy(g.row_offsets.view(np.int64)).cuda()
+    col = torch.from_numpy(g.col.view(np.int32)).cuda()
+    w = torch.from_numpy(g.w.view(np.int32)).cuda()
+    G = fp.Graph(n=g.n, row_offsets=ro, col=col, w=w, layout=fp.FPPR_LAYOUT_GUIDE)
+    G.check()
+    w2 = np.ones(g.m, np.uint32)
+    w2[g.row_offsets[:-1].astype(np.int64)] = 1 << 31  # the first edge of every row
+    w.copy_(torch.from_numpy(w2.view(np.int32)).cuda())
+    G.rebuild()
+    with pytest.raises(fp.FpprError) as ei:
+        G.check()
+    assert "recreate" in str(ei.value)
+    torch.cuda.synchronize()
+    G.close()
+    g2 = synth.CSRGraph(g.n, g.row_offsets, g.col, w2)
+    G2 = fp.Graph(g2, layout=fp.FPPR_LAYOUT_GUIDE)
+    sample = np.sort(rng.choice(n, 96, replace=False)).astype(np.uint32)
+    out = fp.run(G2, 0.15, 40, 12, topk=8, sources=sample, stats=True)
+    ref = O.run(O.Graph.from_csr(g2), 0.15, 40, 12, topk=8, sources=sample)
+    compare(out, ref, 8)
+    stats_equal(out, ref.stats)
+    G2.close()
+
+
 def test_source_lists_and_lane_keys(fp):
     """A source list with duplicates and nodes of every class, then a server
     (many descriptors on one graph: the per-lane-key form) whose every query
