@@ -224,14 +224,17 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
   // (child tables took 1.5x the row tables' entries at R-MAT scale 24).
   // Graphs with no crowded entries are done in one pass.
   uint64_t cap = std::min(kMaxCap, e1 + (1u << 20));
-  uint64_t tcap = e1 / 4 + (1u << 16);  // 0.19 tables per row-table entry at scale 24
+  // 0.19 child tables per row-table entry at scale 24, about one in seven
+  // of them large
+  uint64_t tcap = e1 / 4 + (1u << 16), tcap_big = e1 / 16 + (1u << 16);
   for (int attempt = 0;; ++attempt) {
     if (attempt == 6) return invalid("guide tables did not fit after several attempts");
     if ((e = dmalloc(&g->gent, cap, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide entries)");
-    if ((e = dmalloc(&g->gtab[0], tcap, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide tables)");
-    if ((e = dmalloc(&g->gtab[1], tcap, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide tables)");
+    if ((e = dmalloc(&g->gtab[0], tcap + tcap_big, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide tables)");
+    if ((e = dmalloc(&g->gtab[1], tcap + tcap_big, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide tables)");
     g->g_cap = cap;
     g->g_tcap = static_cast<uint32_t>(tcap);
+    g->g_tcap_big = static_cast<uint32_t>(tcap_big);
     if ((e = zero_ctl(g, s)) != hipSuccess) return hip_fail(e, "zero control words");
     if ((e = launch_guide_build(g, true, kGuideLevels, s)) != hipSuccess) return hip_fail(e, "guide tables");
     uint32_t depth = 1;
@@ -239,7 +242,8 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     for (uint32_t l = 2; l <= kGuideLevels; ++l) {
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "sync");
       if ((e = hipMemcpy(&h, g->gctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read");
-      if (h.tables[l] == 0 || h.tables[l] > tcap || h.next_entry > cap) break;
+      if ((h.tables[l] == 0 && h.big[l] == 0) || h.tables[l] > tcap || h.big[l] > tcap_big || h.next_entry > cap)
+        break;
       if ((e = launch_guide_level(g, l, kGuideLevels, s)) != hipSuccess) return hip_fail(e, "guide level");
       depth = l;
     }
@@ -247,16 +251,20 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     if ((e = hipMemcpy(&h, g->gctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read");
     uint32_t err = 0;
     if ((e = hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read");
-    uint64_t most = 0;
-    for (uint32_t l = 0; l < kGuideLevels + 2; ++l) most = std::max<uint64_t>(most, h.tables[l]);
-    const bool full = h.next_entry > cap || most > tcap;
+    uint64_t most = 0, most_big = 0;
+    for (uint32_t l = 0; l < kGuideLevels + 2; ++l) {
+      most = std::max<uint64_t>(most, h.tables[l]);
+      most_big = std::max<uint64_t>(most_big, h.big[l]);
+    }
+    const bool lists_full = most > tcap || most_big > tcap_big;
+    const bool full = h.next_entry > cap || lists_full;
     if (!full) {
       if (err & kErrGuide) return invalid("guide tables need more than 64 levels");
       if (err) return invalid("graph build failed:" + err_bits(err));
       g->g_levels = depth;
       return FPPR_OK;
     }
-    g->device_bytes -= align_up(cap * sizeof(Entry)) + 2 * align_up(tcap * sizeof(Pending));
+    g->device_bytes -= align_up(cap * sizeof(Entry)) + 2 * align_up((tcap + tcap_big) * sizeof(Pending));
     dfree(g->gent);
     dfree(g->gtab[0]);
     dfree(g->gtab[1]);
@@ -265,8 +273,10 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
     // counted, though the children of those that did not fit are not (a
     // lower bound, so a deep graph may take another pass); lists that ran
     // out grow as well
-    if (most > tcap) {
-      tcap = std::max(tcap * 2, most + most / 4);
+    if (lists_full) {
+      if (most > tcap) tcap = std::max(tcap * 2, most + most / 4);
+      if (most_big > tcap_big) tcap_big = std::max(tcap_big * 2, most_big + most_big / 4);
+      if (tcap + tcap_big >= (1ull << 32)) return invalid("layout GUIDE needs fewer than 2^32 child tables per level");
       cap = std::min(kMaxCap, std::max<uint64_t>(cap, h.next_entry + h.next_entry / 4));
     } else {
       cap = std::min<uint64_t>(kMaxCap, h.next_entry + h.next_entry / 8 + (1u << 20));

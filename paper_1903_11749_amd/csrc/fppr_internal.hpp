@@ -31,7 +31,8 @@ constexpr uint32_t kGuideLevels = 64;
 struct GuideCtl {
   unsigned long long next_entry;       // first free entry
   uint32_t pad[30];                    // the two counters in lines of their own
-  uint32_t tables[kGuideLevels + 2];   // child-table slots taken per level
+  uint32_t tables[kGuideLevels + 2];   // small child-table slots taken per level
+  uint32_t big[kGuideLevels + 2];      // large child-table slots taken per level
 };
 
 }  // namespace fppr
@@ -95,10 +96,11 @@ struct fppr_graph {
   uint64_t* gtsum = nullptr;               // [n_tiles] weight sum, offset within the row, row total
   uint64_t* gtoff = nullptr;
   uint64_t* gttot = nullptr;
-  fppr::guide::Pending* gtab[2] = {nullptr, nullptr};  // child tables of alternate levels, g_tcap each
+  // child tables of alternate levels: g_tcap small ones, then g_tcap_big large ones
+  fppr::guide::Pending* gtab[2] = {nullptr, nullptr};
   fppr::GuideCtl* gctl = nullptr;
   uint64_t g_entries1 = 0, g_cap = 0;
-  uint32_t g_tcap = 0, g_levels = 1;       // deepest level of the last full build
+  uint32_t g_tcap = 0, g_tcap_big = 0, g_levels = 1;       // deepest level of the last full build
   uint64_t pool_cap = 0;             // u64 words allocated
   uint32_t* small_nodes = nullptr;   // [n] rank -> node
   uint64_t device_bytes = 0;

@@ -55,24 +55,35 @@ __device__ __forceinline__ uint4 edge_record(const Head* __restrict__ head, uint
 
 // Child-table allocation for a whole wave, called by every lane in
 // wave-uniform control flow: each lane with `need` gets a slot in the next
-// level's list and nbk entries. A wave takes entries and slots from the
-// shared counters in chunks (kEntChunk, kTabChunk) and hands them out from
-// its registers, so the counters see one atomic per chunk; the unused rest
-// of an entry chunk is never referenced, and unused slots are left with no
-// buckets (flush(), at the wave's end). Returns the child's first entry, or
-// ~0u (and the graph's failure bit) when the list or the entries are full or
-// the level limit is reached.
+// level's list and nbk entries. Tables with fewer than kLargeThr thresholds
+// between their candidates go to the small list (out[0, tcap)), the others
+// to the large list (out[tcap, tcap + tcap_big)), so that a level pass can
+// give each list a lane group of its size. A wave takes entries and slots
+// from the shared counters in chunks (kEntChunk, kTabChunk) and hands them
+// out from its registers, so the counters see one atomic per chunk; the
+// unused rest of an entry chunk is never referenced, and unused slots are
+// left with no buckets (flush(), at the wave's end). Returns the child's
+// first entry, or ~0u (and the graph's failure bit) when its list or the
+// entries are full or the level limit is reached.
 constexpr uint64_t kEntChunk = 1024;
 constexpr uint32_t kTabChunk = 128;
+constexpr uint32_t kLargeThr = 8;
+// lane 0's value as a wave-uniform (scalar) one; every lane is active here
+__device__ __forceinline__ uint64_t first_lane_u64(unsigned long long x) {
+  return static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x)))) |
+         (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32))))
+          << 32);
+}
 struct Alloc {
   GuideCtl* ctl;
   Pending* out;
   uint64_t cap;
-  uint32_t tcap, next_level, max_level;
+  uint32_t tcap, tcap_big, next_level, max_level;
   uint32_t* err;
   // the wave's chunks (wave-uniform)
   uint64_t e_next = 0, e_end = 0;
-  uint64_t t_next = 0, t_end = 0;
+  uint64_t t_next = 0, t_end = 0;  // small list
+  uint64_t b_next = 0, b_end = 0;  // large list
 
   __device__ uint32_t operator()(bool need, uint64_t lo, uint64_t hi, uint32_t first, uint32_t last, uint32_t nbk,
                                  uint32_t sh, uint64_t off, uint32_t row) {
@@ -80,8 +91,7 @@ struct Alloc {
     if (mask == 0) return ~0u;
     const uint64_t v = need ? nbk : 0u;
     const uint64_t inc = wave_inclusive_scan_u64(v);
-    const uint64_t total = __shfl(static_cast<unsigned long long>(inc), 63, 64);
-    const uint32_t cnt = static_cast<uint32_t>(__popcll(mask));
+    const uint64_t total = first_lane_u64(__shfl(static_cast<unsigned long long>(inc), 63, 64));
     const bool open = next_level <= max_level;
     if (!open) {
       if (need) atomicOr(err, kErrGuide);
@@ -91,32 +101,55 @@ struct Alloc {
       const uint64_t take = total > kEntChunk ? total : kEntChunk;
       unsigned long long b = 0;
       if (__lane_id() == 0) b = atomicAdd(&ctl->next_entry, static_cast<unsigned long long>(take));
-      e_next = __shfl(b, 0, 64);
-      e_end = e_next + take;
+      e_next = first_lane_u64(b);
+      e_end = e_next + first_lane_u64(take);
     }
-    if (t_next + cnt > t_end) {
-      flush();
+    const bool large = need && last - first >= kLargeThr;
+    const uint64_t ml = __ballot(large), ms = mask & ~ml;
+    const uint32_t cs = static_cast<uint32_t>(__popcll(ms)), cl = static_cast<uint32_t>(__popcll(ml));
+    if (t_next + cs > t_end) {
+      flush_small();
       unsigned long long b = 0;
       if (__lane_id() == 0) b = atomicAdd(&ctl->tables[next_level], kTabChunk);
-      t_next = __shfl(b, 0, 64);
-      t_end = t_next + kTabChunk;  // cnt <= 64 < kTabChunk
+      t_next = first_lane_u64(b);
+      t_end = t_next + kTabChunk;  // cs <= 64 < kTabChunk
     }
-    const uint64_t slot = t_next + mask_rank(mask), base = e_next + (inc - v);
-    t_next += cnt;
+    if (b_next + cl > b_end) {
+      flush_large();
+      unsigned long long b = 0;
+      if (__lane_id() == 0) b = atomicAdd(&ctl->big[next_level], kTabChunk);
+      b_next = first_lane_u64(b);
+      b_end = b_next + kTabChunk;
+    }
+    const uint64_t slot = large ? b_next + mask_rank(ml) : t_next + mask_rank(ms);
+    const uint64_t base = e_next + (inc - v);
+    t_next += cs;
+    b_next += cl;
     e_next += total;
     if (!need) return ~0u;
-    if (slot >= tcap || base + nbk > cap) {
+    const uint32_t room = large ? tcap_big : tcap;
+    Pending* list = large ? out + tcap : out;
+    if (slot >= room || base + nbk > cap) {
       atomicOr(err, kErrGuide);
-      if (slot < tcap) out[slot] = Pending{0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (slot < room) list[slot] = Pending{0, 0, 0, 0, 0, 0, 0, 0, 0};
       return ~0u;
     }
-    out[slot] = Pending{lo, hi, off, first, last, row, sh, nbk, static_cast<uint32_t>(base)};
+    list[slot] = Pending{lo, hi, off, first, last, row, sh, nbk, static_cast<uint32_t>(base)};
     return static_cast<uint32_t>(base);
   }
-  // the unused slots of the wave's current chunk: no buckets
-  __device__ void flush() {
+  // the unused slots of the wave's current chunks: no buckets
+  __device__ void flush_small() {
     for (uint64_t t = t_next + __lane_id(); t < t_end && t < tcap; t += 64) out[t] = Pending{0, 0, 0, 0, 0, 0, 0, 0, 0};
     t_next = t_end;
+  }
+  __device__ void flush_large() {
+    for (uint64_t t = b_next + __lane_id(); t < b_end && t < tcap_big; t += 64)
+      out[tcap + t] = Pending{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    b_next = b_end;
+  }
+  __device__ void flush() {
+    flush_small();
+    flush_large();
   }
 };
 
@@ -175,7 +208,7 @@ __global__ void k_guide_heads(const uint64_t* __restrict__ off, const uint64_t* 
 }
 
 __global__ void k_guide_ctl_init(GuideCtl* ctl, uint64_t e1) {
-  for (uint32_t i = threadIdx.x; i < kGuideLevels + 2; i += blockDim.x) ctl->tables[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kGuideLevels + 2; i += blockDim.x) ctl->tables[i] = ctl->big[i] = 0;
   if (threadIdx.x == 0) ctl->next_entry = e1;
 }
 
@@ -282,7 +315,7 @@ __device__ __forceinline__ uint32_t containing_from(const Th& T, uint32_t a, uin
 // the wave's LDS), then its 64 to 512 entries, lane k taking entries k,
 // k + 64, ... so that the wave's writes are contiguous: candidates by binary
 // search over the staged thresholds and a doubling search from there.
-__global__ void __launch_bounds__(kThreads, 5) k_guide_mid(const uint32_t* __restrict__ rows, uint64_t count,
+__global__ void __launch_bounds__(kThreads) k_guide_mid(const uint32_t* __restrict__ rows, uint64_t count,
                                                         const uint64_t* __restrict__ off,
                                                         const uint32_t* __restrict__ col,
                                                         const uint32_t* __restrict__ w, const Head* __restrict__ head,
@@ -508,47 +541,61 @@ __global__ void k_run_fill(const uint32_t* __restrict__ rows, uint64_t count, co
     for (uint32_t i = 0; i < flag[r]; ++i) runs[scan[r] + i] = make_uint2(rows[r], i * kRun);
 }
 
-// The child tables of one level, a group of kLevelGroup lanes per table.
-// The group holds the table's thresholds in its lanes when there are at
-// most kLevelGroup of them (almost every table: a child's middle holds a
-// few candidates), and each lane fills one entry at a time: candidates by
+// The child tables of one level, a group of GL lanes per table: 8 for the
+// small list (fewer than kLargeThr thresholds between the candidates: about
+// six tables in seven, most of 2 to 8 entries), 16 for the large list.
+// The group holds the table's thresholds in its lanes when there are fewer
+// than GL of them, and each lane fills one entry at a time: candidates by
 // binary search over the group's thresholds through lane shuffles (over the
 // row's thresholds in memory for larger tables), records from the edge
-// records. Tables of the next level go to the other list.
-constexpr uint32_t kLevelGroup = 16;
+// records. Tables of the next level go to the other lists.
+template <uint32_t GL, bool kLarge>
 __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __restrict__ T,
                                                           const uint4* __restrict__ erec, Entry* __restrict__ ent,
-                                                          const Pending* __restrict__ in, uint32_t level, Alloc alloc) {
-  constexpr uint32_t GL = kLevelGroup;
-  uint32_t count = alloc.ctl->tables[level];
-  if (count > alloc.tcap) count = alloc.tcap;
+                                                          const Pending* lists, uint32_t level, Alloc alloc) {
+  constexpr uint32_t kIters = GL == 8 ? 3u : 4u;  // binary-search steps over at most GL positions
+  // not restrict: the loads through it must stay on their side of the
+  // barriers below
+  const Pending* in = kLarge ? lists + alloc.tcap : lists;
+  uint32_t count = kLarge ? alloc.ctl->big[level] : alloc.ctl->tables[level];
+  const uint32_t room = kLarge ? alloc.tcap_big : alloc.tcap;
+  if (count > room) count = room;
   const uint32_t gi = __lane_id() & (GL - 1);
   const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * kThreads) / GL;
   if (count == 0) return;
-  // The group's next table is loaded one iteration ahead. Every load of an
-  // iteration is issued on every path (inactive lanes read index 0 and drop
-  // the value), so the wait for this table's values below leaves the
-  // prefetch in flight.
+  // The part of the group's next table that its loads need (row offset and
+  // candidate range, bytes 16..31 of the descriptor) is loaded one iteration
+  // ahead; the rest of the descriptor then loads beside the table's
+  // thresholds and records. Every load of an iteration is issued on every
+  // path (inactive lanes read index 0 and drop the value), so the wait for
+  // this table's values below leaves the prefetch in flight.
+  static_assert(sizeof(Pending) == 48, "descriptor layout");
   uint64_t t = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) / GL;
-  Pending pn = in[t < count ? t : 0];
+  uint4 pn = reinterpret_cast<const uint4*>(in + (t < count ? t : 0))[1];
   bool pn_ok = t < count;
   __builtin_amdgcn_s_waitcnt(0);
   for (; __ballot(t < count) != 0; t += groups) {  // wave-uniform loop
-    const Pending p = pn_ok ? pn : Pending{};  // tables that found no room have no buckets
-    const uint32_t nthr = p.b - p.a;  // thresholds between the candidates
+    const uint64_t off = pn_ok ? (static_cast<uint64_t>(pn.y) << 32) | pn.x : 0;
+    const uint32_t pa = pn_ok ? pn.z : 0, pb = pn_ok ? pn.w : 0;
+    const uint32_t nthr = pb - pa;  // thresholds between the candidates
     // small tables: lane j holds threshold a + j and the record of candidate a + j
     const bool small = nthr < GL;
     const bool tv_ok = gi < nthr && small, rv_ok = gi <= nthr && small;
-    const uint64_t Tl = T[tv_ok ? p.off + p.a + gi : 0];
-    const uint4 Rl = erec[rv_ok ? p.off + p.a + gi : 0];
-    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch behind these loads
+    const Pending pl = in[pn_ok ? t : 0];
+    const uint64_t Tl = T[tv_ok ? off + pa + gi : 0];
+    const uint4 Rl = erec[rv_ok ? off + pa + gi : 0];
+    // keep the prefetch behind these loads (an empty statement the compiler
+    // may not move loads across; it emits nothing)
+    __asm__ __volatile__("" ::: "memory");
+    const bool was_ok = pn_ok;
     const uint64_t tn = t + groups;
-    pn = in[tn < count ? tn : 0];
+    pn = reinterpret_cast<const uint4*>(in + (tn < count ? tn : 0))[1];
     pn_ok = tn < count;
-    __builtin_amdgcn_sched_barrier(0);
-    // this table's loads complete (vmcnt <= 4: the prefetch's loads may
-    // still be in flight; the compiler adds whatever more a use needs)
-    __builtin_amdgcn_s_waitcnt(0xF74);
+    __asm__ __volatile__("" ::: "memory");
+    // this table's loads complete (vmcnt <= 1: the prefetch may still be in
+    // flight; the compiler adds whatever more a use needs)
+    __builtin_amdgcn_s_waitcnt(0xF71);
+    const Pending p = was_ok ? pl : Pending{};  // tables that found no room have no buckets
     const uint64_t Tv = tv_ok ? Tl : ~0ull;
     const uint4 Rv = rv_ok ? Rl : make_uint4(0, 0, 0, 0);
     uint32_t most = (p.nbk + GL - 1) / GL;
@@ -571,7 +618,7 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
       // thresholds <= blo and <= bhi among the group's (every lane shuffles)
       uint32_t l0 = 0, h0 = small ? nthr : 0, l1 = 0, h1 = h0;
 #pragma unroll
-      for (uint32_t it = 0; it < 4; ++it) {  // ranges of at most GL = 16 positions
+      for (uint32_t it = 0; it < kIters; ++it) {  // ranges of at most GL positions
         const uint32_t m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
         const uint64_t x0 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(m0 & (GL - 1)), GL);
         const uint64_t x1 = __shfl(static_cast<unsigned long long>(Tv), static_cast<int>(m1 & (GL - 1)), GL);
@@ -764,6 +811,7 @@ Alloc allocator(fppr_graph* g, uint32_t next_level, uint32_t max_level) {
   a.out = g->gtab[list];
   a.cap = g->g_cap;
   a.tcap = g->g_tcap;
+  a.tcap_big = g->g_tcap_big;
   a.next_level = next_level;
   a.max_level = max_level;
   a.err = g->d_err;
@@ -813,8 +861,11 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
 
 hipError_t launch_guide_level(fppr_graph* g, uint32_t level, uint32_t levels, hipStream_t s) {
   const guide::Pending* in = g->gtab[level & 1u ? 1 : 0];
-  hipLaunchKernelGGL(k_guide_level, dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
-                     allocator(g, level + 1, levels));
+  const Alloc a = allocator(g, level + 1, levels);
+  hipLaunchKernelGGL((k_guide_level<8, false>), dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
+                     a);
+  hipLaunchKernelGGL((k_guide_level<16, true>), dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
+                     a);
   return hipGetLastError();
 }
 
