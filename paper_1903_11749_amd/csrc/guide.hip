@@ -833,6 +833,19 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                      bases ? g->scan : nullptr, g->cls, g->n, g->ghead);
   hipLaunchKernelGGL(k_guide_ctl_init, dim3(1), dim3(64), 0, s, g->gctl, g->g_entries1);
   const Alloc p = allocator(g, 2, levels);
+  // Rows of 65-1024 edges on gbs[0], longer rows on gbs[1], both after the
+  // heads and counters above, beside the short rows on s; s waits for both.
+  // A rebuild recorded into a stream capture keeps everything on s.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return e;
+  const bool fork = cs == hipStreamCaptureStatusNone;
+  hipStream_t s_mid = fork ? g->gbs[0] : s, s_long = fork ? g->gbs[1] : s;
+  if (fork) {
+    e = hipEventRecord(g->gb_fork, s);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(g->gbs[k], g->gb_fork, 0);
+    if (e != hipSuccess) return e;
+  }
   launch_rows<0>(g, p, s);
   launch_rows<1>(g, p, s);
   launch_rows<2>(g, p, s);
@@ -842,21 +855,27 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
   launch_rows<6>(g, p, s);
   const uint64_t nmid = g->gclass_off[8] - g->gclass_off[7];
   if (nmid)
-    hipLaunchKernelGGL(k_guide_mid, dim3(std::min<uint32_t>(grid_for(nmid * 64), 2048u)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(k_guide_mid, dim3(std::min<uint32_t>(grid_for(nmid * 64), 2048u)), dim3(kThreads), 0, s_mid,
                        g->gclass + g->gclass_off[7], nmid, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec,
                        g->gent, p);
   const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
   if (nlong) {
+    hipStream_t t = s_long;
     const uint32_t tb = static_cast<uint32_t>(std::min<uint64_t>(g->n_tiles, 8192));
-    hipLaunchKernelGGL(k_tile_sums, dim3(tb), dim3(kThreads), 0, s, g->gtiles, g->n_tiles, g->off, g->w, g->gtsum);
-    hipLaunchKernelGGL(k_tile_offsets, dim3(grid_for(nlong)), dim3(kThreads), 0, s, g->gclass + g->gclass_off[8],
+    hipLaunchKernelGGL(k_tile_sums, dim3(tb), dim3(kThreads), 0, t, g->gtiles, g->n_tiles, g->off, g->w, g->gtsum);
+    hipLaunchKernelGGL(k_tile_offsets, dim3(grid_for(nlong)), dim3(kThreads), 0, t, g->gclass + g->gclass_off[8],
                        nlong, g->off, g->gtile_first, g->gtsum, g->gtoff, g->gttot);
-    hipLaunchKernelGGL(k_tile_thresholds, dim3(tb), dim3(kThreads), 0, s, g->gtiles, g->n_tiles, g->off, g->col,
+    hipLaunchKernelGGL(k_tile_thresholds, dim3(tb), dim3(kThreads), 0, t, g->gtiles, g->n_tiles, g->off, g->col,
                        g->w, g->ghead, g->n, g->gtoff, g->gttot, g->gT, g->gerec);
-    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs * kRun), 2048u)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs * kRun), 2048u)), dim3(kThreads), 0, t,
                        g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
   }
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k = 0; k < 2 && fork && e == hipSuccess; ++k) {
+    e = hipEventRecord(g->gb_join[k], g->gbs[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, g->gb_join[k], 0);
+  }
+  return e;
 }
 
 hipError_t launch_guide_level(fppr_graph* g, uint32_t level, uint32_t levels, hipStream_t s) {
