@@ -79,11 +79,6 @@ void free_graph(fppr_graph* g) {
   dfree(g->gtab[0]);
   dfree(g->gtab[1]);
   dfree(g->gctl);
-  for (int k = 0; k < 2; ++k) {
-    if (g->gbs[k]) (void)hipStreamDestroy(g->gbs[k]);
-    if (g->gb_join[k]) (void)hipEventDestroy(g->gb_join[k]);
-  }
-  if (g->gb_fork) (void)hipEventDestroy(g->gb_fork);
   if (g->side) (void)hipStreamDestroy(g->side);
   if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
   if (g->join_ev) (void)hipEventDestroy(g->join_ev);
@@ -173,14 +168,6 @@ fppr_status create_guide(fppr_graph* g, hipStream_t s) {
   if ((e = hipMemcpy(&e1, g->d_err + 4, 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "read sizes");
   if (e1 >= (1ull << 32)) return invalid("layout GUIDE needs fewer than 2^32 row-table entries");
   g->g_entries1 = e1;
-  for (int k = 0; k < 2; ++k) {
-    if ((e = hipStreamCreateWithFlags(&g->gbs[k], hipStreamNonBlocking)) != hipSuccess)
-      return hip_fail(e, "hipStreamCreate(guide build)");
-    if ((e = hipEventCreateWithFlags(&g->gb_join[k], hipEventDisableTiming)) != hipSuccess)
-      return hip_fail(e, "hipEventCreate(guide build)");
-  }
-  if ((e = hipEventCreateWithFlags(&g->gb_fork, hipEventDisableTiming)) != hipSuccess)
-    return hip_fail(e, "hipEventCreate(guide build)");
   if ((e = dmalloc(&g->ghead, g->n, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide heads)");
   if ((e = dmalloc(&g->gT, g->m, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(guide thresholds)");
   if ((e = dmalloc(&g->gerec, g->m, acc)) != hipSuccess) return hip_fail(e, "hipMalloc(edge records)");

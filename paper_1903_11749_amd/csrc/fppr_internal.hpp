@@ -82,10 +82,6 @@ struct fppr_graph {
   std::mutex side_mu;  // keeps each event record and its wait together across host threads
   // guide-table layout (guide.hpp): instead of node lines and row regions
   bool guide = false;
-  // the guide build's rows of 65-1024 edges and of more edges go on two
-  // streams of their own beside the shorter rows (fork and join events)
-  hipStream_t gbs[2] = {nullptr, nullptr};
-  hipEvent_t gb_fork = nullptr, gb_join[2] = {nullptr, nullptr};
   fppr::guide::Head* ghead = nullptr;      // [n] first entry of each node's table, lg | class << 8
   fppr::guide::Entry* gent = nullptr;      // [g_cap] row tables [0, g_entries1), then child tables
   uint64_t* gT = nullptr;                  // [m] draw thresholds of every edge but a row's last (~0 there)

@@ -833,19 +833,25 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                      bases ? g->scan : nullptr, g->cls, g->n, g->ghead);
   hipLaunchKernelGGL(k_guide_ctl_init, dim3(1), dim3(64), 0, s, g->gctl, g->g_entries1);
   const Alloc p = allocator(g, 2, levels);
-  // Rows of 65-1024 edges on gbs[0], longer rows on gbs[1], both after the
-  // heads and counters above, beside the short rows on s; s waits for both.
-  // A rebuild recorded into a stream capture keeps everything on s.
+  // Rows of more than 1024 edges on the graph's side stream (when it has
+  // one: graphs whose all-nodes runs split off the nodes without out-edges),
+  // after the heads and counters above and beside the shorter rows on s,
+  // which waits for them. No stream of its own: every stream a process
+  // creates takes a hardware queue slot, and more of them made the queues
+  // the serving streams share. A rebuild recorded into a stream capture
+  // keeps everything on s.
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(s, &cs);
   if (e != hipSuccess) return e;
-  const bool fork = cs == hipStreamCaptureStatusNone;
-  hipStream_t s_mid = fork ? g->gbs[0] : s, s_long = fork ? g->gbs[1] : s;
+  const bool fork = cs == hipStreamCaptureStatusNone && g->side != nullptr;
+  std::unique_lock<std::mutex> lk(g->side_mu, std::defer_lock);
   if (fork) {
-    e = hipEventRecord(g->gb_fork, s);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(g->gbs[k], g->gb_fork, 0);
+    lk.lock();
+    e = hipEventRecord(g->fork_ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(g->side, g->fork_ev, 0);
     if (e != hipSuccess) return e;
   }
+  hipStream_t s_long = fork ? g->side : s;
   launch_rows<0>(g, p, s);
   launch_rows<1>(g, p, s);
   launch_rows<2>(g, p, s);
@@ -855,7 +861,7 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
   launch_rows<6>(g, p, s);
   const uint64_t nmid = g->gclass_off[8] - g->gclass_off[7];
   if (nmid)
-    hipLaunchKernelGGL(k_guide_mid, dim3(std::min<uint32_t>(grid_for(nmid * 64), 2048u)), dim3(kThreads), 0, s_mid,
+    hipLaunchKernelGGL(k_guide_mid, dim3(std::min<uint32_t>(grid_for(nmid * 64), 2048u)), dim3(kThreads), 0, s,
                        g->gclass + g->gclass_off[7], nmid, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec,
                        g->gent, p);
   const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
@@ -871,9 +877,9 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                        g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  for (int k = 0; k < 2 && fork && e == hipSuccess; ++k) {
-    e = hipEventRecord(g->gb_join[k], g->gbs[k]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, g->gb_join[k], 0);
+  if (fork) {
+    e = hipEventRecord(g->join_ev, g->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, g->join_ev, 0);
   }
   return e;
 }
