@@ -87,6 +87,22 @@ __device__ __forceinline__ uint4 gload16(uint64_t addr, uint32_t k) {
   const U32x4 v = ((GlobalV4)addr)[k];
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+// The three used words of a 16-byte pool entry: a load with no dead
+// destination register, which the compiler would otherwise reuse at once
+// and so wait for the load there (before the iteration's other loads are
+// issued).
+typedef uint32_t U32x2 __attribute__((ext_vector_type(2)));
+typedef const U32x2 __attribute__((address_space(1)))* GlobalV2;
+__device__ __forceinline__ uint2 gload8(uint64_t addr) {
+  const U32x2 v = *((GlobalV2)addr);
+  return make_uint2(v.x, v.y);
+}
+typedef uint32_t U32x3 __attribute__((ext_vector_type(3)));
+typedef const U32x3 __attribute__((address_space(1)))* GlobalV3;
+__device__ __forceinline__ uint3 gload12(uint64_t addr) {
+  const U32x3 v = *((GlobalV3)addr);
+  return make_uint3(v.x, v.y, v.z);
+}
 
 template <bool kStats, bool kLaneKeys, uint32_t kInlineRestarts>
 __global__ void __launch_bounds__(kThreads) k_walk_guide(WalkTable t) {
@@ -216,14 +232,19 @@ __global__ void __launch_bounds__(kThreads) k_walk_guide(WalkTable t) {
 
     // ---- this iteration's loads ----
     const uint32_t ph = L.ph;
-    uint2 hv = make_uint2(0, 0);
-    uint4 pv = make_uint4(0, 0, 0, 0);
+    // read only by the lanes that load them (no zeroing for the others: a
+    // write to a destination of a load in flight in other lanes would wait
+    // for that load before the iteration's entry loads are issued)
+    uint2 hv;
+    uint3 pv;
     if (ph == kHead) {
-      const guide::Head h = head[L.s];
-      hv = make_uint2(h.base, h.meta);
+      hv = gload8(reinterpret_cast<uint64_t>(head + L.s));
     } else if (ph == kPool) {
-      pv = gload16(L.X, 0);
+      pv = gload12(L.X);
     }
+    // an empty statement loads may not be moved across (it emits nothing):
+    // these loads stay ahead of the entry loads, all in flight together
+    __asm__ __volatile__("" ::: "memory");
     const uint64_t ent_mask = __ballot(ph == kEntry);
     uint32_t r0 = 0, r1 = 0, r2 = 0;
     if (ent_mask) {
