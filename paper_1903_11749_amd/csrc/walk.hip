@@ -288,14 +288,22 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
     // the graph's layout (wave-uniform; a constant unless the table mixes layouts)
     const bool nar = kLayout == 2 ? (dflags & kDescNarrow) != 0 : kLayout == 1;
     const bool rec_line = (ph == kSrcRec || ph == kRec);
-    uint64_t v0 = 0, v1 = 0;
+    // vb and vp are read only by the lanes that load them: no lane writes
+    // them otherwise, since a write to a destination of a load in flight in
+    // other lanes would wait for that load before the line loads below
+    uint32_t vb32;  // narrow layout
+    uint64_t vb64, vp;
     if (ph == kBsearch) {
       const uint64_t lb = reinterpret_cast<uint64_t>(blocks + L.off + L.lo + ((L.hi - L.lo) >> 1));
-      v0 = nar ? static_cast<uint64_t>(((GlobalU32)lb)[kNarrowLeafEdges - 1])
-               : ((GlobalU64)lb)[kLeafEdges - 1];
+      if (nar) vb32 = ((GlobalU32)lb)[kNarrowLeafEdges - 1];
+      else vb64 = ((GlobalU64)lb)[kLeafEdges - 1];
     } else if (ph == kPool) {
-      v0 = *(GlobalU64)L.X;
+      vp = *(GlobalU64)L.X;
     }
+    // an empty statement loads may not be moved across (it emits nothing):
+    // these loads stay ahead of the line loads, all in flight together
+    __asm__ __volatile__("" ::: "memory");
+    uint64_t v0 = 0, v1 = 0;
     const bool want_line = rec_line || ph == kTree || ph == kLeaf;
     const uint64_t line_mask = __ballot(want_line);
     const uint64_t leaf_mask = __ballot(ph == kLeaf);
@@ -406,7 +414,8 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
       }
     } else if (ph == kBsearch) {  // over leaf blocks: their last prefixes
       const uint32_t mid = L.lo + ((L.hi - L.lo) >> 1);
-      if (v0 > L.X) L.hi = mid; else L.lo = mid + 1;
+      const uint64_t vb = nar ? static_cast<uint64_t>(vb32) : vb64;
+      if (vb > L.X) L.hi = mid; else L.lo = mid + 1;
       if (L.lo == L.hi) {
         L.hi = 0;
         L.ph = kLeaf;
@@ -418,7 +427,7 @@ __global__ void __launch_bounds__(kThreads) k_walk(WalkTable t) {
       step = true;
       coin = L.x2 < (kLaneKeys ? L.T : T);
     } else if (ph == kPool) {
-      const uint64_t e = v0;
+      const uint64_t e = vp;
       const uint32_t end = static_cast<uint32_t>(e);
       L.tail = tagged ? end & kIdMask : end;
       tag = tagged ? end >> kTagShift : 0u;
