@@ -167,12 +167,28 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v, uint32_t j) {
   }
 }
 
+// Bitonic sort of the wave's 64 * E values ascending in element order
+// (idx = e * 64 + lane). Every compare-exchange runs one way (the lower
+// index keeps the minimum): during merge level k the blocks that the network
+// orders descending hold their values complemented (~x reverses the unsigned
+// order), so the exchange direction depends only on j, a mask per j instead
+// of one per (k, j, register). Changing the complemented blocks from one
+// level to the next is one XOR per register.
 template <int E>
 __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[E]) {
   const uint32_t lane = __lane_id();
   constexpr uint32_t N = 64 * E;
+  uint32_t flip[E];
+#pragma unroll
+  for (uint32_t e = 0; e < E; ++e) flip[e] = 0;
 #pragma unroll
   for (uint32_t k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t want = ((e * 64 + lane) & k) ? ~0u : 0u;
+      v[e] ^= flip[e] ^ want;
+      flip[e] = want;
+    }
 #pragma unroll
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       if (j >= 64) {  // partner in another register of the same lane
@@ -181,33 +197,42 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[E]) {
         for (uint32_t e = 0; e < E; ++e) {
           const uint32_t pe = e ^ je;
           if (pe > e) {
-            const bool up = (((e * 64 + lane) & k) == 0);
-            const uint32_t a = v[e], b = v[pe];
-            const bool sw = (a > b) == up;
-            v[e] = sw ? b : a;
-            v[pe] = sw ? a : b;
+            const uint32_t x = v[e], y = v[pe];
+            v[e] = x < y ? x : y;
+            v[pe] = x < y ? y : x;
           }
         }
       } else {  // partner in lane ^ j of the same register
+        const bool lower = (lane & j) == 0;  // this lane holds the lower index
 #pragma unroll
         for (uint32_t e = 0; e < E; ++e) {
-          const uint32_t idx = e * 64 + lane;
           const uint32_t other = xor_lane(v[e], j);
-          const bool up = (idx & k) == 0;
-          const bool lower = (lane & j) == 0;  // this lane holds the lower index
-          const bool take_min = (lower == up);
-          v[e] = take_min ? (v[e] < other ? v[e] : other) : (v[e] > other ? v[e] : other);
+          v[e] = lower ? (v[e] < other ? v[e] : other) : (v[e] > other ? v[e] : other);
         }
       }
     }
   }
+  // the last level (k = N) complements nothing: flip is 0 here
+}
+
+// Largest value over the wave (every lane active): rows of 16 lanes by DPP,
+// then the four row results through scalar registers. Wave-uniform result.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (uint32_t j = 1; j < 16; j <<= 1) {
+    const uint32_t y = xor_lane(x, j);
+    x = y > x ? y : x;
+  }
+  const uint32_t r0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 0));
+  const uint32_t r1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 16));
+  const uint32_t r2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 32));
+  const uint32_t r3 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 48));
+  const uint32_t m01 = r0 > r1 ? r0 : r1, m23 = r2 > r3 ? r2 : r3;
+  return m01 > m23 ? m01 : m23;
 }
 
 template <int E>
 __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
-  constexpr uint32_t N = 64 * E;
-  __shared__ uint32_t run_t[kThreads / 64][N];
-  __shared__ uint32_t run_key[kThreads / 64][N];
   const uint32_t lane = __lane_id();
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t R = a.R;
@@ -276,9 +301,11 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       nd += static_cast<uint32_t>(__popcll(hm[e]));
     }
     uint64_t dig = 0;
+    uint32_t cnt[E];  // size of the run this element heads, 0 elsewhere
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
       const uint32_t idx = e * 64 + lane;
+      cnt[e] = 0;
       if ((hm[e] >> lane) & 1ull) {
         const uint32_t rank = before[e] + mask_rank(hm[e]);
         // next head after idx, or R (end of the valid endpoints)
@@ -292,14 +319,12 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
             if (hm[e2]) nxt = e2 * 64 + static_cast<uint32_t>(__builtin_ctzll(hm[e2]));
         }
         const uint32_t c = nxt - idx;
+        cnt[e] = c;
         if (a.counts) {
           a.counts[(row * R + rank) * 2] = v[e];
           a.counts[(row * R + rank) * 2 + 1] = c;
         }
         if (a.digest) dig += digest_term(src, v[e], c);
-        run_t[wv][rank] = v[e];
-        // ranking key: count descending, then rank (= node id) ascending
-        run_key[wv][rank] = ((N - c) << 8) | rank;
       }
       if (a.counts && idx >= nd && idx < R) {
         a.counts[(row * R + idx) * 2] = 0;
@@ -312,39 +337,45 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       if (lane == 0) a.digest[row] = dig;
     }
     if (a.topk && a.k) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      uint32_t kv[E];
+      // Ranking by (count desc, t asc) without a second sort: the run heads
+      // already stand in increasing t (element order), so the runs of the
+      // largest count take the first positions in element order, those of
+      // the next largest count the following ones, and so on until k
+      // positions are taken. One pass per distinct count value (at most
+      // about sqrt(2R) of them, a handful in practice).
+      uint32_t pos[E];
+      uint32_t mx = 0;
 #pragma unroll
       for (uint32_t e = 0; e < E; ++e) {
-        const uint32_t idx = e * 64 + lane;
-        kv[e] = idx < nd ? run_key[wv][idx] : 0xFFFFFFFFu;
+        pos[e] = ~0u;
+        mx = cnt[e] > mx ? cnt[e] : mx;
       }
-      if (E > 1 && nd <= 64) {  // wave-uniform: every key in the first register, the rest padding
-        uint32_t k1[1] = {kv[0]};
-        wave_bitonic<1>(k1);
-        kv[0] = k1[0];
-      } else {
-        wave_bitonic<E>(kv);
+      uint32_t cur = wave_max_u32(mx), base = 0;  // wave-uniform
+      while (cur != 0 && base < a.k) {
+        uint32_t below = 0;  // largest count under cur held by this lane
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) {
+          const bool here = cnt[e] == cur;
+          const uint64_t m = __ballot(here);
+          if (here) pos[e] = base + mask_rank(m);
+          base += static_cast<uint32_t>(__popcll(m));
+          if (cnt[e] < cur && cnt[e] > below) below = cnt[e];
+        }
+        cur = wave_max_u32(below);
       }
 #pragma unroll
       for (uint32_t e = 0; e < E; ++e) {
+        if (pos[e] < a.k) {
+          a.topk[(row * a.k + pos[e]) * 2] = v[e];
+          a.topk[(row * a.k + pos[e]) * 2 + 1] = cnt[e];
+        }
         const uint32_t q = e * 64 + lane;
-        if (q < a.k) {
-          uint32_t t = kNoNode, c = 0;
-          if (q < nd) {
-            t = run_t[wv][kv[e] & 0xFFu];
-            c = N - (kv[e] >> 8);
-          }
-          a.topk[(row * a.k + q) * 2] = t;
-          a.topk[(row * a.k + q) * 2 + 1] = c;
+        if (q >= nd && q < a.k) {
+          a.topk[(row * a.k + q) * 2] = kNoNode;
+          a.topk[(row * a.k + q) * 2 + 1] = 0u;
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
