@@ -459,18 +459,26 @@ __global__ void __launch_bounds__(kThreads) k_tile_thresholds(const uint2* __res
 // Entries of the long rows: a group of kRun lanes per run of kRun
 // consecutive entries of one row (runs listed at creation: (row, first
 // entry)), lane k filling entry k, so that a group writes its run's entries
-// as one contiguous stretch. Each lane finds its bucket's first candidate by
-// binary search over the row's thresholds (the lanes of a group search
-// neighbouring draws, so they share the lines read) and its last by a
-// doubling search from there (a bucket of a long row holds few candidates,
-// except where light edges crowd).
+// as one contiguous stretch. The group first narrows, together, the
+// candidate range holding the run's draws: each round its 16 lanes read 16
+// evenly spaced thresholds of the range at once and keep the part between
+// the last one at or below the run's first draw and the first one above its
+// last draw, so a row of 2^17 edges takes about four rounds of loads where
+// a binary search takes seventeen dependent ones. When at most 32 thresholds
+// remain, they sit two per lane and each lane finds its bucket's candidates
+// by shuffles; otherwise (light edges crowding the run's draws) each lane
+// searches the narrowed range itself.
 constexpr uint32_t kRun = 16;
+constexpr uint32_t kRunWin = 2 * kRun;
+constexpr uint32_t kRunRounds = 6;
 __global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict__ runs, uint64_t count,
                                                          const uint64_t* __restrict__ off, const Head* __restrict__ head,
                                                          const uint64_t* __restrict__ T, const uint4* __restrict__ erec,
                                                          Entry* __restrict__ ent, Alloc alloc) {
-  const uint32_t gi = __lane_id() & (kRun - 1);
+  const uint32_t gi = __lane_id() & (kRun - 1), gb = __lane_id() & ~(kRun - 1);
   const uint64_t groups = (static_cast<uint64_t>(gridDim.x) * kThreads) / kRun;
+  // the group's lanes of a wave-wide ballot
+  auto group_bits = [&](uint64_t m) { return static_cast<uint32_t>((m >> gb) & ((1u << kRun) - 1)); };
   for (uint64_t q = (blockIdx.x * static_cast<uint64_t>(kThreads) + threadIdx.x) / kRun; __ballot(q < count) != 0;
        q += groups) {  // wave-uniform loop
     bool act = q < count;
@@ -484,14 +492,68 @@ __global__ void __launch_bounds__(kThreads) k_guide_runs(const uint2* __restrict
     const Thr th{T + a};
     const ERec rec{erec + a};
     const uint32_t b = rb.y + gi;  // < 2^kb: runs tile the table (2^kb >= 1024 here)
+    uint64_t blo = 0, bhi = 0, x0 = 0, x1 = 0, unused = 0;
+    guide::row_bucket(kb, b, &blo, &bhi);
+    guide::row_bucket(kb, rb.y, &x0, &unused);            // the run's first draw
+    guide::row_bucket(kb, rb.y + kRun - 1, &unused, &x1);  // and its last
+    // [lo, hi]: holds the candidates of every draw in [x0, x1] (thresholds
+    // lo .. hi - 1 remain to be placed)
+    uint32_t lo = 0, hi = last;
+    bool go = act;  // group-uniform
+#pragma unroll 1
+    for (uint32_t round = 0; round < kRunRounds; ++round) {
+      if (__ballot(go) == 0) break;  // wave-uniform
+      const uint32_t span = hi - lo;
+      go = go && span > kRunWin;
+      // probe i at lo + span (i + 1) / 17: strictly increasing, all below hi
+      const uint32_t p = lo + static_cast<uint32_t>(static_cast<uint64_t>(span) * (gi + 1) / (kRun + 1));
+      const uint64_t t = go ? th(p) : 0;
+      const uint32_t n0 = static_cast<uint32_t>(__popc(group_bits(__ballot(go && t <= x0))));
+      const uint32_t n1 = static_cast<uint32_t>(__popc(group_bits(__ballot(go && t <= x1))));
+      if (go) {
+        // probes below n0 are at or below x0, those from n1 on above x1
+        const uint32_t nlo = n0 ? lo + static_cast<uint32_t>(static_cast<uint64_t>(span) * n0 / (kRun + 1)) + 1 : lo;
+        const uint32_t nhi =
+            n1 < kRun ? lo + static_cast<uint32_t>(static_cast<uint64_t>(span) * (n1 + 1) / (kRun + 1)) : hi;
+        go = nlo != lo || nhi != hi;  // no progress: the lanes search from here
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+    const uint32_t span = hi - lo;
+    const bool win = span <= kRunWin;  // group-uniform
+    // the remaining thresholds: lo + i in lane i % 16, register i / 16
+    const uint64_t wa = act && win && gi < span ? th(lo + gi) : ~0ull;
+    const uint64_t wb = act && win && gi + kRun < span ? th(lo + kRun + gi) : ~0ull;
+    uint32_t l0 = 0, h0 = win ? span : 0, l1 = 0, h1 = h0;
+#pragma unroll
+    for (uint32_t it = 0; it < 6; ++it) {  // ranges of at most 33 counts
+      const uint32_t m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
+      const uint64_t y0a = __shfl(static_cast<unsigned long long>(wa), static_cast<int>(m0 & (kRun - 1)), kRun);
+      const uint64_t y0b = __shfl(static_cast<unsigned long long>(wb), static_cast<int>(m0 & (kRun - 1)), kRun);
+      const uint64_t y1a = __shfl(static_cast<unsigned long long>(wa), static_cast<int>(m1 & (kRun - 1)), kRun);
+      const uint64_t y1b = __shfl(static_cast<unsigned long long>(wb), static_cast<int>(m1 & (kRun - 1)), kRun);
+      const uint64_t y0 = m0 < kRun ? y0a : y0b, y1 = m1 < kRun ? y1a : y1b;
+      if (l0 < h0) {
+        if (y0 <= blo) l0 = m0 + 1;
+        else h0 = m0;
+      }
+      if (l1 < h1) {
+        if (y1 <= bhi) l1 = m1 + 1;
+        else h1 = m1;
+      }
+    }
     uint32_t c0 = 0, c1 = 0;
     uint64_t t0 = 0, t1 = 0;
     Cand L{}, M{}, R{};
     if (act) {
-      uint64_t blo, bhi;
-      guide::row_bucket(kb, b, &blo, &bhi);
-      c0 = guide::containing(th, 0u, last, blo);
-      c1 = containing_from(th, c0, last, bhi);
+      if (win) {
+        c0 = lo + l0;
+        c1 = lo + l1;
+      } else {
+        c0 = guide::containing(th, lo, hi, blo);
+        c1 = containing_from(th, c0, hi, bhi);
+      }
       if (c1 > c0) {
         t0 = th(c0);
         t1 = th(c1 - 1);
