@@ -935,8 +935,15 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                        nlong, g->off, g->gtile_first, g->gtsum, g->gtoff, g->gttot);
     hipLaunchKernelGGL(k_tile_thresholds, dim3(tb), dim3(kThreads), 0, t, g->gtiles, g->n_tiles, g->off, g->col,
                        g->w, g->ghead, g->n, g->gtoff, g->gttot, g->gT, g->gerec);
-    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs * kRun), 2048u)), dim3(kThreads), 0, t,
-                       g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
+    // no more blocks than fit at once: waves left for a second round would
+    // run it nearly alone, waiting on their searches' loads
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_guide_runs, kThreads, 0)) != hipSuccess) return e;
+    const uint32_t resident = static_cast<uint32_t>(std::max(1, per_cu) * std::max(1, cus));
+    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs * kRun), std::min(resident, 2048u))),
+                       dim3(kThreads), 0, t, g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (fork) {
