@@ -29,6 +29,20 @@ uint32_t grid_for(uint64_t items) {
   if (b > 65536) b = 65536;
   return static_cast<uint32_t>(b);
 }
+// Blocks for a grid-stride kernel over `items` threads' work: no more
+// than fit on the device at once (a second round of waves would run with
+// the SIMDs partly empty, waiting on loads) and at most `cap`.
+template <typename Kernel>
+hipError_t resident_grid(Kernel kernel, uint64_t items, uint32_t cap, uint32_t* blocks) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0);
+  if (e != hipSuccess) return e;
+  const uint32_t fit = static_cast<uint32_t>(std::max(1, per_cu) * std::max(1, cus));
+  *blocks = std::min(grid_for(items), std::min(fit, cap));
+  return hipSuccess;
+}
 
 // thresholds of a row: T(j) for j < d - 1
 struct Thr {
@@ -74,6 +88,20 @@ __device__ __forceinline__ uint64_t first_lane_u64(unsigned long long x) {
          (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32))))
           << 32);
 }
+// Inclusive sum over the wave of a 32-bit value by DPP (every lane
+// active): within rows of 16 lanes by shifts of 1, 2, 4 and 8 (lanes shifted
+// in read 0), then across rows by the broadcasts of lane 15 of each row to
+// the next (rows 1 and 3 take it) and of lane 31 (rows 2 and 3 take it).
+__device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t x) {
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xF, 0xF, true));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xF, 0xF, true));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xF, 0xF, true));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xF, 0xF, true));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xA, 0xF, false));
+  x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xC, 0xF, false));
+  return x;
+}
+
 struct Alloc {
   GuideCtl* ctl;
   Pending* out;
@@ -90,8 +118,15 @@ struct Alloc {
     const uint64_t mask = __ballot(need);
     if (mask == 0) return ~0u;
     const uint64_t v = need ? nbk : 0u;
-    const uint64_t inc = wave_inclusive_scan_u64(v);
-    const uint64_t total = first_lane_u64(__shfl(static_cast<unsigned long long>(inc), 63, 64));
+    uint64_t inc = 0, total = 0;
+    if (__ballot(v >= (1u << 25)) == 0) {  // wave-uniform: the 64 values sum below 2^31
+      const uint32_t i32 = wave_inclusive_scan_u32(static_cast<uint32_t>(v));
+      inc = i32;
+      total = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(i32), 63));
+    } else {
+      inc = wave_inclusive_scan_u64(v);
+      total = first_lane_u64(__shfl(static_cast<unsigned long long>(inc), 63, 64));
+    }
     const bool open = next_level <= max_level;
     if (!open) {
       if (need) atomicOr(err, kErrGuide);
@@ -880,13 +915,16 @@ Alloc allocator(fppr_graph* g, uint32_t next_level, uint32_t max_level) {
   return a;
 }
 template <uint32_t CL>
-void launch_rows(fppr_graph* g, const Alloc& p, hipStream_t s) {
+hipError_t launch_rows(fppr_graph* g, const Alloc& p, hipStream_t s) {
   const uint64_t count = g->gclass_off[CL + 1] - g->gclass_off[CL];
-  if (!count) return;
-  const uint32_t blocks = std::min<uint32_t>(grid_for(count << CL), 2048u);  // few waves: few partial chunks
+  if (!count) return hipSuccess;
+  uint32_t blocks = 0;  // few waves: few partial chunks
+  const hipError_t e = resident_grid(k_guide_rows<CL>, count << CL, 2048u, &blocks);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_guide_rows<CL>, dim3(blocks), dim3(kThreads), 0, s,
                      g->gclass + g->gclass_off[CL], count, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec,
                      g->gent, p);
+  return hipGetLastError();
 }
 }  // namespace
 
@@ -914,16 +952,16 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
     if (e != hipSuccess) return e;
   }
   hipStream_t s_long = fork ? g->side : s;
-  launch_rows<0>(g, p, s);
-  launch_rows<1>(g, p, s);
-  launch_rows<2>(g, p, s);
-  launch_rows<3>(g, p, s);
-  launch_rows<4>(g, p, s);
-  launch_rows<5>(g, p, s);
-  launch_rows<6>(g, p, s);
+  if ((e = launch_rows<0>(g, p, s)) != hipSuccess || (e = launch_rows<1>(g, p, s)) != hipSuccess ||
+      (e = launch_rows<2>(g, p, s)) != hipSuccess || (e = launch_rows<3>(g, p, s)) != hipSuccess ||
+      (e = launch_rows<4>(g, p, s)) != hipSuccess || (e = launch_rows<5>(g, p, s)) != hipSuccess ||
+      (e = launch_rows<6>(g, p, s)) != hipSuccess)
+    return e;
   const uint64_t nmid = g->gclass_off[8] - g->gclass_off[7];
+  uint32_t mid_blocks = 0;
+  if (nmid && (e = resident_grid(k_guide_mid, nmid * 64, 2048u, &mid_blocks)) != hipSuccess) return e;
   if (nmid)
-    hipLaunchKernelGGL(k_guide_mid, dim3(std::min<uint32_t>(grid_for(nmid * 64), 2048u)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(k_guide_mid, dim3(mid_blocks), dim3(kThreads), 0, s,
                        g->gclass + g->gclass_off[7], nmid, g->off, g->col, g->w, g->ghead, g->n, g->gT, g->gerec,
                        g->gent, p);
   const uint64_t nlong = g->gclass_off[9] - g->gclass_off[8];
@@ -935,15 +973,10 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
                        nlong, g->off, g->gtile_first, g->gtsum, g->gtoff, g->gttot);
     hipLaunchKernelGGL(k_tile_thresholds, dim3(tb), dim3(kThreads), 0, t, g->gtiles, g->n_tiles, g->off, g->col,
                        g->w, g->ghead, g->n, g->gtoff, g->gttot, g->gT, g->gerec);
-    // no more blocks than fit at once: waves left for a second round would
-    // run it nearly alone, waiting on their searches' loads
-    int dev = 0, cus = 0, per_cu = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_guide_runs, kThreads, 0)) != hipSuccess) return e;
-    const uint32_t resident = static_cast<uint32_t>(std::max(1, per_cu) * std::max(1, cus));
-    hipLaunchKernelGGL(k_guide_runs, dim3(std::min<uint32_t>(grid_for(g->n_runs * kRun), std::min(resident, 2048u))),
-                       dim3(kThreads), 0, t, g->gruns, g->n_runs, g->off, g->ghead, g->gT, g->gerec, g->gent, p);
+    uint32_t run_blocks = 0;
+    if ((e = resident_grid(k_guide_runs, g->n_runs * kRun, 2048u, &run_blocks)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_guide_runs, dim3(run_blocks), dim3(kThreads), 0, t, g->gruns, g->n_runs, g->off, g->ghead,
+                       g->gT, g->gerec, g->gent, p);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (fork) {
@@ -956,9 +989,14 @@ hipError_t launch_guide_build(fppr_graph* g, bool bases, uint32_t levels, hipStr
 hipError_t launch_guide_level(fppr_graph* g, uint32_t level, uint32_t levels, hipStream_t s) {
   const guide::Pending* in = g->gtab[level & 1u ? 1 : 0];
   const Alloc a = allocator(g, level + 1, levels);
-  hipLaunchKernelGGL((k_guide_level<8, false>), dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
-                     a);
-  hipLaunchKernelGGL((k_guide_level<16, true>), dim3(2048), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
+  // the table counts are on the device: as many blocks as fit
+  constexpr uint64_t kAll = 2048ull * kThreads;
+  uint32_t b8 = 0, b16 = 0;
+  hipError_t e = resident_grid(k_guide_level<8, false>, kAll, 2048u, &b8);
+  if (e == hipSuccess) e = resident_grid(k_guide_level<16, true>, kAll, 2048u, &b16);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_guide_level<8, false>), dim3(b8), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level, a);
+  hipLaunchKernelGGL((k_guide_level<16, true>), dim3(b16), dim3(kThreads), 0, s, g->gT, g->gerec, g->gent, in, level,
                      a);
   return hipGetLastError();
 }
