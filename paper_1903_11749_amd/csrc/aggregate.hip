@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
   __shared__ uint32_t pos[kTile];
   __shared__ uint64_t rk[kTile];
   __shared__ uint32_t seg_base[kMaxSegs + 1];
+  __shared__ uint32_t seg_end[kMaxSegs];  // endpoints of the segment that are not FPPR_NO_NODE
   __shared__ unsigned long long dig[kMaxSegs];
   __shared__ uint64_t scan_lds[kThreads / 64];
 
@@ -79,6 +80,9 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
       const uint32_t idx = e0 + q;
       const uint32_t v = key[idx];
       const bool h = v != kPad && ((idx % Rp) == 0 || key[idx - 1] != v);
+      // the last endpoint before the padding (FPPR_NO_NODE sorts last) ends
+      // the last run
+      if (v != kPad && ((idx % Rp) == Rp - 1 || key[idx + 1] == kPad)) seg_end[idx / Rp] = idx % Rp + 1;
       hmask |= (h ? 1u : 0u) << q;
       heads += h ? 1u : 0u;
     }
@@ -106,7 +110,7 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
         if (r < nd) {
           const uint32_t p = pos[idx];
           const uint32_t t = key[seg * Rp + p];
-          const uint32_t c = ((r + 1 < nd) ? pos[idx + 1] : R) - p;
+          const uint32_t c = ((r + 1 < nd) ? pos[idx + 1] : seg_end[seg]) - p;
           rkey = (static_cast<uint64_t>(~c) << 32) | t;
           if (a.counts) {
             a.counts[(row * R + r) * 2] = t;
@@ -246,6 +250,11 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       v[e] = idx < R ? a.endpoints[row * R + idx] : kPad;
     }
     const uint32_t src = a.sources ? a.sources[row] : static_cast<uint32_t>(a.row0 + row);
+    // endpoints that are not FPPR_NO_NODE: they sort first, and the last
+    // run ends where they end
+    uint32_t nvalid = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) nvalid += static_cast<uint32_t>(__popcll(__ballot(v[e] != kPad)));
     // Every walk of the source ended at the same node (always the case for a
     // source without out-edges, whose walks restart at it until they stop):
     // one distinct endpoint with count R, no sorting.
@@ -308,9 +317,9 @@ __global__ void __launch_bounds__(kThreads) k_aggregate_wave(AggLaunch a) {
       cnt[e] = 0;
       if ((hm[e] >> lane) & 1ull) {
         const uint32_t rank = before[e] + mask_rank(hm[e]);
-        // next head after idx, or R (end of the valid endpoints)
+        // next head after idx, or the end of the valid endpoints
         const uint64_t above = lane == 63 ? 0ull : (hm[e] & (~0ull << (lane + 1)));
-        uint32_t nxt = R;
+        uint32_t nxt = nvalid;
         if (above) {
           nxt = e * 64 + static_cast<uint32_t>(__builtin_ctzll(above));
         } else {

@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import counting_ref
 import synth
 from oracle import alias as A
 
@@ -265,23 +266,7 @@ def test_alias_walks_scale24_ab(fp):
 
 
 def count_reference(ep, sources, k):
-    """Algorithm 2's last phase written out: per source the (t, count) pairs
-    of its walks' endpoints, the top-k by count descending then t ascending
-    (padded with (FPPR_NO_NODE, 0)), and the digest as the oracle defines it."""
-    from oracle import oracle as O
-
-    topk = np.zeros((len(sources), k, 2), dtype=np.uint32)
-    topk[:, :, 0] = 0xFFFFFFFF
-    digest = np.zeros(len(sources), dtype=np.uint64)
-    for r, s in enumerate(sources):
-        t, c = np.unique(ep[r][ep[r] != 0xFFFFFFFF], return_counts=True)
-        order = np.lexsort((t, -c))[:k]
-        topk[r, :order.size, 0] = t[order]
-        topk[r, :order.size, 1] = c[order]
-        d = 0
-        for tt, cc in zip(t, c):
-            d = (d + O.digest_term(int(s), int(tt), int(cc))) % 2**64
-        digest[r] = d
+    topk, digest, _, _ = counting_ref.count_reference(ep, sources, k)
     return topk, digest
 
 
