@@ -145,6 +145,45 @@ def test_crowded_thresholds(fp):
     check_all(fp, g, 0.1, 300, 23, 10, pool_opts=dict(S=32, L=3, K=64, seed=9), narrow_too=False)
 
 
+def long_crowded_graph():
+    """Rows of more than 1024 edges (entries built a run of 16 at a time)
+    whose light edges crowd many thresholds into few entries while holding
+    a real share of the weight, so that walks do draw there: one heavy edge
+    with three times the weight of thousands of unit edges, a 1-1-1-50
+    pattern, Zipf(1.05) weights, unit weights just above 1024 edges; short
+    rows and rows without out-edges between them."""
+    rng = np.random.default_rng(2093)
+    n = 320
+    rows = []
+    for u in range(n):
+        kind = u % 6
+        if kind == 0:
+            d = int(rng.integers(1100, 4000))
+            w = np.ones(d, np.uint64)
+            w[int(rng.integers(0, d))] = 3 * (d - 1)
+        elif kind == 1:
+            d = int(rng.integers(1100, 4000))
+            w = np.where(np.arange(d) % 4 == 3, 50, 1).astype(np.uint64)
+        elif kind == 2:
+            w = np.minimum(rng.zipf(1.05, int(rng.integers(2000, 6000))), 0xFFFFFFFF).astype(np.uint64)
+        elif kind == 3:
+            w = np.ones(int(rng.integers(1025, 1100)), np.uint64)
+        elif kind == 4:
+            w = rng.integers(1, 1000, int(rng.integers(1, 60))).astype(np.uint64)
+        else:
+            w = np.zeros(0, np.uint64)
+        rows.append(w)
+    src = np.concatenate([np.full(r.size, u, np.uint32) for u, r in enumerate(rows)])
+    dst = rng.integers(0, n, src.size).astype(np.uint32)
+    return synth.csr_from_edges(n, src, dst, np.concatenate(rows).astype(np.uint32))
+
+
+def test_crowded_long_rows(fp):
+    g = long_crowded_graph()
+    say(f"case: guide layout, crowded long rows, m {g.m}, max out-degree {g.degrees().max()}")
+    check_all(fp, g, 0.15, 400, 29, 16, pool_opts=dict(S=32, L=3, K=32, seed=11), narrow_too=False)
+
+
 def test_borrowed_csr_rebuild(fp):
     """New weights written into a borrowed CSR, then a rebuild: the oracle's
     result for the new weights (or, when they need more child tables than
