@@ -102,6 +102,26 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t x) {
   return x;
 }
 
+// Largest value over the wave (every lane active), wave-uniform: rows of 16
+// lanes by DPP (quad swaps, then half-row and row mirrors), then the four
+// row results through scalar registers.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  uint32_t y = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
+  x = y > x ? y : x;
+  y = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x4E, 0xF, 0xF, false));
+  x = y > x ? y : x;
+  y = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x141, 0xF, 0xF, false));
+  x = y > x ? y : x;
+  y = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x140, 0xF, 0xF, false));
+  x = y > x ? y : x;
+  const uint32_t r0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 0));
+  const uint32_t r1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 16));
+  const uint32_t r2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 32));
+  const uint32_t r3 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 48));
+  const uint32_t m01 = r0 > r1 ? r0 : r1, m23 = r2 > r3 ? r2 : r3;
+  return m01 > m23 ? m01 : m23;
+}
+
 struct Alloc {
   GuideCtl* ctl;
   Pending* out;
@@ -695,12 +715,7 @@ __global__ void __launch_bounds__(kThreads) k_guide_level(const uint64_t* __rest
     const Pending p = was_ok ? pl : Pending{};  // tables that found no room have no buckets
     const uint64_t Tv = tv_ok ? Tl : ~0ull;
     const uint4 Rv = rv_ok ? Rl : make_uint4(0, 0, 0, 0);
-    uint32_t most = (p.nbk + GL - 1) / GL;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint32_t x = static_cast<uint32_t>(__shfl_xor(static_cast<int>(most), o, 64));
-      most = x > most ? x : most;
-    }
+    const uint32_t most = wave_max_u32((p.nbk + GL - 1) / GL);
     const Thr th{T + p.off};
     const ERec rec{erec + p.off};
     // at least one pass (with no active lane when the wave has no buckets),
