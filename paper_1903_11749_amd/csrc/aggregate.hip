@@ -151,7 +151,9 @@ __global__ void __launch_bounds__(kThreads) k_aggregate(AggLaunch a, uint32_t Rp
 
 // ---------------------------------------------------------------------------
 // R <= 256: one wave per source, E = ceil(R/64) endpoints per lane (element
-// index idx = e * 64 + lane), sorted across the wave with shuffles.
+// index idx = e * 64 + lane), sorted across the wave by lane exchanges; the
+// runs of equal endpoints found by ballots give counts and digests, and the
+// top-k positions are handed out by ballots too (no second sort).
 // ---------------------------------------------------------------------------
 // The value of lane (this lane ^ j), j a power of two below 64 (a constant
 // once the sort's loops are unrolled): DPP within rows of 16 lanes for
